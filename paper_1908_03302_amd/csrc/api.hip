@@ -1,0 +1,568 @@
+// C ABI entry points: context, validation, geometry pre-pass, table upload,
+// and dispatch of the operator kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+using namespace fftt;
+
+#define FFTT_HIP(ctx, expr)                                                          \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);         \
+            return e_ == hipErrorOutOfMemory ? FFTT_E_NOMEM : FFTT_E_DEVICE;        \
+        }                                                                           \
+    } while (0)
+
+#define FFTT_BAD(ctx, msg)          \
+    do {                            \
+        (ctx)->err = (msg);         \
+        return FFTT_E_INVALID;      \
+    } while (0)
+
+namespace {
+
+bool finite3(const double* v) {
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+uint16_t bf16_rne(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+fftt_status set_device(fftt_ctx* c) {
+    FFTT_HIP(c, hipSetDevice(c->device));
+    return FFTT_OK;
+}
+
+double r_max_all(const fftt_ctx* c) {
+    double r = 0.0;
+    for (double v : c->r_max) r = std::max(r, v);
+    return r;
+}
+
+fftt_status upload_tables(fftt_ctx* c) {
+    if (!c->tab_dirty) return FFTT_OK;
+    const int nb = c->nb, n = c->ntab;
+    std::vector<float> t32((size_t)nb * n * 2);
+    std::vector<double> t64((size_t)nb * n * 2);
+    std::vector<uint32_t> tbf((size_t)nb * n);
+    for (int b = 0; b < nb; ++b) {
+        const std::vector<double>& h = c->h[b];
+        for (int k = 0; k < n; ++k) {
+            const size_t i = (size_t)b * n + k;
+            if (k < n - 1) {
+                t64[2 * i] = h[k];
+                t64[2 * i + 1] = h[k + 1] - h[k];
+                t32[2 * i] = (float)h[k];
+                t32[2 * i + 1] = (float)(h[k + 1] - h[k]);
+                const uint16_t lo = bf16_rne((float)h[k]);
+                uint32_t lo32 = (uint32_t)lo << 16;
+                float lo_f;
+                std::memcpy(&lo_f, &lo32, 4);
+                const uint16_t hi = bf16_rne((float)(h[k + 1] - (double)lo_f));
+                tbf[i] = (uint32_t)lo | ((uint32_t)hi << 16);
+            } else {
+                t64[2 * i] = t64[2 * i + 1] = 0.0;
+                t32[2 * i] = t32[2 * i + 1] = 0.f;
+                tbf[i] = 0u;
+            }
+        }
+    }
+    FFTT_HIP(c, c->d_tab32.alloc(t32.size() * sizeof(float)));
+    FFTT_HIP(c, c->d_tab64.alloc(t64.size() * sizeof(double)));
+    FFTT_HIP(c, c->d_tabbf.alloc(tbf.size() * sizeof(uint32_t)));
+    FFTT_HIP(c, hipMemcpy(c->d_tab32.p, t32.data(), t32.size() * sizeof(float),
+                          hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_tab64.p, t64.data(), t64.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_tabbf.p, tbf.data(), tbf.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice));
+    c->tab_dirty = false;
+    return FFTT_OK;
+}
+
+ApplyArgs base_args(const fftt_ctx* c) {
+    ApplyArgs a{};
+    a.tiles = c->d_tiles.as<int32_t>();
+    a.n_act = (int64_t)c->act_tiles.size();
+    a.tptr = c->d_tptr.as<int64_t>();
+    a.ents = c->d_ents.as<Entry>();
+    a.txc = c->d_txc.as<TxConst>();
+    a.n_tx = c->n_tx;
+    a.nnz = c->nnz;
+    a.M = c->M;
+    a.g = c->g;
+    a.mask = c->d_mask.as<uint8_t>();
+    a.nb = c->nb;
+    a.ntab = c->ntab;
+    a.waves_per_block = c->waves_per_block;
+    a.n_cu = c->n_cu;
+    a.unroll = c->unroll_jt;
+    for (int b = 0; b < c->nb; ++b) {
+        a.inv_dr64[b] = (double)(c->ntab - 1) / c->r_max[b];
+        a.inv_dr[b] = (float)a.inv_dr64[b];
+    }
+    return a;
+}
+
+fftt_status build_lists(fftt_ctx* c) {
+    const int64_t n_act = (int64_t)c->act_tiles.size();
+    const int64_t n_tx = c->n_tx, M = c->M;
+    const double r_cut = r_max_all(c) + 1e-7;
+    hipStream_t s = c->stream;
+    c->lists_ok = false;
+
+    FFTT_HIP(c, c->d_txc.alloc((size_t)n_act * n_tx * sizeof(TxConst)));
+    FFTT_HIP(c, launch_txc(s, c->d_tiles.as<int32_t>(), n_act, c->d_tx.as<double>(), n_tx, c->g,
+                           c->d_txc.as<TxConst>()));
+
+    DevBuf counts;
+    FFTT_HIP(c, counts.alloc((size_t)std::max<int64_t>(n_act, 1) * sizeof(int64_t)));
+    FFTT_HIP(c, launch_cull(s, false, c->d_tiles.as<int32_t>(), n_act, c->d_txc.as<TxConst>(),
+                            n_tx, c->d_ps.as<int32_t>(), c->d_pr.as<int32_t>(),
+                            c->d_L.as<double>(), M, c->g, r_cut, counts.as<int64_t>(), nullptr,
+                            nullptr));
+    std::vector<int64_t> cnt(n_act), tptr(n_act + 1, 0);
+    if (n_act)
+        FFTT_HIP(c, hipMemcpyAsync(cnt.data(), counts.p, n_act * sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, s));
+    FFTT_HIP(c, hipStreamSynchronize(s));
+    for (int64_t a = 0; a < n_act; ++a) tptr[a + 1] = tptr[a] + cnt[a];
+    const int64_t nnz = tptr[n_act];
+    FFTT_HIP(c, c->d_tptr.alloc((n_act + 1) * sizeof(int64_t)));
+    FFTT_HIP(c, hipMemcpyAsync(c->d_tptr.p, tptr.data(), (n_act + 1) * sizeof(int64_t),
+                               hipMemcpyHostToDevice, s));
+    FFTT_HIP(c, c->d_ents.alloc((size_t)std::max<int64_t>(nnz, 1) * sizeof(Entry)));
+    FFTT_HIP(c, launch_cull(s, true, c->d_tiles.as<int32_t>(), n_act, c->d_txc.as<TxConst>(),
+                            n_tx, c->d_ps.as<int32_t>(), c->d_pr.as<int32_t>(),
+                            c->d_L.as<double>(), M, c->g, r_cut, nullptr,
+                            c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>()));
+
+    // pair-major index of the entries (for the deterministic J reduction)
+    const int64_t chunk = 256;
+    const int64_t n_chunks = (n_act + chunk - 1) / chunk;
+    DevBuf ccnt, total;
+    FFTT_HIP(c, ccnt.alloc((size_t)std::max<int64_t>(n_chunks * M, 1) * sizeof(int32_t)));
+    FFTT_HIP(c, total.alloc((size_t)M * sizeof(int64_t)));
+    FFTT_HIP(c, hipMemsetAsync(ccnt.p, 0, (size_t)n_chunks * M * sizeof(int32_t), s));
+    FFTT_HIP(c, launch_chunk_count(s, c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(), n_act,
+                                   chunk, M, ccnt.as<int32_t>()));
+    FFTT_HIP(c, launch_chunk_scan(s, ccnt.as<int32_t>(), n_chunks, M, total.as<int64_t>()));
+    std::vector<int64_t> tot(M), pptr(M + 1, 0);
+    FFTT_HIP(c, hipMemcpyAsync(tot.data(), total.p, M * sizeof(int64_t), hipMemcpyDeviceToHost,
+                               s));
+    FFTT_HIP(c, hipStreamSynchronize(s));
+    for (int64_t p = 0; p < M; ++p) pptr[p + 1] = pptr[p] + tot[p];
+    if (pptr[M] != nnz) {
+        c->err = "internal: transposed index size mismatch";
+        return FFTT_E_DEVICE;
+    }
+    FFTT_HIP(c, c->d_pptr.alloc((M + 1) * sizeof(int64_t)));
+    FFTT_HIP(c, hipMemcpyAsync(c->d_pptr.p, pptr.data(), (M + 1) * sizeof(int64_t),
+                               hipMemcpyHostToDevice, s));
+    FFTT_HIP(c, c->d_pidx.alloc((size_t)std::max<int64_t>(nnz, 1) * sizeof(int64_t)));
+    FFTT_HIP(c, launch_chunk_fill(s, c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(), n_act,
+                                  chunk, M, ccnt.as<int32_t>(), c->d_pptr.as<int64_t>(),
+                                  c->d_pidx.as<int64_t>()));
+    c->nnz = nnz;
+
+    // exact work count (FP64 decision R < R_max)
+    DevBuf pvb;
+    FFTT_HIP(c, pvb.alloc(sizeof(unsigned long long)));
+    FFTT_HIP(c, hipMemsetAsync(pvb.p, 0, sizeof(unsigned long long), s));
+    ApplyArgs a = base_args(c);
+    FFTT_HIP(c, launch_count_pv(s, a, r_max_all(c), c->d_L.as<double>(), c->d_ps.as<int32_t>(),
+                                c->d_pr.as<int32_t>(), c->d_tx.as<double>(),
+                                pvb.as<unsigned long long>(), nullptr));
+    unsigned long long pv = 0;
+    FFTT_HIP(c, hipMemcpyAsync(&pv, pvb.p, sizeof(pv), hipMemcpyDeviceToHost, s));
+    FFTT_HIP(c, hipStreamSynchronize(s));
+    c->pv = (int64_t)pv;
+    c->lanes = nnz * kTileVox;
+    c->lists_rcut = r_cut;
+    c->lists_ok = true;
+    return FFTT_OK;
+}
+
+// Event pair for one timed launch of kernel family k (or nulls when off).
+hipError_t prof_begin(fftt_ctx* c, int k, hipEvent_t* stop) {
+    *stop = nullptr;
+    if (!c->prof) return hipSuccess;
+    auto& v = c->prof_ev[k];
+    if (c->prof_used[k] == v.size()) {
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+        v.emplace_back(a, b);
+    }
+    auto& ev = v[c->prof_used[k]++];
+    *stop = ev.second;
+    return hipEventRecord(ev.first, c->stream);
+}
+
+hipError_t prof_end(fftt_ctx* c, hipEvent_t stop) {
+    return stop ? hipEventRecord(stop, c->stream) : hipSuccess;
+}
+
+fftt_status ensure_ready(fftt_ctx* c) {
+    if (!c->has_geom) {
+        c->err = "geometry not set";
+        return FFTT_E_STATE;
+    }
+    if (c->nb == 0) {
+        c->err = "no kernel table set";
+        return FFTT_E_STATE;
+    }
+    for (int b = 0; b < c->nb; ++b)
+        if (!c->band_set[b]) {
+            c->err = "kernel table of band " + std::to_string(b) + " missing";
+            return FFTT_E_STATE;
+        }
+    fftt_status st = set_device(c);
+    if (st != FFTT_OK) return st;
+    st = upload_tables(c);
+    if (st != FFTT_OK) return st;
+    if (!c->lists_ok) return build_lists(c);
+    return FFTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fftt_status fftt_create(fftt_ctx** out, int device, void* hip_stream) {
+    if (!out) return FFTT_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return FFTT_E_DEVICE;
+    fftt_ctx* c = new (std::nothrow) fftt_ctx();
+    if (!c) return FFTT_E_NOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return FFTT_E_DEVICE;
+    }
+    c->n_cu = prop.multiProcessorCount;
+    *out = c;
+    return FFTT_OK;
+}
+
+void fftt_destroy(fftt_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+const char* fftt_last_error(const fftt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+fftt_status fftt_set_stream(fftt_ctx* c, void* hip_stream) {
+    if (!c) return FFTT_E_INVALID;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return FFTT_OK;
+}
+
+fftt_status fftt_set_geometry(fftt_ctx* c, double c0, const double* tx_xyz, int64_t n_tx,
+                              const int32_t* pairs, int64_t n_pairs, const double origin[3],
+                              const double spacing[3], const int64_t dims[3],
+                              const uint8_t* active_mask) {
+    if (!c) return FFTT_E_INVALID;
+    if (!(c0 > 0) || !std::isfinite(c0)) FFTT_BAD(c, "c0 must be positive and finite");
+    if (!tx_xyz || n_tx < 2 || n_tx > 65535) FFTT_BAD(c, "need 2 <= n_tx <= 65535 transducers");
+    if (!pairs || n_pairs < 1 || n_pairs > INT32_MAX) FFTT_BAD(c, "need 1 <= n_pairs < 2^31");
+    if (!origin || !spacing || !dims || !finite3(origin) || !finite3(spacing))
+        FFTT_BAD(c, "grid origin/spacing must be finite");
+    for (int k = 0; k < 3; ++k) {
+        if (!(spacing[k] > 0)) FFTT_BAD(c, "grid spacing must be positive");
+        if (dims[k] < 1 || dims[k] > (1 << 20)) FFTT_BAD(c, "grid dims out of range");
+    }
+    const int64_t N = dims[0] * dims[1] * dims[2];
+    if (N > INT32_MAX) FFTT_BAD(c, "grid has more than 2^31 voxels");
+    for (int64_t q = 0; q < n_tx; ++q)
+        if (!finite3(tx_xyz + 3 * q)) FFTT_BAD(c, "non-finite transducer coordinate");
+    for (int64_t i = 0; i < n_pairs; ++i) {
+        const int32_t s = pairs[2 * i], r = pairs[2 * i + 1];
+        if (s < 0 || r < 0 || s >= n_tx || r >= n_tx) FFTT_BAD(c, "pair index out of range");
+        if (s == r) FFTT_BAD(c, "pair with source == receiver");
+    }
+    // no transducer may sit on an active voxel centre (the kernel is singular there)
+    for (int64_t q = 0; q < n_tx; ++q) {
+        int64_t idx[3];
+        double d2 = 0.0;
+        bool in = true;
+        for (int k = 0; k < 3; ++k) {
+            const double u = (tx_xyz[3 * q + k] - origin[k]) / spacing[k];
+            idx[k] = (int64_t)std::llround(u);
+            if (idx[k] < 0 || idx[k] >= dims[k]) in = false;
+            const double d = (u - (double)idx[k]) * spacing[k];
+            d2 += d * d;
+        }
+        if (in) {
+            const int64_t v = idx[0] + dims[0] * (idx[1] + dims[1] * idx[2]);
+            const bool act = active_mask ? active_mask[v] != 0 : true;
+            const double hmin = std::min(spacing[0], std::min(spacing[1], spacing[2]));
+            if (act && std::sqrt(d2) < 1e-3 * hmin)
+                FFTT_BAD(c, "transducer " + std::to_string(q) + " lies on an active voxel centre");
+        }
+    }
+    fftt_status st = set_device(c);
+    if (st != FFTT_OK) return st;
+
+    c->has_geom = false;
+    c->lists_ok = false;
+    c->c0 = c0;
+    c->n_tx = n_tx;
+    c->M = n_pairs;
+    c->N = N;
+    c->tx.assign(tx_xyz, tx_xyz + 3 * n_tx);
+    std::vector<int32_t> order(n_pairs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        if (pairs[2 * x] != pairs[2 * y]) return pairs[2 * x] < pairs[2 * y];
+        return pairs[2 * x + 1] < pairs[2 * y + 1];
+    });
+    c->ps.resize(n_pairs);
+    c->pr.resize(n_pairs);
+    c->porig = order;
+    c->L.resize(n_pairs);
+    c->C.resize(n_pairs);
+    c->dV = spacing[0] * spacing[1] * spacing[2];
+    for (int64_t i = 0; i < n_pairs; ++i) {
+        const int32_t o = order[i];
+        c->ps[i] = pairs[2 * o];
+        c->pr[i] = pairs[2 * o + 1];
+        const double* a = tx_xyz + 3 * c->ps[i];
+        const double* b = tx_xyz + 3 * c->pr[i];
+        const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+        c->L[i] = std::sqrt(dx * dx + dy * dy + dz * dz);
+        c->C[i] = -c->L[i] * c->dV / (2.0 * M_PI * c0 * c0 * c0);
+    }
+    for (int k = 0; k < 3; ++k) {
+        c->g.dims[k] = dims[k];
+        c->g.origin[k] = origin[k];
+        c->g.spacing[k] = spacing[k];
+        c->g.ntile[k] = (dims[k] + kTile - 1) / kTile;
+    }
+    c->mask.assign((size_t)N, 1);
+    if (active_mask) std::memcpy(c->mask.data(), active_mask, (size_t)N);
+    std::vector<uint8_t> tact((size_t)(c->g.ntile[0] * c->g.ntile[1] * c->g.ntile[2]), 0);
+    for (int64_t k = 0; k < dims[2]; ++k)
+        for (int64_t j = 0; j < dims[1]; ++j)
+            for (int64_t i = 0; i < dims[0]; ++i)
+                if (c->mask[i + dims[0] * (j + dims[1] * k)])
+                    tact[(i / kTile) + c->g.ntile[0] * ((j / kTile) + c->g.ntile[1] * (k / kTile))] = 1;
+    c->act_tiles.clear();
+    for (size_t t = 0; t < tact.size(); ++t)
+        if (tact[t]) c->act_tiles.push_back((int32_t)t);
+
+    FFTT_HIP(c, c->d_tx.alloc(c->tx.size() * sizeof(double)));
+    FFTT_HIP(c, c->d_ps.alloc(n_pairs * sizeof(int32_t)));
+    FFTT_HIP(c, c->d_pr.alloc(n_pairs * sizeof(int32_t)));
+    FFTT_HIP(c, c->d_porig.alloc(n_pairs * sizeof(int32_t)));
+    FFTT_HIP(c, c->d_L.alloc(n_pairs * sizeof(double)));
+    FFTT_HIP(c, c->d_C.alloc(n_pairs * sizeof(double)));
+    FFTT_HIP(c, c->d_mask.alloc((size_t)N));
+    FFTT_HIP(c, c->d_tiles.alloc(std::max<size_t>(c->act_tiles.size(), 1) * sizeof(int32_t)));
+    FFTT_HIP(c, hipMemcpy(c->d_tx.p, c->tx.data(), c->tx.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_ps.p, c->ps.data(), n_pairs * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_pr.p, c->pr.data(), n_pairs * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_porig.p, c->porig.data(), n_pairs * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_L.p, c->L.data(), n_pairs * sizeof(double),
+                          hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_C.p, c->C.data(), n_pairs * sizeof(double),
+                          hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_mask.p, c->mask.data(), (size_t)N, hipMemcpyHostToDevice));
+    if (!c->act_tiles.empty())
+        FFTT_HIP(c, hipMemcpy(c->d_tiles.p, c->act_tiles.data(),
+                              c->act_tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    c->has_geom = true;
+    return FFTT_OK;
+}
+
+fftt_status fftt_set_kernel_table(fftt_ctx* c, int32_t band, const double* h, int64_t n,
+                                  double r_max) {
+    if (!c) return FFTT_E_INVALID;
+    if (band < 0 || band >= kMaxBands) FFTT_BAD(c, "band out of range (0..3)");
+    if (!h || n < 2 || n > kMaxTable) FFTT_BAD(c, "table length must be in 2..16384");
+    if (!(r_max > 0) || !std::isfinite(r_max)) FFTT_BAD(c, "r_max must be positive and finite");
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(h[k])) FFTT_BAD(c, "non-finite table value");
+    bool other = false;
+    for (int b = 0; b < c->nb; ++b)
+        if (b != band && c->band_set[b]) other = true;
+    if (other && n != c->ntab) FFTT_BAD(c, "all bands must use the same table length");
+    const double old_max = r_max_all(c);
+    if (band >= c->nb) {
+        c->nb = band + 1;
+        c->h.resize(c->nb);
+        c->r_max.resize(c->nb, 0.0);
+        c->band_set.resize(c->nb, false);
+    }
+    c->ntab = (int)n;
+    c->h[band].assign(h, h + n);
+    c->r_max[band] = r_max;
+    c->band_set[band] = true;
+    c->tab_dirty = true;
+    if (r_max_all(c) != old_max) c->lists_ok = false;
+    return FFTT_OK;
+}
+
+fftt_status fftt_build_table_from_pulse(double c0, const double* f, int64_t nt, double dt,
+                                        int64_t n, double r_max, double* h_out,
+                                        double* r_max_out) {
+    std::string err;
+    const int rc = build_table_from_pulse(c0, f, nt, dt, n, r_max, h_out, r_max_out, &err);
+    return rc == 0 ? FFTT_OK : FFTT_E_INVALID;
+}
+
+fftt_status fftt_prepare(fftt_ctx* c) {
+    if (!c) return FFTT_E_INVALID;
+    return ensure_ready(c);
+}
+
+fftt_status fftt_work_count(fftt_ctx* c, int64_t* pv, int64_t* lanes) {
+    if (!c) return FFTT_E_INVALID;
+    fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    if (pv) *pv = c->pv;
+    if (lanes) *lanes = c->lanes;
+    return FFTT_OK;
+}
+
+fftt_status fftt_apply_J(fftt_ctx* c, fftt_precision prec, const void* dc, void* dT,
+                         int32_t n_rhs) {
+    if (!c) return FFTT_E_INVALID;
+    if (prec < FFTT_FP64 || prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "unknown precision");
+    if (!dc || !dT || n_rhs < 1) FFTT_BAD(c, "apply_J: null buffer or n_rhs < 1");
+    fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    const bool fp64 = prec == FFTT_FP64;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    FFTT_HIP(c, c->d_part.alloc((size_t)c->nb * std::max<int64_t>(c->nnz, 1) * es));
+    ApplyArgs a = base_args(c);
+    a.tab = fp64 ? c->d_tab64.p : (prec == FFTT_FP32 ? c->d_tab32.p : c->d_tabbf.p);
+    a.out = c->d_part.p;
+    a.unroll = c->unroll_j;
+    a.split = c->split_j;
+    for (int32_t r = 0; r < n_rhs; ++r) {
+        a.x = static_cast<const char*>(dc) + (size_t)r * c->N * es;
+        void* y = static_cast<char*>(dT) + (size_t)r * c->nb * c->M * es;
+        hipEvent_t stop;
+        FFTT_HIP(c, prof_begin(c, 0, &stop));
+        FFTT_HIP(c, launch_apply(c->stream, prec, false, a));
+        FFTT_HIP(c, prof_end(c, stop));
+        FFTT_HIP(c, prof_begin(c, 2, &stop));
+        FFTT_HIP(c, launch_reduce(c->stream, fp64, c->d_part.p, c->nnz, c->d_pptr.as<int64_t>(),
+                                  c->d_pidx.as<int64_t>(), c->d_C.as<double>(),
+                                  c->d_porig.as<int32_t>(), c->M, c->nb, y));
+        FFTT_HIP(c, prof_end(c, stop));
+    }
+    return FFTT_OK;
+}
+
+fftt_status fftt_apply_JT(fftt_ctx* c, fftt_precision prec, const void* dT, void* dc,
+                          int32_t n_rhs) {
+    if (!c) return FFTT_E_INVALID;
+    if (prec < FFTT_FP64 || prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "unknown precision");
+    if (!dc || !dT || n_rhs < 1) FFTT_BAD(c, "apply_JT: null buffer or n_rhs < 1");
+    fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    const bool fp64 = prec == FFTT_FP64;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    FFTT_HIP(c, c->d_w.alloc((size_t)c->nb * c->M * es));
+    ApplyArgs a = base_args(c);
+    a.tab = fp64 ? c->d_tab64.p : (prec == FFTT_FP32 ? c->d_tab32.p : c->d_tabbf.p);
+    a.w = c->d_w.p;
+    for (int32_t r = 0; r < n_rhs; ++r) {
+        const void* y = static_cast<const char*>(dT) + (size_t)r * c->nb * c->M * es;
+        void* x = static_cast<char*>(dc) + (size_t)r * c->N * es;
+        FFTT_HIP(c, launch_weights(c->stream, fp64, y, c->d_porig.as<int32_t>(),
+                                   c->d_C.as<double>(), c->M, c->nb, c->d_w.p));
+        FFTT_HIP(c, launch_fill(c->stream, fp64, x, c->N));
+        a.out = x;
+        hipEvent_t stop;
+        FFTT_HIP(c, prof_begin(c, 1, &stop));
+        FFTT_HIP(c, launch_apply(c->stream, prec, true, a));
+        FFTT_HIP(c, prof_end(c, stop));
+    }
+    return FFTT_OK;
+}
+
+fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
+    if (!c) return FFTT_E_INVALID;
+    switch (key) {
+        case FFTT_TUNE_WAVES_PER_BLOCK:
+            if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+                FFTT_BAD(c, "waves per block must be 1, 2, 4, 8 or 16");
+            c->waves_per_block = value;
+            return FFTT_OK;
+        case FFTT_TUNE_UNROLL_JT:
+        case FFTT_TUNE_UNROLL_J:
+            if (value != 1 && value != 2 && value != 4) FFTT_BAD(c, "unroll must be 1, 2 or 4");
+            (key == FFTT_TUNE_UNROLL_J ? c->unroll_j : c->unroll_jt) = value;
+            return FFTT_OK;
+        case FFTT_TUNE_SPLIT_JT:
+        case FFTT_TUNE_SPLIT_J:
+            if (value != 0 && value != 1) FFTT_BAD(c, "split must be 0 or 1");
+            (key == FFTT_TUNE_SPLIT_J ? c->split_j : c->split_jt) = value;
+            return FFTT_OK;
+    }
+    FFTT_BAD(c, "unknown tuning key");
+}
+
+fftt_status fftt_profile(fftt_ctx* c, int32_t enable) {
+    if (!c) return FFTT_E_INVALID;
+    c->prof = enable != 0;
+    for (auto& u : c->prof_used) u = 0;
+    return FFTT_OK;
+}
+
+fftt_status fftt_kernel_time(fftt_ctx* c, int32_t which, double* ms, int64_t* launches) {
+    if (!c) return FFTT_E_INVALID;
+    if (which < 0 || which > 2 || !ms || !launches) FFTT_BAD(c, "kernel_time: bad argument");
+    FFTT_HIP(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < c->prof_used[which]; ++i) {
+        float t = 0.f;
+        FFTT_HIP(c, hipEventElapsedTime(&t, c->prof_ev[which][i].first,
+                                        c->prof_ev[which][i].second));
+        tot += t;
+    }
+    *ms = tot;
+    *launches = (int64_t)c->prof_used[which];
+    return FFTT_OK;
+}
+
+fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts*, const void*, void*,
+                       fftt_solve_report*) {
+    if (!c) return FFTT_E_INVALID;
+    c->err = "solve: not built yet";
+    return FFTT_E_UNSUPPORTED;
+}
+
+fftt_status fftt_psf(fftt_ctx* c, fftt_precision, const int64_t*, int32_t, double, void*) {
+    if (!c) return FFTT_E_INVALID;
+    c->err = "psf: not built yet";
+    return FFTT_E_UNSUPPORTED;
+}
+
+}  // extern "C"

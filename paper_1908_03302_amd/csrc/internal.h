@@ -1,0 +1,185 @@
+// Internal declarations shared by the host and device parts of libfftt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fftt.h"
+
+namespace fftt {
+
+constexpr int kTile = 4;         // voxels per tile edge: a 4x4x4 tile is one wavefront
+constexpr int kTileVox = 64;
+constexpr int kMaxBands = 4;
+constexpr int kWavesPerBlock = 4;
+constexpr int kMaxTable = 16384;
+
+// Geometry of one transducer seen from one tile centre c (all exact in FP64
+// except the two FP32 roundings, which the kernels compensate):
+//   R_x(u)^2 = D0f^2 + n(u),  n(u) = cq + 2 d.u + |u|^2,  d = c - x_q,
+// so R_x - D0f = n / (R_x + D0f) carries no cancellation.
+struct TxConst {
+    double d2x, d2y, d2z;   // 2 (c - x_q)
+    double cq;              // |c - x_q|^2 - D0f^2
+    float D0f;              // |c - x_q| rounded to FP32
+    float Q0f;              // D0f^2 rounded to FP32
+};
+static_assert(sizeof(TxConst) == 40, "TxConst layout");
+
+// One (tile, pair) incidence that survived culling.
+struct Entry {
+    int32_t p;              // internal pair index
+    uint32_t sr;            // source | receiver << 16
+    float R0hi, R0lo;       // detour D0f_s + D0f_r - L at the tile centre, hi + lo
+};
+static_assert(sizeof(Entry) == 16, "Entry layout");
+
+struct GridGeom {
+    int64_t dims[3];
+    int64_t ntile[3];
+    double origin[3];
+    double spacing[3];
+};
+
+// Arguments of the apply kernels.
+struct ApplyArgs {
+    const int32_t* tiles;     // active tile ids [n_act]
+    int64_t n_act;
+    const int64_t* tptr;      // [n_act + 1]
+    const Entry* ents;        // [nnz]
+    const TxConst* txc;       // [n_act][n_tx]
+    int64_t n_tx;
+    int64_t nnz;
+    int64_t M;
+    GridGeom g;
+    const uint8_t* mask;      // [N]
+    int nb;
+    int ntab;
+    float inv_dr[kMaxBands];  // (n-1)/r_max per band
+    double inv_dr64[kMaxBands];
+    const void* tab;          // device table [nb][ntab] in the kernel's format
+    const void* w;            // JT: [nb][M] weights C_p dT_p (internal pair order)
+    const void* x;            // J: dc [N]
+    void* out;                // JT: dc [N]; J: partials [nb][nnz]
+    int waves_per_block;      // wavefronts per workgroup, sharing one tile (1..16)
+    int n_cu;                 // compute units of the device (persistent grid size)
+    int unroll;               // entries per inner-loop step (1, 2, 4)
+    int split;                // 1: a workgroup shares one tile, its waves split the entries
+};
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t n) {
+        if (n <= bytes && p) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n ? n : 1);
+        if (e == hipSuccess) bytes = n;
+        return e;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---- device-side launchers (kernels.hip) ----
+hipError_t launch_txc(hipStream_t s, const int32_t* tiles, int64_t n_act, const double* tx,
+                      int64_t n_tx, const GridGeom& g, TxConst* out);
+hipError_t launch_cull(hipStream_t s, bool fill, const int32_t* tiles, int64_t n_act,
+                       const TxConst* txc, int64_t n_tx, const int32_t* ps, const int32_t* pr,
+                       const double* L, int64_t M, const GridGeom& g, double r_cut,
+                       int64_t* counts, const int64_t* tptr, Entry* ents);
+hipError_t launch_chunk_count(hipStream_t s, const int64_t* tptr, const Entry* ents,
+                              int64_t n_act, int64_t chunk, int64_t M, int32_t* cnt);
+hipError_t launch_chunk_scan(hipStream_t s, int32_t* cnt, int64_t n_chunks, int64_t M,
+                             int64_t* total);
+hipError_t launch_chunk_fill(hipStream_t s, const int64_t* tptr, const Entry* ents,
+                             int64_t n_act, int64_t chunk, int64_t M, int32_t* cnt,
+                             const int64_t* pptr, int64_t* pidx);
+hipError_t launch_count_pv(hipStream_t s, const ApplyArgs& a, double r_max_all,
+                           const double* L, const int32_t* ps, const int32_t* pr,
+                           const double* tx, unsigned long long* pv,
+                           unsigned long long* lanes);
+hipError_t launch_weights(hipStream_t s, bool fp64, const void* dT, const int32_t* porig,
+                          const double* C, int64_t M, int nb, void* w);
+hipError_t launch_fill(hipStream_t s, bool fp64, void* p, int64_t n);
+hipError_t launch_apply(hipStream_t s, fftt_precision prec, bool transpose,
+                        const ApplyArgs& a);
+hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz,
+                         const int64_t* pptr, const int64_t* pidx, const double* C,
+                         const int32_t* porig, int64_t M, int nb, void* dT);
+
+// ---- host table builder (table.cpp) ----
+int build_table_from_pulse(double c0, const double* f, int64_t nt, double dt, int64_t n,
+                           double r_max, double* h_out, double* r_max_out, std::string* err);
+
+}  // namespace fftt
+
+struct fftt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // geometry (host)
+    bool has_geom = false;
+    double c0 = 0;
+    int64_t n_tx = 0, M = 0, N = 0;
+    std::vector<double> tx;
+    std::vector<int32_t> ps, pr, porig;   // internal pair order: sorted by (source, receiver)
+    std::vector<double> L, C;             // per internal pair: length, -L dV / (2 pi c0^3)
+    fftt::GridGeom g{};
+    double dV = 0;
+    std::vector<uint8_t> mask;
+    std::vector<int32_t> act_tiles;
+
+    // geometry (device)
+    fftt::DevBuf d_tx, d_ps, d_pr, d_porig, d_L, d_C, d_mask, d_tiles;
+
+    // kernel tables
+    int nb = 0;
+    int ntab = 0;
+    std::vector<std::vector<double>> h;
+    std::vector<double> r_max;
+    std::vector<bool> band_set;
+    bool tab_dirty = true;
+    fftt::DevBuf d_tab32, d_tab64, d_tabbf;
+
+    // culling lists
+    bool lists_ok = false;
+    double lists_rcut = 0;
+    int64_t nnz = 0;
+    int64_t pv = 0, lanes = 0;
+    fftt::DevBuf d_txc, d_tptr, d_ents, d_pptr, d_pidx;
+
+    // launch shape of the operator kernels
+    int waves_per_block = 16;
+    int n_cu = 0;
+    int unroll_jt = 2;
+    int unroll_j = 4;
+    int split_jt = 0, split_j = 1;
+
+    // work buffers
+    fftt::DevBuf d_w, d_part;
+
+    // optional event timing of the main kernels (index: 0 J, 1 J^T, 2 reduction)
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[3];
+    size_t prof_used[3] = {0, 0, 0};
+    ~fftt_ctx() {
+        for (auto& v : prof_ev)
+            for (auto& e : v) {
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
+    }
+};

@@ -1,0 +1,878 @@
+// HIP kernels for gfx950: geometry pre-pass and the matrix-free traveltime
+// Jacobian J (eq. forward_compact) and its transpose.
+//
+// Layout of the work: the voxel grid is cut into 4x4x4 tiles, one tile per
+// wavefront (lane = voxel).  For every tile the pre-pass keeps the list of
+// source-receiver pairs whose truncated kernel (detour R < R_max) can reach
+// it.  Both operators walk that list: J^T accumulates sum_i J_ij dT_i in a
+// register per voxel (no atomics), J reduces sum_j J_ij dc_j across the
+// wavefront and writes one partial per (tile, pair), which a second kernel
+// sums per pair in a fixed order.  Every kernel value is evaluated on the fly
+// (Sec. II-C): A(x) from the two distances, h(R) from a table in LDS.
+#include "internal.h"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace fftt {
+
+// ----------------------------------------------------------------- helpers
+
+__device__ __forceinline__ void tile_xyz(int64_t t, const GridGeom& g, int64_t& tx, int64_t& ty,
+                                         int64_t& tz) {
+    tx = t % g.ntile[0];
+    ty = (t / g.ntile[0]) % g.ntile[1];
+    tz = t / (g.ntile[0] * g.ntile[1]);
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Sum over the 64 lanes of a wavefront (row butterflies, then row
+// broadcasts); fixed order, so deterministic.  Result is wave-uniform.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += __int_as_float(dpp_i<0xb1>(__float_as_int(v)));        // quad_perm 1,0,3,2
+    v += __int_as_float(dpp_i<0x4e>(__float_as_int(v)));        // quad_perm 2,3,0,1
+    v += __int_as_float(dpp_i<0x141>(__float_as_int(v)));       // row_half_mirror
+    v += __int_as_float(dpp_i<0x140>(__float_as_int(v)));       // row_mirror
+    v += __int_as_float(dpp_i<0x142, 0xa>(__float_as_int(v)));  // row_bcast:15
+    v += __int_as_float(dpp_i<0x143, 0xc>(__float_as_int(v)));  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL, ROW_MASK>((int)(b & 0xffffffffll));
+    const int hi = dpp_i<CTRL, ROW_MASK>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_d<0xb1>(v);
+    v += dpp_d<0x4e>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    v += dpp_d<0x142, 0xa>(v);
+    v += dpp_d<0x143, 0xc>(v);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Swap the two 32-lane halves / the odd and even 16-lane rows and add: with
+// the same register as both operands, the two results of the gfx950
+// permlane swaps hold the two halves, so their sum is the cross-half sum.
+__device__ __forceinline__ float add_halves(float x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x),
+                                                    false, false);
+    x = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x),
+                                                    false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
+__device__ __forceinline__ double add_halves(double x) {
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)(b & 0xffffffffll), hi = (unsigned)(b >> 32);
+    const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    x = __longlong_as_double(((long long)rh[0] << 32) | rl[0]) +
+        __longlong_as_double(((long long)rh[1] << 32) | rl[1]);
+    const long long c = __double_as_longlong(x);
+    const unsigned lo2 = (unsigned)(c & 0xffffffffll), hi2 = (unsigned)(c >> 32);
+    const auto ql = __builtin_amdgcn_permlane16_swap(lo2, lo2, false, false);
+    const auto qh = __builtin_amdgcn_permlane16_swap(hi2, hi2, false, false);
+    return __longlong_as_double(((long long)qh[0] << 32) | ql[0]) +
+           __longlong_as_double(((long long)qh[1] << 32) | ql[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v) {
+    return dpp_d<CTRL>(v);
+}
+
+// U simultaneous wavefront sums: afterwards lane l holds sum_lanes v[l % U]
+// (U = 1, 2 or 4).  Lanes are first paired so each lane carries one of the
+// U sums, then the 64 / U lanes of each class are combined (row rotations by
+// 4 and 8 keep l % 4, the half/row swaps finish).  Fixed order: deterministic.
+template <int U, class T>
+__device__ __forceinline__ T multi_sum(const T (&v)[U], int lane) {
+    T x;
+    if constexpr (U == 1) {
+        x = v[0];
+        x += dpp_f<0xb1>(x);                  // quad_perm 1,0,3,2  (lane ^ 1)
+        x += dpp_f<0x4e>(x);                  // quad_perm 2,3,0,1  (lane ^ 2)
+    } else if constexpr (U == 2) {
+        const bool odd = lane & 1;
+        x = odd ? v[1] : v[0];
+        const T y = odd ? v[0] : v[1];
+        x += dpp_f<0xb1>(y);
+        x += dpp_f<0x4e>(x);
+    } else {
+        const bool odd = lane & 1, two = lane & 2;
+        T a = odd ? v[1] : v[0];
+        const T b = odd ? v[0] : v[1];
+        a += dpp_f<0xb1>(b);
+        T c = odd ? v[3] : v[2];
+        const T d = odd ? v[2] : v[3];
+        c += dpp_f<0xb1>(d);
+        x = two ? c : a;
+        const T y = two ? a : c;
+        x += dpp_f<0x4e>(y);
+    }
+    x += dpp_f<0x124>(x);                     // row_ror:4
+    x += dpp_f<0x128>(x);                     // row_ror:8
+    return add_halves(x);
+}
+
+// ------------------------------------------------- per (tile, transducer)
+
+__global__ void k_txc(const int32_t* __restrict__ tiles, int64_t n_act,
+                      const double* __restrict__ tx, int64_t n_tx, GridGeom g,
+                      TxConst* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_act * n_tx) return;
+    const int64_t a = i / n_tx, q = i - a * n_tx;
+    int64_t tix, tiy, tiz;
+    tile_xyz(tiles[a], g, tix, tiy, tiz);
+    const double cx = g.origin[0] + ((double)(kTile * tix) + 1.5) * g.spacing[0];
+    const double cy = g.origin[1] + ((double)(kTile * tiy) + 1.5) * g.spacing[1];
+    const double cz = g.origin[2] + ((double)(kTile * tiz) + 1.5) * g.spacing[2];
+    const double dx = cx - tx[3 * q], dy = cy - tx[3 * q + 1], dz = cz - tx[3 * q + 2];
+    const double D2 = dx * dx + dy * dy + dz * dz;
+    const float Df = (float)sqrt(D2);
+    const double Dfd = (double)Df;
+    TxConst c;
+    c.d2x = 2.0 * dx;
+    c.d2y = 2.0 * dy;
+    c.d2z = 2.0 * dz;
+    c.cq = D2 - Dfd * Dfd;
+    c.D0f = Df;
+    c.Q0f = (float)(Dfd * Dfd);
+    out[i] = c;
+}
+
+hipError_t launch_txc(hipStream_t s, const int32_t* tiles, int64_t n_act, const double* tx,
+                      int64_t n_tx, const GridGeom& g, TxConst* out) {
+    const int64_t n = n_act * n_tx;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_txc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tiles, n_act,
+                       tx, n_tx, g, out);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- culling
+//
+// R(x) = |x - x_s| + |x - x_r| - L is convex, so over the box that holds the
+// tile's voxel centres (half-widths hw) it is bounded below by its tangent
+// plane at the centre: R >= R(c) - sum_k |dR/dx_k(c)| hw_k.  A pair is kept
+// when that bound is below the cut radius; the list is in pair order.
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_cull(const int32_t* __restrict__ tiles, int64_t n_act,
+                                              const TxConst* __restrict__ txc, int64_t n_tx,
+                                              const int32_t* __restrict__ ps,
+                                              const int32_t* __restrict__ pr,
+                                              const double* __restrict__ L, int64_t M,
+                                              double hwx, double hwy, double hwz, double r_cut,
+                                              int64_t* __restrict__ counts,
+                                              const int64_t* __restrict__ tptr,
+                                              Entry* __restrict__ ents) {
+    __shared__ int s_wsum[4];
+    const int64_t a = blockIdx.x;
+    const TxConst* row = txc + a * n_tx;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = FILL ? tptr[a] : 0;
+    int64_t count = 0;
+    for (int64_t p0 = 0; p0 < M; p0 += 256) {
+        const int64_t p = p0 + threadIdx.x;
+        bool pass = false;
+        double R0 = 0.0;
+        uint32_t sr = 0;
+        if (p < M) {
+            const int s = ps[p], r = pr[p];
+            const TxConst A = row[s], B = row[r];
+            R0 = (double)A.D0f + (double)B.D0f - L[p];
+            const double ia = 0.5 / (double)A.D0f, ib = 0.5 / (double)B.D0f;
+            const double gx = A.d2x * ia + B.d2x * ib;
+            const double gy = A.d2y * ia + B.d2y * ib;
+            const double gz = A.d2z * ia + B.d2z * ib;
+            const double lb = R0 - (fabs(gx) * hwx + fabs(gy) * hwy + fabs(gz) * hwz);
+            pass = lb < r_cut;
+            sr = (uint32_t)s | ((uint32_t)r << 16);
+        }
+        const unsigned long long bal = __ballot(pass);
+        const int my = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wsum[wave] = __popcll(bal);
+        __syncthreads();
+        int off = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int c = s_wsum[w];
+            off += (w < wave) ? c : 0;
+            tot += c;
+        }
+        if (FILL && pass) {
+            const float hi = (float)R0;
+            const float lo = (float)(R0 - (double)hi);
+            Entry E;
+            E.p = (int32_t)p;
+            E.sr = sr;
+            E.R0hi = hi;
+            E.R0lo = lo;
+            ents[base + count + off + my] = E;
+        }
+        count += tot;
+        __syncthreads();
+    }
+    if (!FILL && threadIdx.x == 0) counts[a] = count;
+}
+
+hipError_t launch_cull(hipStream_t s, bool fill, const int32_t* tiles, int64_t n_act,
+                       const TxConst* txc, int64_t n_tx, const int32_t* ps, const int32_t* pr,
+                       const double* L, int64_t M, const GridGeom& g, double r_cut,
+                       int64_t* counts, const int64_t* tptr, Entry* ents) {
+    if (n_act == 0) return hipSuccess;
+    const double hwx = 0.5 * (kTile - 1) * g.spacing[0];
+    const double hwy = 0.5 * (kTile - 1) * g.spacing[1];
+    const double hwz = 0.5 * (kTile - 1) * g.spacing[2];
+    if (fill)
+        hipLaunchKernelGGL(k_cull<true>, dim3((unsigned)n_act), dim3(256), 0, s, tiles, n_act,
+                           txc, n_tx, ps, pr, L, M, hwx, hwy, hwz, r_cut, counts, tptr, ents);
+    else
+        hipLaunchKernelGGL(k_cull<false>, dim3((unsigned)n_act), dim3(256), 0, s, tiles, n_act,
+                           txc, n_tx, ps, pr, L, M, hwx, hwy, hwz, r_cut, counts, tptr, ents);
+    return hipGetLastError();
+}
+
+// ------------------------------------------- pair-major (transposed) index
+//
+// Positions of each pair's entries, in increasing entry (= tile) order, built
+// deterministically: tiles are grouped in chunks; a chunk counts its entries
+// per pair, the counts are scanned across chunks per pair, and each chunk
+// then hands out slots tile by tile (a pair occurs at most once per tile).
+
+__global__ void k_chunk_count(const int64_t* __restrict__ tptr, const Entry* __restrict__ ents,
+                              int64_t n_act, int64_t chunk, int64_t M, int32_t* __restrict__ cnt) {
+    const int64_t c = blockIdx.x;
+    const int64_t a0 = c * chunk;
+    const int64_t a1 = min(n_act, a0 + chunk);
+    int32_t* row = cnt + c * M;
+    for (int64_t e = tptr[a0] + threadIdx.x; e < tptr[a1]; e += blockDim.x)
+        atomicAdd(&row[ents[e].p], 1);
+}
+
+__global__ void k_chunk_scan(int32_t* __restrict__ cnt, int64_t n_chunks, int64_t M,
+                             int64_t* __restrict__ total) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    int64_t run = 0;
+    for (int64_t c = 0; c < n_chunks; ++c) {
+        const int32_t v = cnt[c * M + p];
+        cnt[c * M + p] = (int32_t)run;
+        run += v;
+    }
+    total[p] = run;
+}
+
+__global__ void k_chunk_fill(const int64_t* __restrict__ tptr, const Entry* __restrict__ ents,
+                             int64_t n_act, int64_t chunk, int64_t M, int32_t* __restrict__ cnt,
+                             const int64_t* __restrict__ pptr, int64_t* __restrict__ pidx) {
+    const int64_t c = blockIdx.x;
+    const int64_t a0 = c * chunk;
+    const int64_t a1 = min(n_act, a0 + chunk);
+    int32_t* row = cnt + c * M;
+    for (int64_t a = a0; a < a1; ++a) {
+        for (int64_t e = tptr[a] + threadIdx.x; e < tptr[a + 1]; e += blockDim.x) {
+            const int p = ents[e].p;
+            const int32_t slot = atomicAdd(&row[p], 1);
+            pidx[pptr[p] + slot] = e;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_chunk_count(hipStream_t s, const int64_t* tptr, const Entry* ents,
+                              int64_t n_act, int64_t chunk, int64_t M, int32_t* cnt) {
+    const int64_t nc = (n_act + chunk - 1) / chunk;
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)nc), dim3(256), 0, s, tptr, ents, n_act,
+                       chunk, M, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_scan(hipStream_t s, int32_t* cnt, int64_t n_chunks, int64_t M,
+                             int64_t* total) {
+    hipLaunchKernelGGL(k_chunk_scan, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, cnt,
+                       n_chunks, M, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_fill(hipStream_t s, const int64_t* tptr, const Entry* ents,
+                             int64_t n_act, int64_t chunk, int64_t M, int32_t* cnt,
+                             const int64_t* pptr, int64_t* pidx) {
+    const int64_t nc = (n_act + chunk - 1) / chunk;
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_fill, dim3((unsigned)nc), dim3(256), 0, s, tptr, ents, n_act,
+                       chunk, M, cnt, pptr, pidx);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- work count
+
+__device__ __forceinline__ void voxel_of_lane(const ApplyArgs& A, int64_t t, int lane,
+                                              bool& inside, bool& act, int64_t& vidx,
+                                              int64_t v[3]) {
+    int64_t tix, tiy, tiz;
+    tile_xyz(t, A.g, tix, tiy, tiz);
+    v[0] = kTile * tix + (lane & 3);
+    v[1] = kTile * tiy + ((lane >> 2) & 3);
+    v[2] = kTile * tiz + (lane >> 4);
+    inside = v[0] < A.g.dims[0] && v[1] < A.g.dims[1] && v[2] < A.g.dims[2];
+    vidx = inside ? v[0] + A.g.dims[0] * (v[1] + A.g.dims[1] * v[2]) : 0;
+    act = inside && A.mask[vidx] != 0;
+}
+
+__global__ __launch_bounds__(256) void k_count_pv(ApplyArgs A, double rmax,
+                                                  const double* __restrict__ L,
+                                                  const int32_t* __restrict__ ps,
+                                                  const int32_t* __restrict__ pr,
+                                                  const double* __restrict__ tx,
+                                                  unsigned long long* pv) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t a = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    if (a >= A.n_act) return;
+    bool inside, act;
+    int64_t vidx, v[3];
+    voxel_of_lane(A, A.tiles[a], lane, inside, act, vidx, v);
+    const double x = A.g.origin[0] + (double)v[0] * A.g.spacing[0];
+    const double y = A.g.origin[1] + (double)v[1] * A.g.spacing[1];
+    const double z = A.g.origin[2] + (double)v[2] * A.g.spacing[2];
+    unsigned long long cnt = 0;
+    for (int64_t e = A.tptr[a]; e < A.tptr[a + 1]; ++e) {
+        const int p = A.ents[e].p;
+        const double* xs = tx + 3 * ps[p];
+        const double* xr = tx + 3 * pr[p];
+        const double Rs = sqrt((x - xs[0]) * (x - xs[0]) + (y - xs[1]) * (y - xs[1]) +
+                               (z - xs[2]) * (z - xs[2]));
+        const double Rr = sqrt((x - xr[0]) * (x - xr[0]) + (y - xr[1]) * (y - xr[1]) +
+                               (z - xr[2]) * (z - xr[2]));
+        const bool in = act && (Rs + Rr - L[p] < rmax);
+        cnt += __popcll(__ballot(in));
+    }
+    if (lane == 0) atomicAdd(pv, cnt);
+}
+
+hipError_t launch_count_pv(hipStream_t s, const ApplyArgs& a, double r_max_all,
+                           const double* L, const int32_t* ps, const int32_t* pr,
+                           const double* tx, unsigned long long* pv,
+                           unsigned long long* /*lanes*/) {
+    if (a.n_act == 0) return hipSuccess;
+    const unsigned nblk = (unsigned)((a.n_act + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(k_count_pv, dim3(nblk), dim3(64 * kWavesPerBlock), 0, s, a, r_max_all, L,
+                       ps, pr, tx, pv);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- small vector kernels
+
+template <class T>
+__global__ void k_weights(const T* __restrict__ dT, const int32_t* __restrict__ porig,
+                          const double* __restrict__ C, int64_t M, int nb, T* __restrict__ w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * nb) return;
+    const int64_t b = i / M, p = i - b * M;
+    w[i] = (T)(C[p] * (double)dT[b * M + porig[p]]);
+}
+
+hipError_t launch_weights(hipStream_t s, bool fp64, const void* dT, const int32_t* porig,
+                          const double* C, int64_t M, int nb, void* w) {
+    const int64_t n = M * nb;
+    const unsigned nblk = (unsigned)((n + 255) / 256);
+    if (fp64)
+        hipLaunchKernelGGL(k_weights<double>, dim3(nblk), dim3(256), 0, s, (const double*)dT,
+                           porig, C, M, nb, (double*)w);
+    else
+        hipLaunchKernelGGL(k_weights<float>, dim3(nblk), dim3(256), 0, s, (const float*)dT,
+                           porig, C, M, nb, (float*)w);
+    return hipGetLastError();
+}
+
+template <class T>
+__global__ void k_fill0(T* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (T)0;
+}
+
+hipError_t launch_fill(hipStream_t s, bool fp64, void* p, int64_t n) {
+    if (n == 0) return hipSuccess;
+    const unsigned nblk = (unsigned)((n + 255) / 256);
+    if (fp64)
+        hipLaunchKernelGGL(k_fill0<double>, dim3(nblk), dim3(256), 0, s, (double*)p, n);
+    else
+        hipLaunchKernelGGL(k_fill0<float>, dim3(nblk), dim3(256), 0, s, (float*)p, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ kernel evaluation
+
+// FP32 path: the distance to a transducer is split as R_x = D0f + delta with
+// delta = n / (R_x + D0f), n formed in FP64 from the tile-relative geometry,
+// so the detour R = R0 + delta_s + delta_r never subtracts large numbers.
+__device__ __forceinline__ void dist32(const TxConst& c, double ux, double uy, double uz,
+                                       double uu, float& delta, float& rs) {
+    const double n = fma(c.d2x, ux, fma(c.d2y, uy, fma(c.d2z, uz, uu + c.cq)));
+    const float nf = (float)n;
+    const float q = c.Q0f + nf;
+    rs = __builtin_amdgcn_rsqf(q);
+    const float Rx = q * rs;
+    delta = nf * __builtin_amdgcn_rcpf(Rx + c.D0f);
+}
+
+// FP64 path: plain distances (FP64 leaves no cancellation that matters).
+__device__ __forceinline__ void dist64(const TxConst& c, double ux, double uy, double uz,
+                                       double uu, double& delta, double& Rx) {
+    const double n = fma(c.d2x, ux, fma(c.d2y, uy, fma(c.d2z, uz, uu + c.cq)));
+    const double D = (double)c.D0f;
+    Rx = sqrt(fma(D, D, n));
+    delta = Rx - D;
+}
+
+// Linear interpolation in a table of nodes k = 0..n-1 over [0, r_max]; entry
+// k stores (h_k, h_{k+1} - h_k) and entry n-1 is (0, 0), so clamping the
+// coordinate to n-1 yields zero for every R >= r_max.
+// The coordinate is clamped to [0, n-1] (v_med3; a NaN maps into range).
+__device__ __forceinline__ float lookup(const float2* tab, float R, float inv_dr, float nm1) {
+    const float x = __builtin_amdgcn_fmed3f(R * inv_dr, 0.0f, nm1);
+    const int k = (int)x;
+    const float f = x - (float)k;
+    const float2 t = tab[k];
+    return fmaf(f, t.y, t.x);
+}
+
+// BF16 table: entry k packs a = bf16(h_k) in the low half and
+// d = bf16(h_{k+1} - a) in the high half, so h = a + f d; the rounding of a
+// is fully felt at the node and fades linearly to the next node.
+__device__ __forceinline__ float lookup(const uint32_t* tab, float R, float inv_dr, float nm1) {
+    const float x = __builtin_amdgcn_fmed3f(R * inv_dr, 0.0f, nm1);
+    const int k = (int)x;
+    const float f = x - (float)k;
+    const uint32_t e = tab[k];
+    return fmaf(f, __uint_as_float(e & 0xffff0000u), __uint_as_float(e << 16));
+}
+
+__device__ __forceinline__ double lookup(const double2* tab, double R, double inv_dr, double nm1) {
+    const double x = fmin(fmax(R * inv_dr, 0.0), nm1);
+    const int k = (int)x;
+    const double f = x - (double)k;
+    const double2 t = tab[k];
+    return fma(f, t.y, t.x);
+}
+
+struct LaneVox {
+    bool inside, act;
+    int64_t vidx;
+    double ux, uy, uz, uu;
+};
+
+__device__ __forceinline__ LaneVox lane_vox(const ApplyArgs& A, int64_t a, int lane) {
+    LaneVox L;
+    int64_t v[3];
+    voxel_of_lane(A, A.tiles[a], lane, L.inside, L.act, L.vidx, v);
+    L.ux = ((double)(lane & 3) - 1.5) * A.g.spacing[0];
+    L.uy = ((double)((lane >> 2) & 3) - 1.5) * A.g.spacing[1];
+    L.uz = ((double)(lane >> 4) - 1.5) * A.g.spacing[2];
+    L.uu = L.ux * L.ux + L.uy * L.uy + L.uz * L.uz;
+    return L;
+}
+
+template <class TabT>
+__device__ __forceinline__ const TabT* stage_table(const ApplyArgs& A, int nb) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    TabT* st = reinterpret_cast<TabT*>(smem);
+    const TabT* gt = static_cast<const TabT*>(A.tab);
+    const int n = nb * A.ntab;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) st[i] = gt[i];
+    __syncthreads();
+    return st;
+}
+
+// Work of one wavefront: a tile and a range of its entries.  Either every
+// wavefront owns a tile (split == 0: blockDim.x/64 tiles per workgroup) or a
+// workgroup owns a tile and its wavefronts split the tile's entries into
+// contiguous ranges of multiples of U (split == 1).  Returns false when the
+// wavefront has no tile.
+__device__ __forceinline__ bool wave_work(const ApplyArgs& A, int U, int64_t& a, int64_t& eb,
+                                          int64_t& ee) {
+    if (A.split) {
+        a = blockIdx.x;
+        if (a >= A.n_act) return false;
+        const int W = (int)(blockDim.x >> 6);
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const int64_t e0 = A.tptr[a], e1 = A.tptr[a + 1];
+        int64_t chunk = (e1 - e0 + W - 1) / W;
+        chunk = (chunk + U - 1) / U * U;
+        eb = min(e1, e0 + (int64_t)wave * chunk);
+        ee = min(e1, eb + chunk);
+        return true;
+    }
+    const int t = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    a = (int64_t)__builtin_amdgcn_readfirstlane(t);
+    if (a >= A.n_act) return false;
+    eb = A.tptr[a];
+    ee = A.tptr[a + 1];
+    return true;
+}
+
+// Write one voxel value per lane; in split mode the workgroup's partial sums
+// are first added in wavefront order through LDS.
+template <class T>
+__device__ __forceinline__ void store_voxel(const ApplyArgs& A, const LaneVox& V, T acc,
+                                            T* s_acc) {
+    if (A.split) {
+        const int W = (int)(blockDim.x >> 6);
+        const int wave = (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+        s_acc[wave * 64 + lane] = acc;
+        __syncthreads();
+        if (wave != 0) return;
+        acc = s_acc[lane];
+        for (int k = 1; k < W; ++k) acc += s_acc[k * 64 + lane];
+    }
+    if (V.inside) static_cast<T*>(A.out)[V.vidx] = V.act ? acc : (T)0;
+}
+
+template <class TabT>
+__device__ __forceinline__ unsigned char* lds_after(const ApplyArgs& A, int nb) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    return smem + (((size_t)nb * A.ntab * sizeof(TabT) + 15) & ~(size_t)15);
+}
+
+// Wave-uniform tile index of this wavefront (blocks hold blockDim.x/64 tiles).
+__device__ __forceinline__ int64_t wave_tile() {
+    const int t = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    return (int64_t)__builtin_amdgcn_readfirstlane(t);
+}
+
+// Source part of U consecutive entries: recomputed only when the source
+// changes (entries are sorted by source, receiver within a tile).
+template <int U, class F, class Dist>
+__device__ __forceinline__ void source_parts(const Entry (&E)[U], const TxConst* row,
+                                             const LaneVox& V, int& prev, F& ds, F& as,
+                                             F (&dsu)[U], F (&asu)[U], Dist dist) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int s = (int)(E[u].sr & 0xffffu);
+        if (s != prev) {
+            prev = s;
+            dist(row[s], V.ux, V.uy, V.uz, V.uu, ds, as);
+        }
+        dsu[u] = ds;
+        asu[u] = as;
+    }
+}
+
+// J^T, FP32 / BF16 table: dc_j = sum_i sum_b J^b_ij dT^b_i.
+template <int NB, class TabT, int U>
+__device__ __forceinline__ void jt32_step(const ApplyArgs& A, const TabT* st,
+                                          const Entry* __restrict__ ents,
+                                          const TxConst* __restrict__ row,
+                                          const float* __restrict__ w, const LaneVox& V,
+                                          float nm1, int64_t e, int& prev, float& ds, float& rss,
+                                          float& acc) {
+    Entry E[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) E[u] = ents[e + u];
+    float wu[U][NB];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) wu[u][b] = w[b * A.M + E[u].p];
+    float dsu[U], rssu[U], dr[U], rsr[U];
+    source_parts<U>(E, row, V, prev, ds, rss, dsu, rssu, dist32);
+#pragma unroll
+    for (int u = 0; u < U; ++u) dist32(row[E[u].sr >> 16], V.ux, V.uy, V.uz, V.uu, dr[u], rsr[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const float R = (dsu[u] + dr[u]) + E[u].R0hi;
+        float hw = 0.f;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            hw = fmaf(lookup(st + b * A.ntab, R, A.inv_dr[b], nm1), wu[u][b], hw);
+        acc = fmaf(hw, rssu[u] * rsr[u], acc);
+    }
+}
+
+template <int NB, class TabT, int U>
+__global__ __launch_bounds__(1024) void k_jt32(ApplyArgs A) {
+    const TabT* st = stage_table<TabT>(A, NB);
+    float* s_acc = reinterpret_cast<float*>(lds_after<TabT>(A, NB));
+    int64_t a, e0, e1;
+    if (!wave_work(A, U, a, e0, e1)) return;
+    const int lane = threadIdx.x & 63;
+    const LaneVox V = lane_vox(A, a, lane);
+    const TxConst* __restrict__ row = A.txc + a * A.n_tx;
+    const float* __restrict__ w = static_cast<const float*>(A.w);
+    const float nm1 = (float)(A.ntab - 1);
+    float acc = 0.f, ds = 0.f, rss = 0.f;
+    int prev = -1;
+    int64_t e = e0;
+    for (; e + U <= e1; e += U) jt32_step<NB, TabT, U>(A, st, A.ents, row, w, V, nm1, e, prev, ds, rss, acc);
+    for (; e < e1; ++e) jt32_step<NB, TabT, 1>(A, st, A.ents, row, w, V, nm1, e, prev, ds, rss, acc);
+    store_voxel(A, V, acc, s_acc);
+}
+
+// J, FP32 / BF16 table: partial[b][e] = sum_{j in tile} h^b(R_ij) A_ij / C_i dc_j.
+// The U entries of a step are reduced together; lane u then stores entry e+u.
+template <int NB, class TabT, int U>
+__device__ __forceinline__ void j32_step(const ApplyArgs& A, const TabT* st,
+                                         const Entry* __restrict__ ents,
+                                         const TxConst* __restrict__ row, float* __restrict__ part,
+                                         const LaneVox& V, float xv, float nm1, int lane, int64_t e,
+                                         int& prev, float& ds, float& rss) {
+    Entry E[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) E[u] = ents[e + u];
+    float dsu[U], rssu[U], dr[U], rsr[U];
+    source_parts<U>(E, row, V, prev, ds, rss, dsu, rssu, dist32);
+#pragma unroll
+    for (int u = 0; u < U; ++u) dist32(row[E[u].sr >> 16], V.ux, V.uy, V.uz, V.uu, dr[u], rsr[u]);
+    float R[U], t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        R[u] = (dsu[u] + dr[u]) + E[u].R0hi;
+        t[u] = (rssu[u] * xv) * rsr[u];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = lookup(st + b * A.ntab, R[u], A.inv_dr[b], nm1) * t[u];
+        const float sum = multi_sum<U>(v, lane);
+        if (lane < U) part[b * A.nnz + e + lane] = sum;
+    }
+}
+
+template <int NB, class TabT, int U>
+__global__ __launch_bounds__(1024) void k_j32(ApplyArgs A) {
+    const TabT* st = stage_table<TabT>(A, NB);
+    int64_t a, e0, e1;
+    if (!wave_work(A, U, a, e0, e1)) return;
+    const int lane = threadIdx.x & 63;
+    const LaneVox V = lane_vox(A, a, lane);
+    const TxConst* __restrict__ row = A.txc + a * A.n_tx;
+    float* __restrict__ part = static_cast<float*>(A.out);
+    const float xv = V.act ? static_cast<const float*>(A.x)[V.vidx] : 0.f;
+    const float nm1 = (float)(A.ntab - 1);
+    float ds = 0.f, rss = 0.f;
+    int prev = -1;
+    int64_t e = e0;
+    for (; e + U <= e1; e += U)
+        j32_step<NB, TabT, U>(A, st, A.ents, row, part, V, xv, nm1, lane, e, prev, ds, rss);
+    for (; e < e1; ++e)
+        j32_step<NB, TabT, 1>(A, st, A.ents, row, part, V, xv, nm1, lane, e, prev, ds, rss);
+}
+
+// FP64 counterparts (Rx carried instead of 1/Rx).
+template <int NB, int U>
+__device__ __forceinline__ void jt64_step(const ApplyArgs& A, const double2* st,
+                                          const Entry* __restrict__ ents,
+                                          const TxConst* __restrict__ row,
+                                          const double* __restrict__ w, const LaneVox& V,
+                                          double nm1, int64_t e, int& prev, double& ds,
+                                          double& Rs, double& acc) {
+    Entry E[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) E[u] = ents[e + u];
+    double dsu[U], Rsu[U], dr[U], Rr[U];
+    source_parts<U>(E, row, V, prev, ds, Rs, dsu, Rsu, dist64);
+#pragma unroll
+    for (int u = 0; u < U; ++u) dist64(row[E[u].sr >> 16], V.ux, V.uy, V.uz, V.uu, dr[u], Rr[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const double R = (dsu[u] + dr[u]) + ((double)E[u].R0hi + (double)E[u].R0lo);
+        double hw = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            hw = fma(lookup(st + b * A.ntab, R, A.inv_dr64[b], nm1), w[b * A.M + E[u].p], hw);
+        acc += hw / (Rsu[u] * Rr[u]);
+    }
+}
+
+template <int NB, bool LDS_TAB, int U>
+__global__ __launch_bounds__(1024) void k_jt64(ApplyArgs A) {
+    const double2* st = LDS_TAB ? stage_table<double2>(A, NB) : static_cast<const double2*>(A.tab);
+    double* s_acc = reinterpret_cast<double*>(lds_after<double2>(A, LDS_TAB ? NB : 0));
+    int64_t a, e0, e1;
+    if (!wave_work(A, U, a, e0, e1)) return;
+    const int lane = threadIdx.x & 63;
+    const LaneVox V = lane_vox(A, a, lane);
+    const TxConst* __restrict__ row = A.txc + a * A.n_tx;
+    const double* __restrict__ w = static_cast<const double*>(A.w);
+    const double nm1 = (double)(A.ntab - 1);
+    double acc = 0.0, ds = 0.0, Rs = 1.0;
+    int prev = -1;
+    int64_t e = e0;
+    for (; e + U <= e1; e += U) jt64_step<NB, U>(A, st, A.ents, row, w, V, nm1, e, prev, ds, Rs, acc);
+    for (; e < e1; ++e) jt64_step<NB, 1>(A, st, A.ents, row, w, V, nm1, e, prev, ds, Rs, acc);
+    store_voxel(A, V, acc, s_acc);
+}
+
+template <int NB, int U>
+__device__ __forceinline__ void j64_step(const ApplyArgs& A, const double2* st,
+                                         const Entry* __restrict__ ents,
+                                         const TxConst* __restrict__ row,
+                                         double* __restrict__ part, const LaneVox& V, double xv,
+                                         double nm1, int lane, int64_t e, int& prev, double& ds,
+                                         double& Rs) {
+    Entry E[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) E[u] = ents[e + u];
+    double dsu[U], Rsu[U], dr[U], Rr[U];
+    source_parts<U>(E, row, V, prev, ds, Rs, dsu, Rsu, dist64);
+#pragma unroll
+    for (int u = 0; u < U; ++u) dist64(row[E[u].sr >> 16], V.ux, V.uy, V.uz, V.uu, dr[u], Rr[u]);
+    double R[U], t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        R[u] = (dsu[u] + dr[u]) + ((double)E[u].R0hi + (double)E[u].R0lo);
+        t[u] = xv / (Rsu[u] * Rr[u]);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = lookup(st + b * A.ntab, R[u], A.inv_dr64[b], nm1) * t[u];
+        const double sum = multi_sum<U>(v, lane);
+        if (lane < U) part[b * A.nnz + e + lane] = sum;
+    }
+}
+
+template <int NB, bool LDS_TAB, int U>
+__global__ __launch_bounds__(1024) void k_j64(ApplyArgs A) {
+    const double2* st = LDS_TAB ? stage_table<double2>(A, NB) : static_cast<const double2*>(A.tab);
+    int64_t a, e0, e1;
+    if (!wave_work(A, U, a, e0, e1)) return;
+    const int lane = threadIdx.x & 63;
+    const LaneVox V = lane_vox(A, a, lane);
+    const TxConst* __restrict__ row = A.txc + a * A.n_tx;
+    double* __restrict__ part = static_cast<double*>(A.out);
+    const double xv = V.act ? static_cast<const double*>(A.x)[V.vidx] : 0.0;
+    const double nm1 = (double)(A.ntab - 1);
+    double ds = 0.0, Rs = 1.0;
+    int prev = -1;
+    int64_t e = e0;
+    for (; e + U <= e1; e += U)
+        j64_step<NB, U>(A, st, A.ents, row, part, V, xv, nm1, lane, e, prev, ds, Rs);
+    for (; e < e1; ++e)
+        j64_step<NB, 1>(A, st, A.ents, row, part, V, xv, nm1, lane, e, prev, ds, Rs);
+}
+
+// One wavefront per tile, waves_per_block tiles per workgroup sharing the
+// LDS copy of the tables.
+template <class K>
+static hipError_t launch_k(K kern, hipStream_t s, const ApplyArgs& a, size_t table_bytes,
+                           size_t acc_bytes) {
+    if (a.n_act == 0) return hipSuccess;
+    const int wpb = a.waves_per_block;
+    const size_t lds = ((table_bytes + 15) & ~(size_t)15) + (a.split ? acc_bytes * 64 * wpb : 0);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const unsigned nblk = a.split ? (unsigned)a.n_act : (unsigned)((a.n_act + wpb - 1) / wpb);
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * wpb), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int NB, int U>
+static hipError_t launch_nbu(hipStream_t s, fftt_precision prec, bool transpose,
+                             const ApplyArgs& a) {
+    const size_t n = (size_t)NB * a.ntab;
+    switch (prec) {
+        case FFTT_FP32:
+            return transpose ? launch_k(k_jt32<NB, float2, U>, s, a, n * sizeof(float2), 4)
+                             : launch_k(k_j32<NB, float2, U>, s, a, n * sizeof(float2), 0);
+        case FFTT_FP32_BF16TABLE:
+            return transpose ? launch_k(k_jt32<NB, uint32_t, U>, s, a, n * sizeof(uint32_t), 4)
+                             : launch_k(k_j32<NB, uint32_t, U>, s, a, n * sizeof(uint32_t), 0);
+        case FFTT_FP64: {
+            const size_t bytes = n * sizeof(double2);
+            if (bytes <= 131072)
+                return transpose ? launch_k(k_jt64<NB, true, U>, s, a, bytes, 8)
+                                 : launch_k(k_j64<NB, true, U>, s, a, bytes, 0);
+            return transpose ? launch_k(k_jt64<NB, false, U>, s, a, 0, 8)
+                             : launch_k(k_j64<NB, false, U>, s, a, 0, 0);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int NB>
+static hipError_t launch_nb(hipStream_t s, fftt_precision prec, bool transpose,
+                            const ApplyArgs& a) {
+    switch (a.unroll) {
+        case 1: return launch_nbu<NB, 1>(s, prec, transpose, a);
+        case 2: return launch_nbu<NB, 2>(s, prec, transpose, a);
+        case 4: return launch_nbu<NB, 4>(s, prec, transpose, a);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_apply(hipStream_t s, fftt_precision prec, bool transpose, const ApplyArgs& a) {
+    switch (a.nb) {
+        case 1: return launch_nb<1>(s, prec, transpose, a);
+        case 2: return launch_nb<2>(s, prec, transpose, a);
+        case 3: return launch_nb<3>(s, prec, transpose, a);
+        case 4: return launch_nb<4>(s, prec, transpose, a);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ J reduction
+//
+// dT^b[porig[p]] = C_p * sum over the pair's partials, one wavefront per pair,
+// FP64 accumulation in a fixed order.
+
+template <class T>
+__global__ __launch_bounds__(1024) void k_reduce(const T* __restrict__ part, int64_t nnz,
+                                                const int64_t* __restrict__ pptr,
+                                                const int64_t* __restrict__ pidx,
+                                                const double* __restrict__ C,
+                                                const int32_t* __restrict__ porig, int64_t M,
+                                                int nb, T* __restrict__ dT) {
+    const int64_t p = wave_tile();
+    const int lane = threadIdx.x & 63;
+    if (p >= M) return;
+    const int64_t k0 = pptr[p], k1 = pptr[p + 1];
+    for (int b = 0; b < nb; ++b) {
+        double acc = 0.0;
+        for (int64_t k = k0 + lane; k < k1; k += 64) acc += (double)part[b * nnz + pidx[k]];
+        acc = wave_sum(acc);
+        if (lane == 0) dT[b * M + porig[p]] = (T)(C[p] * acc);
+    }
+}
+
+hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz,
+                         const int64_t* pptr, const int64_t* pidx, const double* C,
+                         const int32_t* porig, int64_t M, int nb, void* dT) {
+    const unsigned nblk = (unsigned)((M + 15) / 16);
+    if (fp64)
+        hipLaunchKernelGGL(k_reduce<double>, dim3(nblk), dim3(64 * 16), 0, s,
+                           (const double*)part, nnz, pptr, pidx, C, porig, M, nb, (double*)dT);
+    else
+        hipLaunchKernelGGL(k_reduce<float>, dim3(nblk), dim3(64 * 16), 0, s,
+                           (const float*)part, nnz, pptr, pidx, C, porig, M, nb, (float*)dT);
+    return hipGetLastError();
+}
+
+}  // namespace fftt

@@ -1,0 +1,316 @@
+"""Parity of the HIP operators with the CPU FP64 oracle (through the C ABI).
+
+Tolerances (norm-wise relative, |y - y_ref|_2 / |y_ref|_2):
+  FP32 path vs oracle quadrature ........ 1e-5
+  BF16-table path vs oracle quadrature .. 1e-3
+  FP64 path vs oracle with the same linear table ... 1e-11
+  FP64 path vs oracle quadrature: the table's own interpolation error (the
+  oracle's table-vs-quadrature difference) plus 1e-11.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_03302_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _fftt():
+    from paper_1908_03302_amd import fftt
+    return fftt
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(x, prec):
+    f = _fftt()
+    dt = torch.float64 if prec == f.FP64 else torch.float32
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dt).to("cuda:0").contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------ workloads
+
+def ragged_workload():
+    """Grid that is not a multiple of the 4^3 tile, masked, two bands."""
+    g = I.centred_grid((37, 29, 11), 1.0e-3)
+    tx = I.ring(24, 0.03, 0.0005, phase=0.1)
+    return I.Workload(
+        name="ragged", c0=1500.0, tx=tx, pairs=I.all_ordered_pairs(24), grid=g,
+        mask=I.cylinder_mask(g, 0.02),
+        pulses=[I.sampled_pulse(1e6, 1.0), I.sampled_pulse(2e6, 1.0)],
+        r_max=[I.R_MAX[1e6], I.R_MAX[2e6]], n_table=4096)
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = I.small_fp64()
+    say("fixture small:", w.name)
+    o = oracle.Oracle.from_workload(w)
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    ctx = _fftt().context_for_workload(w)
+    ctx.prepare()
+    return w, o, ot, ctx
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    w = ragged_workload()
+    say("fixture ragged:", w.name)
+    o = oracle.Oracle.from_workload(w)
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    ctx = _fftt().context_for_workload(w)
+    ctx.prepare()
+    return w, o, ot, ctx
+
+
+# ------------------------------------------------------------ small (config 1)
+
+def test_small_work_count_exact(small):
+    w, o, ot, ctx = small
+    pv, lanes = ctx.work_count()
+    assert pv == o.count_pv()
+    assert lanes >= pv
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32", "FP32_BF16TABLE"])
+def test_small_apply_J(small, prec_name):
+    w, o, ot, ctx = small
+    f = _fftt()
+    prec = getattr(f, prec_name)
+    x = w.model
+    y_ref = o.apply_J(x)
+    y = host(ctx.apply_J(dev(x, prec), prec=prec))
+    e = rel(y, y_ref)
+    say("small J", prec_name, "rel err vs quadrature oracle", e)
+    if prec == f.FP64:
+        y_tab = ot.apply_J(x)
+        assert rel(y, y_tab) < 1e-11
+        assert e <= rel(y_tab, y_ref) + 1e-11
+    elif prec == f.FP32:
+        assert e < 1e-5
+    else:
+        assert e < 1e-3
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32", "FP32_BF16TABLE"])
+def test_small_apply_JT(small, prec_name):
+    w, o, ot, ctx = small
+    f = _fftt()
+    prec = getattr(f, prec_name)
+    y = I.random_vector(w.m, 7) * 1e-7
+    x_ref = o.apply_JT(y)
+    x = host(ctx.apply_JT(dev(y, prec), prec=prec))
+    e = rel(x, x_ref)
+    say("small JT", prec_name, "rel err vs quadrature oracle", e)
+    if prec == f.FP64:
+        x_tab = ot.apply_JT(y)
+        assert rel(x, x_tab) < 1e-11
+        assert e <= rel(x_tab, x_ref) + 1e-11
+    elif prec == f.FP32:
+        assert e < 1e-5
+    else:
+        assert e < 1e-3
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32"])
+def test_small_adjoint_identity(small, prec_name):
+    w, o, ot, ctx = small
+    f = _fftt()
+    prec = getattr(f, prec_name)
+    x = I.random_vector(w.n, 21)
+    y = I.random_vector(w.m, 22)
+    Jx = host(ctx.apply_J(dev(x, prec), prec=prec))
+    JTy = host(ctx.apply_JT(dev(y, prec), prec=prec))
+    lhs, rhs = float(Jx @ y), float(x @ JTy)
+    tol = 1e-12 if prec == f.FP64 else 1e-5
+    assert abs(lhs - rhs) <= tol * max(abs(lhs), np.linalg.norm(Jx) * np.linalg.norm(y))
+
+
+def test_small_determinism(small):
+    w, o, ot, ctx = small
+    f = _fftt()
+    x = dev(I.random_vector(w.n, 3), f.FP32)
+    y = dev(I.random_vector(w.m, 4), f.FP32)
+    a1 = host(ctx.apply_J(x, prec=f.FP32))
+    a2 = host(ctx.apply_J(x, prec=f.FP32))
+    b1 = host(ctx.apply_JT(y, prec=f.FP32))
+    b2 = host(ctx.apply_JT(y, prec=f.FP32))
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+
+
+def test_small_reciprocity(small):
+    w, o, ot, ctx = small
+    f = _fftt()
+    idx = {tuple(p): i for i, p in enumerate(w.pairs)}
+    rec = np.array([idx[(p[1], p[0])] for p in w.pairs])
+    y = host(ctx.apply_J(dev(I.random_vector(w.n, 8), f.FP32), prec=f.FP32))
+    assert rel(y[rec], y) < 1e-6
+
+
+def test_small_columns_elementwise(small):
+    """J e_j (one column) for a few voxels: element-wise kernel values."""
+    w, o, ot, ctx = small
+    f = _fftt()
+    for j in (0, 1234, 3456, 6911):
+        e = np.zeros(w.n)
+        e[j] = 1.0
+        col_ref = o.block(cols=np.array([j]))[:, 0]
+        col = host(ctx.apply_J(dev(e, f.FP32), prec=f.FP32))
+        assert np.abs(col - col_ref).max() <= 2e-5 * np.abs(col_ref).max()
+
+
+def test_small_multi_rhs(small):
+    w, o, ot, ctx = small
+    f = _fftt()
+    X = np.stack([I.random_vector(w.n, 30 + k) for k in range(3)])
+    Y = host(ctx.apply_J(dev(X.ravel(), f.FP32), prec=f.FP32, n_rhs=3)).reshape(3, -1)
+    for k in range(3):
+        yk = host(ctx.apply_J(dev(X[k], f.FP32), prec=f.FP32))
+        assert np.array_equal(Y[k], yk)
+    Z = np.stack([I.random_vector(w.m, 40 + k) for k in range(2)])
+    XT = host(ctx.apply_JT(dev(Z.ravel(), f.FP32), prec=f.FP32, n_rhs=2)).reshape(2, -1)
+    for k in range(2):
+        assert np.array_equal(XT[k], host(ctx.apply_JT(dev(Z[k], f.FP32), prec=f.FP32)))
+
+
+# ------------------------------------------------------------ ragged, two bands
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32", "FP32_BF16TABLE"])
+def test_ragged_two_bands(ragged, prec_name):
+    w, o, ot, ctx = ragged
+    f = _fftt()
+    prec = getattr(f, prec_name)
+    x = I.random_vector(w.n, 50) * 10.0
+    y_ref = o.apply_J(x)            # [2][M]
+    y = host(ctx.apply_J(dev(x, prec), prec=prec)).reshape(2, -1)
+    yt = I.random_vector(2 * w.m, 51) * 1e-7
+    x_ref = o.apply_JT(yt)
+    xg = host(ctx.apply_JT(dev(yt, prec), prec=prec))
+    ej, et = rel(y, y_ref), rel(xg, x_ref)
+    say("ragged", prec_name, "J", ej, "JT", et)
+    # inactive voxels are written as zero
+    assert np.all(xg[w.mask == 0] == 0.0)
+    if prec == f.FP64:
+        assert rel(y, ot.apply_J(x)) < 1e-11 and rel(xg, ot.apply_JT(yt)) < 1e-11
+    elif prec == f.FP32:
+        assert ej < 1e-5 and et < 1e-5
+    else:
+        assert ej < 1e-3 and et < 1e-3
+    pv, _ = ctx.work_count()
+    assert pv == o.count_pv()
+
+
+# ------------------------------------------------------------ on-ray zero
+
+def test_zero_on_the_ray_fp32():
+    """A voxel centre on the straight path between a source and a receiver
+    has zero sensitivity (R = 0); the FP32 kernel must not lose that to
+    cancellation in R_xs + R_xr - L."""
+    f = _fftt()
+    g = I.centred_grid((41, 21, 9), 0.8e-3)
+    tx = np.array([[-0.11, 0.0, 0.0], [0.11, 0.0, 0.0]])
+    pairs = np.array([[0, 1]], dtype=np.int32)
+    p = I.sampled_pulse(1e6, 1.0)
+    ctx = f.Context(0)
+    ctx.set_geometry(1500.0, tx, pairs, g.origin, g.spacing, g.dims, None)
+    h, rm = f.build_table_from_pulse(1500.0, p.samples, p.dt, 4096, I.R_MAX[1e6])
+    ctx.set_kernel_table(0, h, rm)
+    y = I.random_vector(1, 1) * 0 + 1.0
+    col = host(ctx.apply_JT(dev(y, f.FP32), prec=f.FP32)).reshape(9, 21, 41)
+    on = np.abs(col[4, 10, :])            # y = z = 0: on the ray
+    say("on-ray max", on.max(), "column max", np.abs(col).max())
+    # cancellation-free detour: ~1e-6 of the peak; a plain FP32 sum of the
+    # two 0.1 m distances would leave ~1e-4
+    assert on.max() <= 2e-5 * np.abs(col).max()
+
+
+# ------------------------------------------------------------ lab-like ring (config 2)
+
+@pytest.fixture(scope="module")
+def ring2d():
+    w = I.ring2d()
+    say("fixture ring2d:", w.name)
+    ctx = _fftt().context_for_workload(w)
+    ctx.prepare()
+    o = oracle.Oracle.from_workload(w)
+    return w, o, ctx
+
+
+def test_ring2d_sampled_rows_and_columns(ring2d):
+    """Full-size 128-element ring on the 256x256x64 grid, FP32: sampled rows
+    of J dc (the phantom) and sampled columns of J^T dT against the oracle."""
+    w, o, ctx = ring2d
+    f = _fftt()
+    rng = np.random.default_rng(9)
+    rows = np.sort(rng.choice(w.m, 24, replace=False))
+    x = w.model
+    y = host(ctx.apply_J(dev(x, f.FP32), prec=f.FP32))
+    y_ref = o.rows(rows, x)
+    ej = rel(y[rows], y_ref)
+    act = np.flatnonzero(w.mask)
+    cols = np.sort(rng.choice(act, 2048, replace=False))
+    yt = I.random_vector(w.m, 10) * 1e-7
+    xg = host(ctx.apply_JT(dev(yt, f.FP32), prec=f.FP32))
+    x_ref = o.cols(cols, yt)
+    et = rel(xg[cols], x_ref)
+    say("ring2d FP32 sampled rows", ej, "cols", et)
+    assert ej < 1e-5 and et < 1e-5
+    xb = host(ctx.apply_JT(dev(yt, f.FP32_BF16TABLE), prec=f.FP32_BF16TABLE))
+    assert rel(xb[cols], x_ref) < 1e-3
+
+
+def test_ring2d_adjoint_fp32(ring2d):
+    w, o, ctx = ring2d
+    f = _fftt()
+    x = I.random_vector(w.n, 61) * w.mask
+    y = I.random_vector(w.m, 62)
+    Jx = host(ctx.apply_J(dev(x, f.FP32), prec=f.FP32))
+    JTy = host(ctx.apply_JT(dev(y, f.FP32), prec=f.FP32))
+    lhs, rhs = float(Jx @ y), float(x @ JTy)
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(Jx) * np.linalg.norm(y)
+
+
+# ------------------------------------------------------------ launch shapes
+
+@pytest.mark.parametrize("wpb,unroll,split", [(1, 1, 0), (4, 2, 0), (8, 4, 0), (16, 4, 0),
+                                              (4, 1, 1), (8, 2, 1), (16, 4, 1)])
+def test_launch_shapes_agree(ragged, wpb, unroll, split):
+    """Every tuning (tiles per workgroup, unroll, split of a tile's pairs over
+    a workgroup) computes the same operator, within the FP32/FP64 bars."""
+    w, o, ot, ctx = ragged
+    f = _fftt()
+    ctx.set_tuning(waves_per_block=wpb, unroll_jt=unroll, unroll_j=unroll, split_jt=split,
+                   split_j=split)
+    try:
+        x = I.random_vector(w.n, 70) * 5.0
+        yt = I.random_vector(2 * w.m, 71) * 1e-7
+        y_ref, x_ref = o.apply_J(x), o.apply_JT(yt)
+        for prec in (f.FP32, f.FP64):
+            y = host(ctx.apply_J(dev(x, prec), prec=prec)).reshape(2, -1)
+            xg = host(ctx.apply_JT(dev(yt, prec), prec=prec))
+            if prec == f.FP64:
+                assert rel(y, ot.apply_J(x)) < 1e-11 and rel(xg, ot.apply_JT(yt)) < 1e-11
+            else:
+                assert rel(y, y_ref) < 1e-5 and rel(xg, x_ref) < 1e-5
+    finally:
+        ctx.set_tuning(waves_per_block=16, unroll_jt=2, unroll_j=4, split_jt=0, split_j=1)
