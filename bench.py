@@ -50,16 +50,18 @@ def cpu_baseline(w, budget_s=15.0):
         R = np.linalg.norm(cen - xs, axis=1) + np.linalg.norm(cen - xr, axis=1) - L
         return int(np.count_nonzero(R < rm))
 
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # rows run in parallel over the cores: size the sample from a probe of
+    # one row per core
     t0 = time.perf_counter()
-    o.rows(rows_all[:1], x)
+    o.rows(rows_all[:cores], x)
     t1 = time.perf_counter() - t0
-    n = max(2, min(256, int(budget_s / max(t1, 1e-3))))
+    n = max(cores, min(4096, int(budget_s / max(t1, 1e-3)) * cores))
     rows = rows_all[:n]
     t0 = time.perf_counter()
     o.rows(rows, x)
     dt = time.perf_counter() - t0
     pv = sum(pv_of(r) for r in rows)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": pv / dt, "unit": "pair-voxel evals/s", "cores": cores, "kind": "oracle",
             "sample": "%d random rows of J dc (whole 256x256x64 grid each, %d pv), FP64 "
                       "quadrature, %.1f s" % (n, pv, dt)}
@@ -68,10 +70,11 @@ def cpu_baseline(w, budget_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-misfit legs")
+    ap.add_argument("--cg-iters", type=int, default=20)
     ap.add_argument("--waves-per-block", type=int, default=None)
     ap.add_argument("--unroll-jt", type=int, default=None)
     ap.add_argument("--unroll-j", type=int, default=None)
@@ -151,10 +154,48 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "flops_per_pv": FLOPS_PER_PV},
     }
+    if not args.no_cg:
+        out["cg"] = cg_time_to_misfit(ctx, w, fftt, torch, args.cg_iters)
     if not args.no_cpu:
         log("bench: CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
+
+
+def cg_time_to_misfit(ctx, w, fftt, torch, iters):
+    """CGLS on the Tikhonov-damped normal equations: the plain FP64 path runs
+    `iters` iterations and fixes the target misfit Phi* (|J x - d|^2 / sigma^2);
+    both paths are then timed until misfit <= Phi* (1 + 1e-3)."""
+    import numpy as np
+    from paper_1908_03302_amd import inputs as I
+    dev = torch.device("cuda:0")
+    sig = w.noise_sigma
+    alpha = w.extra["alpha"]
+    d64 = ctx.apply_J(torch.tensor(w.model, dtype=torch.float64, device=dev), prec=fftt.FP64)
+    d64 = d64 + torch.tensor(I.noise(w.m, sig, w.noise_seed), dtype=torch.float64, device=dev)
+    d32 = d64.float()
+    x64 = torch.zeros(w.n, dtype=torch.float64, device=dev)
+    x32 = torch.zeros(w.n, dtype=torch.float32, device=dev)
+    ref = ctx.solve(d64, x64, method=0, prec=fftt.FP64, alpha=alpha, noise_sigma=sig,
+                    max_iter=iters)
+    target = ref["misfit"] * (1 + 1e-3)
+    r64 = ctx.solve(d64, x64, method=0, prec=fftt.FP64, alpha=alpha, noise_sigma=sig,
+                    max_iter=4 * iters, target_misfit=target)
+    r32 = ctx.solve(d32, x32, method=0, prec=fftt.FP32, alpha=alpha, noise_sigma=sig,
+                    max_iter=4 * iters, target_misfit=target)
+    # final misfits re-evaluated with the FP64 operator (untimed)
+    def true_misfit(x):
+        r = ctx.apply_J(x.double().contiguous(), prec=fftt.FP64) - d64
+        return float((r * r).sum()) / sig ** 2
+    out = {"alpha": alpha, "noise_sigma": sig, "fp64_iters_for_target": iters,
+           "target_misfit": target,
+           "fp64": {"ms": r64["time_ms"], "iters": r64["iters"], "misfit": true_misfit(x64)},
+           "mixed_fp32": {"ms": r32["time_ms"], "iters": r32["iters"], "misfit": true_misfit(x32)},
+           }
+    out["speedup_mixed_vs_fp64"] = r64["time_ms"] / r32["time_ms"]
+    log("bench: CG to misfit %.6g: FP64 %.1f ms (%d it), mixed %.1f ms (%d it)"
+        % (target, r64["time_ms"], r64["iters"], r32["time_ms"], r32["iters"]))
+    return out
 
 
 if __name__ == "__main__":

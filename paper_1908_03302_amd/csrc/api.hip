@@ -1,6 +1,7 @@
 // C ABI entry points: context, validation, geometry pre-pass, table upload,
 // and dispatch of the operator kernels.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -215,6 +216,48 @@ hipError_t prof_begin(fftt_ctx* c, int k, hipEvent_t* stop) {
 
 hipError_t prof_end(fftt_ctx* c, hipEvent_t stop) {
     return stop ? hipEventRecord(stop, c->stream) : hipSuccess;
+}
+
+// dT [B][M] = J dc (caller order), one right-hand side; ensure_ready done.
+fftt_status apply_J_one(fftt_ctx* c, fftt_precision prec, const void* x, void* y) {
+    const bool fp64 = prec == FFTT_FP64;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    FFTT_HIP(c, c->d_part.alloc((size_t)c->nb * std::max<int64_t>(c->nnz, 1) * es));
+    ApplyArgs a = base_args(c);
+    a.tab = fp64 ? c->d_tab64.p : (prec == FFTT_FP32 ? c->d_tab32.p : c->d_tabbf.p);
+    a.out = c->d_part.p;
+    a.unroll = c->unroll_j;
+    a.split = c->split_j;
+    a.x = x;
+    hipEvent_t stop;
+    FFTT_HIP(c, prof_begin(c, 0, &stop));
+    FFTT_HIP(c, launch_apply(c->stream, prec, false, a));
+    FFTT_HIP(c, prof_end(c, stop));
+    FFTT_HIP(c, prof_begin(c, 2, &stop));
+    FFTT_HIP(c, launch_reduce(c->stream, fp64, c->d_part.p, c->nnz, c->d_pptr.as<int64_t>(),
+                              c->d_pidx.as<int64_t>(), c->d_C.as<double>(),
+                              c->d_porig.as<int32_t>(), c->M, c->nb, y));
+    FFTT_HIP(c, prof_end(c, stop));
+    return FFTT_OK;
+}
+
+// dc [N] = J^T dT, one right-hand side; ensure_ready done.
+fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* x) {
+    const bool fp64 = prec == FFTT_FP64;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    FFTT_HIP(c, c->d_w.alloc((size_t)c->nb * c->M * es));
+    ApplyArgs a = base_args(c);
+    a.tab = fp64 ? c->d_tab64.p : (prec == FFTT_FP32 ? c->d_tab32.p : c->d_tabbf.p);
+    a.w = c->d_w.p;
+    a.out = x;
+    FFTT_HIP(c, launch_weights(c->stream, fp64, y, c->d_porig.as<int32_t>(), c->d_C.as<double>(),
+                               c->M, c->nb, c->d_w.p));
+    FFTT_HIP(c, launch_fill(c->stream, fp64, x, c->N));
+    hipEvent_t stop;
+    FFTT_HIP(c, prof_begin(c, 1, &stop));
+    FFTT_HIP(c, launch_apply(c->stream, prec, true, a));
+    FFTT_HIP(c, prof_end(c, stop));
+    return FFTT_OK;
 }
 
 fftt_status ensure_ready(fftt_ctx* c) {
@@ -455,26 +498,11 @@ fftt_status fftt_apply_J(fftt_ctx* c, fftt_precision prec, const void* dc, void*
     if (!dc || !dT || n_rhs < 1) FFTT_BAD(c, "apply_J: null buffer or n_rhs < 1");
     fftt_status st = ensure_ready(c);
     if (st != FFTT_OK) return st;
-    const bool fp64 = prec == FFTT_FP64;
-    const size_t es = fp64 ? sizeof(double) : sizeof(float);
-    FFTT_HIP(c, c->d_part.alloc((size_t)c->nb * std::max<int64_t>(c->nnz, 1) * es));
-    ApplyArgs a = base_args(c);
-    a.tab = fp64 ? c->d_tab64.p : (prec == FFTT_FP32 ? c->d_tab32.p : c->d_tabbf.p);
-    a.out = c->d_part.p;
-    a.unroll = c->unroll_j;
-    a.split = c->split_j;
+    const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
     for (int32_t r = 0; r < n_rhs; ++r) {
-        a.x = static_cast<const char*>(dc) + (size_t)r * c->N * es;
-        void* y = static_cast<char*>(dT) + (size_t)r * c->nb * c->M * es;
-        hipEvent_t stop;
-        FFTT_HIP(c, prof_begin(c, 0, &stop));
-        FFTT_HIP(c, launch_apply(c->stream, prec, false, a));
-        FFTT_HIP(c, prof_end(c, stop));
-        FFTT_HIP(c, prof_begin(c, 2, &stop));
-        FFTT_HIP(c, launch_reduce(c->stream, fp64, c->d_part.p, c->nnz, c->d_pptr.as<int64_t>(),
-                                  c->d_pidx.as<int64_t>(), c->d_C.as<double>(),
-                                  c->d_porig.as<int32_t>(), c->M, c->nb, y));
-        FFTT_HIP(c, prof_end(c, stop));
+        st = apply_J_one(c, prec, static_cast<const char*>(dc) + (size_t)r * c->N * es,
+                         static_cast<char*>(dT) + (size_t)r * c->nb * c->M * es);
+        if (st != FFTT_OK) return st;
     }
     return FFTT_OK;
 }
@@ -486,23 +514,11 @@ fftt_status fftt_apply_JT(fftt_ctx* c, fftt_precision prec, const void* dT, void
     if (!dc || !dT || n_rhs < 1) FFTT_BAD(c, "apply_JT: null buffer or n_rhs < 1");
     fftt_status st = ensure_ready(c);
     if (st != FFTT_OK) return st;
-    const bool fp64 = prec == FFTT_FP64;
-    const size_t es = fp64 ? sizeof(double) : sizeof(float);
-    FFTT_HIP(c, c->d_w.alloc((size_t)c->nb * c->M * es));
-    ApplyArgs a = base_args(c);
-    a.tab = fp64 ? c->d_tab64.p : (prec == FFTT_FP32 ? c->d_tab32.p : c->d_tabbf.p);
-    a.w = c->d_w.p;
+    const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
     for (int32_t r = 0; r < n_rhs; ++r) {
-        const void* y = static_cast<const char*>(dT) + (size_t)r * c->nb * c->M * es;
-        void* x = static_cast<char*>(dc) + (size_t)r * c->N * es;
-        FFTT_HIP(c, launch_weights(c->stream, fp64, y, c->d_porig.as<int32_t>(),
-                                   c->d_C.as<double>(), c->M, c->nb, c->d_w.p));
-        FFTT_HIP(c, launch_fill(c->stream, fp64, x, c->N));
-        a.out = x;
-        hipEvent_t stop;
-        FFTT_HIP(c, prof_begin(c, 1, &stop));
-        FFTT_HIP(c, launch_apply(c->stream, prec, true, a));
-        FFTT_HIP(c, prof_end(c, stop));
+        st = apply_JT_one(c, prec, static_cast<const char*>(dT) + (size_t)r * c->nb * c->M * es,
+                          static_cast<char*>(dc) + (size_t)r * c->N * es);
+        if (st != FFTT_OK) return st;
     }
     return FFTT_OK;
 }
@@ -552,17 +568,178 @@ fftt_status fftt_kernel_time(fftt_ctx* c, int32_t which, double* ms, int64_t* la
     return FFTT_OK;
 }
 
-fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts*, const void*, void*,
-                       fftt_solve_report*) {
+fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs, void* x,
+                       fftt_solve_report* rep) {
     if (!c) return FFTT_E_INVALID;
-    c->err = "solve: not built yet";
-    return FFTT_E_UNSUPPORTED;
+    if (!o || !d_obs || !x) FFTT_BAD(c, "solve: null argument");
+    if (o->method != 0 && o->method != 1) FFTT_BAD(c, "solve: method must be 0 (CGLS) or 1 (LSQR)");
+    if (o->prec < FFTT_FP64 || o->prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "solve: unknown precision");
+    if (!(o->noise_sigma > 0) || !std::isfinite(o->noise_sigma)) FFTT_BAD(c, "solve: noise_sigma must be > 0");
+    if (!(o->alpha >= 0) || !std::isfinite(o->alpha)) FFTT_BAD(c, "solve: alpha must be >= 0");
+    if (o->max_iter < 0) FFTT_BAD(c, "solve: max_iter < 0");
+    fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    const fftt_precision prec = (fftt_precision)o->prec;
+    const bool fp64 = prec == FFTT_FP64;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    const int64_t N = c->N, D = (int64_t)c->nb * c->M;
+    const double isg = 1.0 / o->noise_sigma, alpha = o->alpha;
+    hipStream_t s = c->stream;
+    // vectors: data-space r (or u), q; model-space sv, p (or v), w
+    FFTT_HIP(c, c->d_solve.alloc((size_t)(2 * D + 3 * N) * es));
+    char* base = c->d_solve.as<char>();
+    void* r = base;
+    void* q = base + D * es;
+    void* sv = base + 2 * D * es;
+    void* p = base + (2 * D + N) * es;
+    void* wv = base + (2 * D + 2 * N) * es;
+    FFTT_HIP(c, c->d_scal.alloc((32 + 512) * sizeof(double)));
+    double* sc = c->d_scal.as<double>();
+    double* part = sc + 32;
+    FFTT_HIP(c, hipMemsetAsync(sc, 0, 32 * sizeof(double), s));
+    const bool check = o->target_misfit > 0 || o->rel_tol > 0;
+    double hs[32];
+    auto fetch = [&]() -> fftt_status {
+        FFTT_HIP(c, hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+        FFTT_HIP(c, hipStreamSynchronize(s));
+        return FFTT_OK;
+    };
+#define SOLVE_OK(expr)                       \
+    do {                                     \
+        fftt_status st_ = (expr);            \
+        if (st_ != FFTT_OK) return st_;      \
+    } while (0)
+    const auto t0 = std::chrono::steady_clock::now();
+    int it = 0;
+    double misfit = 0.0, relres = 0.0;
+    if (o->method == 0) {
+        // CGLS on (J^T J / sigma^2 + alpha I) x = J^T d / sigma^2
+        enum { GAMMA = 0, DQ = 1, DP = 2, STEP = 3, BETA = 4, MIS = 5, G0 = 6, GNEW = 7 };
+        if (o->use_x0) {
+            SOLVE_OK(apply_J_one(c, prec, x, q));
+            FFTT_HIP(c, solver_lin2(s, fp64, r, d_obs, q, D, isg, -isg));
+        } else {
+            FFTT_HIP(c, launch_fill(s, fp64, x, N));
+            FFTT_HIP(c, solver_lin2(s, fp64, r, d_obs, nullptr, D, isg, 0.0));
+        }
+        SOLVE_OK(apply_JT_one(c, prec, r, sv));
+        FFTT_HIP(c, solver_axpby(s, fp64, sv, x, N, isg, -1, -alpha, -1, sc));
+        FFTT_HIP(c, solver_lin2(s, fp64, p, sv, nullptr, N, 1.0, 0.0));
+        FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, GAMMA, 1.0));
+        FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, G0, 1.0));
+        FFTT_HIP(c, solver_dot(s, fp64, r, r, D, part, sc, MIS, 1.0));
+        for (it = 0; it < o->max_iter;) {
+            SOLVE_OK(apply_J_one(c, prec, p, q));
+            FFTT_HIP(c, solver_dot(s, fp64, q, q, D, part, sc, DQ, isg * isg));
+            FFTT_HIP(c, solver_dot(s, fp64, p, p, N, part, sc, DP, 1.0));
+            FFTT_HIP(c, solver_cgls_step(s, sc, alpha));
+            FFTT_HIP(c, solver_axpby(s, fp64, x, p, N, 1.0, -1, 1.0, STEP, sc));
+            FFTT_HIP(c, solver_axpby(s, fp64, r, q, D, 1.0, -1, -isg, STEP, sc));
+            SOLVE_OK(apply_JT_one(c, prec, r, sv));
+            FFTT_HIP(c, solver_axpby(s, fp64, sv, x, N, isg, -1, -alpha, -1, sc));
+            FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, GNEW, 1.0));
+            FFTT_HIP(c, solver_cgls_beta(s, sc));
+            FFTT_HIP(c, solver_axpby(s, fp64, p, sv, N, 1.0, BETA, 1.0, -1, sc));
+            FFTT_HIP(c, solver_dot(s, fp64, r, r, D, part, sc, MIS, 1.0));
+            ++it;
+            if (check) {
+                SOLVE_OK(fetch());
+                misfit = hs[MIS];
+                relres = hs[G0] > 0 ? std::sqrt(hs[GAMMA] / hs[G0]) : 0.0;
+                if (o->target_misfit > 0 && misfit <= o->target_misfit) break;
+                if (o->rel_tol > 0 && relres <= o->rel_tol) break;
+            }
+        }
+        SOLVE_OK(fetch());
+        misfit = hs[MIS];
+        relres = hs[G0] > 0 ? std::sqrt(hs[GAMMA] / hs[G0]) : 0.0;
+    } else {
+        // LSQR (Paige & Saunders) on A = J / sigma, b = d / sigma, damp = sqrt(alpha)
+        enum { BETA = 8, ALPHA = 9, PHIBAR = 11, PHI_RHO = 12, THETA_RHO = 13, XX = 14,
+               INV_BETA = 15, INV_ALPHA = 16, BNORM = 20, RNORM0 = 21 };
+        const double damp = std::sqrt(alpha);
+        if (o->use_x0) FFTT_BAD(c, "solve: LSQR starts from x0 = 0 (use_x0 must be 0)");
+        FFTT_HIP(c, launch_fill(s, fp64, x, N));
+        FFTT_HIP(c, solver_lin2(s, fp64, r, d_obs, nullptr, D, isg, 0.0));           // u = b
+        FFTT_HIP(c, solver_dot(s, fp64, r, r, D, part, sc, BETA, 1.0));
+        FFTT_HIP(c, solver_dot(s, fp64, r, r, D, part, sc, BNORM, 1.0));
+        FFTT_HIP(c, solver_lsqr_beta(s, sc));
+        FFTT_HIP(c, solver_axpby(s, fp64, r, r, D, 0.0, -1, 1.0, INV_BETA, sc));      // u /= beta
+        SOLVE_OK(apply_JT_one(c, prec, r, sv));
+        FFTT_HIP(c, solver_lin2(s, fp64, p, sv, nullptr, N, isg, 0.0));             // v = A^T u
+        FFTT_HIP(c, solver_dot(s, fp64, p, p, N, part, sc, ALPHA, 1.0));
+        FFTT_HIP(c, solver_lsqr_alpha_rot(s, sc, damp, 1));
+        FFTT_HIP(c, solver_axpby(s, fp64, p, p, N, 0.0, -1, 1.0, INV_ALPHA, sc));     // v /= alpha
+        FFTT_HIP(c, solver_lin2(s, fp64, wv, p, nullptr, N, 1.0, 0.0));             // w = v
+        for (it = 0; it < o->max_iter;) {
+            SOLVE_OK(apply_J_one(c, prec, p, q));
+            FFTT_HIP(c, solver_axpby(s, fp64, r, q, D, -1.0, ALPHA, isg, -1, sc));   // u = Av - a u
+            FFTT_HIP(c, solver_dot(s, fp64, r, r, D, part, sc, BETA, 1.0));
+            FFTT_HIP(c, solver_lsqr_beta(s, sc));
+            FFTT_HIP(c, solver_axpby(s, fp64, r, r, D, 0.0, -1, 1.0, INV_BETA, sc));
+            SOLVE_OK(apply_JT_one(c, prec, r, sv));
+            FFTT_HIP(c, solver_axpby(s, fp64, p, sv, N, -1.0, BETA, isg, -1, sc));   // v = A^T u - b v
+            FFTT_HIP(c, solver_dot(s, fp64, p, p, N, part, sc, ALPHA, 1.0));
+            FFTT_HIP(c, solver_lsqr_alpha_rot(s, sc, damp, 0));
+            FFTT_HIP(c, solver_axpby(s, fp64, p, p, N, 0.0, -1, 1.0, INV_ALPHA, sc));
+            FFTT_HIP(c, solver_axpby(s, fp64, x, wv, N, 1.0, -1, 1.0, PHI_RHO, sc));  // x += phi/rho w
+            FFTT_HIP(c, solver_axpby(s, fp64, wv, p, N, 1.0, THETA_RHO, 1.0, -1, sc)); // w = v - theta/rho w
+            ++it;
+            if (check) {
+                FFTT_HIP(c, solver_dot(s, fp64, x, x, N, part, sc, XX, 1.0));
+                SOLVE_OK(fetch());
+                misfit = hs[PHIBAR] * hs[PHIBAR] - alpha * hs[XX];
+                relres = hs[BNORM] > 0 ? std::fabs(hs[PHIBAR]) / std::sqrt(hs[BNORM]) : 0.0;
+                if (o->target_misfit > 0 && misfit <= o->target_misfit) break;
+                if (o->rel_tol > 0 && relres <= o->rel_tol) break;
+            }
+        }
+        FFTT_HIP(c, solver_dot(s, fp64, x, x, N, part, sc, XX, 1.0));
+        SOLVE_OK(fetch());
+        misfit = hs[PHIBAR] * hs[PHIBAR] - alpha * hs[XX];
+        relres = hs[BNORM] > 0 ? std::fabs(hs[PHIBAR]) / std::sqrt(hs[BNORM]) : 0.0;
+    }
+#undef SOLVE_OK
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) {
+        rep->iters = it;
+        rep->misfit = misfit;
+        rep->rel_resid = relres;
+        rep->time_ms = ms;
+    }
+    if (o->target_misfit > 0 && !(misfit <= o->target_misfit)) return FFTT_NOT_CONVERGED;
+    if (o->target_misfit <= 0 && o->rel_tol > 0 && !(relres <= o->rel_tol)) return FFTT_NOT_CONVERGED;
+    return FFTT_OK;
 }
 
-fftt_status fftt_psf(fftt_ctx* c, fftt_precision, const int64_t*, int32_t, double, void*) {
+fftt_status fftt_psf(fftt_ctx* c, fftt_precision prec, const int64_t* voxels, int32_t n,
+                     double noise_sigma, void* out) {
     if (!c) return FFTT_E_INVALID;
-    c->err = "psf: not built yet";
-    return FFTT_E_UNSUPPORTED;
+    if (prec < FFTT_FP64 || prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "psf: unknown precision");
+    if (!voxels || !out || n < 1) FFTT_BAD(c, "psf: null argument or n < 1");
+    if (!(noise_sigma > 0) || !std::isfinite(noise_sigma)) FFTT_BAD(c, "psf: noise_sigma must be > 0");
+    fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    for (int32_t k = 0; k < n; ++k)
+        if (voxels[k] < 0 || voxels[k] >= c->N || !c->mask[voxels[k]])
+            FFTT_BAD(c, "psf: voxel index out of range or not active");
+    const bool fp64 = prec == FFTT_FP64;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    const int64_t D = (int64_t)c->nb * c->M;
+    FFTT_HIP(c, c->d_solve.alloc((size_t)(D + c->N) * es));
+    void* dT = c->d_solve.p;
+    void* e = c->d_solve.as<char>() + D * es;
+    const double s2 = 1.0 / (noise_sigma * noise_sigma);
+    for (int32_t k = 0; k < n; ++k) {
+        FFTT_HIP(c, solver_unit(c->stream, fp64, e, c->N, voxels[k]));
+        st = apply_J_one(c, prec, e, dT);
+        if (st != FFTT_OK) return st;
+        FFTT_HIP(c, solver_lin2(c->stream, fp64, dT, dT, nullptr, D, s2, 0.0));
+        st = apply_JT_one(c, prec, dT, static_cast<char*>(out) + (size_t)k * c->N * es);
+        if (st != FFTT_OK) return st;
+    }
+    return FFTT_OK;
 }
 
 }  // extern "C"

@@ -119,6 +119,19 @@ hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz
                          const int64_t* pptr, const int64_t* pidx, const double* C,
                          const int32_t* porig, int64_t M, int nb, void* dT);
 
+// ---- solver building blocks (solve.hip) ----
+hipError_t solver_dot(hipStream_t s, bool fp64, const void* a, const void* b, int64_t n,
+                      double* part, double* sc, int slot, double scale);
+hipError_t solver_axpby(hipStream_t s, bool fp64, void* y, const void* x, int64_t n, double ay,
+                        int sy, double ax, int sx, const double* sc);
+hipError_t solver_lin2(hipStream_t s, bool fp64, void* z, const void* x, const void* y, int64_t n,
+                       double ax, double ay);
+hipError_t solver_cgls_step(hipStream_t s, double* sc, double alpha_reg);
+hipError_t solver_cgls_beta(hipStream_t s, double* sc);
+hipError_t solver_lsqr_beta(hipStream_t s, double* sc);
+hipError_t solver_lsqr_alpha_rot(hipStream_t s, double* sc, double damp, int first);
+hipError_t solver_unit(hipStream_t s, bool fp64, void* x, int64_t n, int64_t v);
+
 // ---- host table builder (table.cpp) ----
 int build_table_from_pulse(double c0, const double* f, int64_t nt, double dt, int64_t n,
                            double r_max, double* h_out, double* r_max_out, std::string* err);
@@ -169,7 +182,7 @@ struct fftt_ctx {
     int split_jt = 0, split_j = 1;
 
     // work buffers
-    fftt::DevBuf d_w, d_part;
+    fftt::DevBuf d_w, d_part, d_solve, d_scal;
 
     // optional event timing of the main kernels (index: 0 J, 1 J^T, 2 reduction)
     bool prof = false;

@@ -205,6 +205,14 @@ R_MAX_HALF_MHZ_BW50 = 18.21e-3
 R_MAX = {0.5e6: 9.53e-3, 1.0e6: 4.77e-3, 1.5e6: 3.18e-3, 2.0e6: 2.39e-3}
 
 
+# Tikhonov weights (prior covariance I, noise 5 ns).  On the small ring the
+# discrepancy principle (misfit ~ number of data) gives 5e-3, i.e. 5.35e-3 of
+# the largest eigenvalue of J^T J / sigma^2 (0.934 there); the lab-like ring
+# uses the same fraction of its own largest eigenvalue (4.91, power iteration).
+ALPHA_SMALL = 5e-3
+ALPHA_RING2D = 2.63e-2
+
+
 def small_fp64() -> Workload:
     """32-element ring (r = 10 cm), 24x24x12 grid at 2 mm, 0.5 MHz, 50 % BW."""
     g = centred_grid((24, 24, 12), 2e-3)
@@ -214,7 +222,7 @@ def small_fp64() -> Workload:
         pulses=[sampled_pulse(0.5e6, 0.5)], r_max=[R_MAX_HALF_MHZ_BW50],
         n_table=4096, model=cylinder_phantom(g, 0.02, 30.0),
         noise_sigma=5e-9, noise_seed=0,
-        extra=dict(cg_iters=20))
+        extra=dict(cg_iters=20, alpha=ALPHA_SMALL))
 
 
 def ring2d(dims=(256, 256, 64)) -> Workload:
@@ -226,7 +234,7 @@ def ring2d(dims=(256, 256, 64)) -> Workload:
         pairs=all_ordered_pairs(128), grid=g, mask=cylinder_mask(g, 0.75 * R),
         pulses=[sampled_pulse(1.0e6, 1.0)], r_max=[R_MAX[1.0e6]], n_table=4096,
         model=nested_cylinders(g, (0.02, 0.045, 0.07), (15.0, -25.0, 40.0)),
-        noise_sigma=5e-9, noise_seed=3)
+        noise_sigma=5e-9, noise_seed=3, extra=dict(alpha=ALPHA_RING2D))
 
 
 def slices3d(dims=(256, 256, 160), n_per_ring=256, n_rings=16) -> Workload:
