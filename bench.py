@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-misfit legs")
     ap.add_argument("--cg-iters", type=int, default=20)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--waves-per-block", type=int, default=None)
     ap.add_argument("--unroll-jt", type=int, default=None)
     ap.add_argument("--unroll-j", type=int, default=None)
@@ -106,6 +108,13 @@ def main():
     def step():
         ctx.apply_J(dc, dT, prec=fftt.FP32)
         ctx.apply_JT(dT, dc2, prec=fftt.FP32)
+
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()

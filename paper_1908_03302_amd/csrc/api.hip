@@ -656,7 +656,7 @@ fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs,
     } else {
         // LSQR (Paige & Saunders) on A = J / sigma, b = d / sigma, damp = sqrt(alpha)
         enum { BETA = 8, ALPHA = 9, PHIBAR = 11, PHI_RHO = 12, THETA_RHO = 13, XX = 14,
-               INV_BETA = 15, INV_ALPHA = 16, BNORM = 20, RNORM0 = 21 };
+               INV_BETA = 15, INV_ALPHA = 16, RES2 = 19, BNORM = 20 };
         const double damp = std::sqrt(alpha);
         if (o->use_x0) FFTT_BAD(c, "solve: LSQR starts from x0 = 0 (use_x0 must be 0)");
         FFTT_HIP(c, launch_fill(s, fp64, x, N));
@@ -688,7 +688,7 @@ fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs,
             if (check) {
                 FFTT_HIP(c, solver_dot(s, fp64, x, x, N, part, sc, XX, 1.0));
                 SOLVE_OK(fetch());
-                misfit = hs[PHIBAR] * hs[PHIBAR] - alpha * hs[XX];
+                misfit = hs[PHIBAR] * hs[PHIBAR] + hs[RES2] - alpha * hs[XX];
                 relres = hs[BNORM] > 0 ? std::fabs(hs[PHIBAR]) / std::sqrt(hs[BNORM]) : 0.0;
                 if (o->target_misfit > 0 && misfit <= o->target_misfit) break;
                 if (o->rel_tol > 0 && relres <= o->rel_tol) break;
@@ -696,7 +696,7 @@ fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs,
         }
         FFTT_HIP(c, solver_dot(s, fp64, x, x, N, part, sc, XX, 1.0));
         SOLVE_OK(fetch());
-        misfit = hs[PHIBAR] * hs[PHIBAR] - alpha * hs[XX];
+        misfit = hs[PHIBAR] * hs[PHIBAR] + hs[RES2] - alpha * hs[XX];
         relres = hs[BNORM] > 0 ? std::fabs(hs[PHIBAR]) / std::sqrt(hs[BNORM]) : 0.0;
     }
 #undef SOLVE_OK

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kDotThreads) void k_dot_final(const double* __restr
 
 // y = cy * y + cx * x, where cy = ay (* sc[sy] if sy >= 0), cx likewise.
 template <class T>
-__global__ void k_axpby(T* __restrict__ y, const T* __restrict__ x, int64_t n, double ay, int sy,
+__global__ void k_axpby(T* y, const T* x, int64_t n, double ay, int sy,
                         double ax, int sx, const double* __restrict__ sc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -66,7 +66,7 @@ __global__ void k_axpby(T* __restrict__ y, const T* __restrict__ x, int64_t n, d
 
 // z = ax * x + ay * y (host constants)
 template <class T>
-__global__ void k_lin2(T* __restrict__ z, const T* __restrict__ x, const T* __restrict__ y,
+__global__ void k_lin2(T* z, const T* x, const T* y,
                        int64_t n, double ax, double ay) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -78,7 +78,7 @@ enum Slot {
     GAMMA = 0, DELTA_Q = 1, DELTA_P = 2, STEP = 3, BETA = 4, MISFIT = 5, GAMMA0 = 6, GNEW = 7,
     // LSQR
     L_BETA = 8, L_ALPHA = 9, L_RHOBAR = 10, L_PHIBAR = 11, L_PHI_RHO = 12, L_THETA_RHO = 13,
-    L_XX = 14, L_INV_BETA = 15, L_INV_ALPHA = 16, L_NEG_BETA = 17, L_NEG_ALPHA = 18,
+    L_XX = 14, L_INV_BETA = 15, L_INV_ALPHA = 16, L_NEG_BETA = 17, L_NEG_ALPHA = 18, L_RES2 = 19,
     NSLOTS = 24
 };
 
@@ -118,6 +118,9 @@ __global__ void k_lsqr_alpha_rot(double* sc, double damp, int first) {
     double phibar = sc[L_PHIBAR];
     const double rhobar1 = hypot(rhobar, damp);
     const double c1 = rhobar1 > 0.0 ? rhobar / rhobar1 : 1.0;
+    const double s1 = rhobar1 > 0.0 ? damp / rhobar1 : 0.0;
+    const double psi = s1 * phibar;   // part of the residual moved into the damping block
+    sc[L_RES2] += psi * psi;
     phibar *= c1;
     const double rho = hypot(rhobar1, beta);
     const double c = rho > 0.0 ? rhobar1 / rho : 1.0;
@@ -128,7 +131,7 @@ __global__ void k_lsqr_alpha_rot(double* sc, double damp, int first) {
     sc[L_PHIBAR] = s * phibar;
     sc[L_PHI_RHO] = rho > 0.0 ? phi / rho : 0.0;
     sc[L_THETA_RHO] = rho > 0.0 ? -theta / rho : 0.0;
-    // data misfit estimate |A x - b|^2 = phibar^2 - damp^2 |x|^2 is formed on the host
+    // |A x - b|^2 = phibar^2 + sum psi^2 - damp^2 |x|^2 is formed on the host
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
