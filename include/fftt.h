@@ -171,9 +171,14 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *     inner-loop step of the J^T / J kernel: 1, 2 or 4.
  *   FFTT_TUNE_SPLIT_JT / FFTT_TUNE_SPLIT_J: 0 = every wavefront owns a tile;
  *     1 = a workgroup owns a tile and its wavefronts split the tile's pairs.
+ *   FFTT_TUNE_STAGED: 1 (default) = FP32/BF16 operators first evaluate every
+ *     transducer distance of a tile into LDS when it fits (n_tx * 512 bytes
+ *     plus the tables), 0 = never.
+ *   FFTT_TUNE_UNROLL_JT_STAGED / FFTT_TUNE_UNROLL_J_STAGED: unroll of those.
  * FFTT_E_INVALID for other keys or values. */
 enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_J = 2,
-       FFTT_TUNE_SPLIT_JT = 3, FFTT_TUNE_SPLIT_J = 4 };
+       FFTT_TUNE_SPLIT_JT = 3, FFTT_TUNE_SPLIT_J = 4, FFTT_TUNE_STAGED = 5,
+       FFTT_TUNE_UNROLL_JT_STAGED = 6, FFTT_TUNE_UNROLL_J_STAGED = 7 };
 fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
 
 /* Measurement aid.  With enable != 0 every launch of the main operator

@@ -58,10 +58,12 @@ fftt_status upload_tables(fftt_ctx* c) {
     std::vector<float> t32((size_t)nb * n * 2);
     std::vector<double> t64((size_t)nb * n * 2);
     std::vector<uint32_t> tbf((size_t)nb * n);
+    std::vector<float> tnode((size_t)nb * n);
     for (int b = 0; b < nb; ++b) {
         const std::vector<double>& h = c->h[b];
         for (int k = 0; k < n; ++k) {
             const size_t i = (size_t)b * n + k;
+            tnode[i] = (float)h[k];
             if (k < n - 1) {
                 t64[2 * i] = h[k];
                 t64[2 * i + 1] = h[k + 1] - h[k];
@@ -83,6 +85,9 @@ fftt_status upload_tables(fftt_ctx* c) {
     FFTT_HIP(c, c->d_tab32.alloc(t32.size() * sizeof(float)));
     FFTT_HIP(c, c->d_tab64.alloc(t64.size() * sizeof(double)));
     FFTT_HIP(c, c->d_tabbf.alloc(tbf.size() * sizeof(uint32_t)));
+    FFTT_HIP(c, c->d_tab32n.alloc(tnode.size() * sizeof(float)));
+    FFTT_HIP(c, hipMemcpy(c->d_tab32n.p, tnode.data(), tnode.size() * sizeof(float),
+                          hipMemcpyHostToDevice));
     FFTT_HIP(c, hipMemcpy(c->d_tab32.p, t32.data(), t32.size() * sizeof(float),
                           hipMemcpyHostToDevice));
     FFTT_HIP(c, hipMemcpy(c->d_tab64.p, t64.data(), t64.size() * sizeof(double),
@@ -150,32 +155,30 @@ fftt_status build_lists(fftt_ctx* c) {
                             c->d_L.as<double>(), M, c->g, r_cut, nullptr,
                             c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>()));
 
-    // pair-major index of the entries (for the deterministic J reduction)
+    // run descriptors of 64-pair groups (for the deterministic J reduction)
     const int64_t chunk = 256;
     const int64_t n_chunks = (n_act + chunk - 1) / chunk;
+    const int64_t G = (M + 63) / 64;
     DevBuf ccnt, total;
-    FFTT_HIP(c, ccnt.alloc((size_t)std::max<int64_t>(n_chunks * M, 1) * sizeof(int32_t)));
-    FFTT_HIP(c, total.alloc((size_t)M * sizeof(int64_t)));
-    FFTT_HIP(c, hipMemsetAsync(ccnt.p, 0, (size_t)n_chunks * M * sizeof(int32_t), s));
-    FFTT_HIP(c, launch_chunk_count(s, c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(), n_act,
-                                   chunk, M, ccnt.as<int32_t>()));
-    FFTT_HIP(c, launch_chunk_scan(s, ccnt.as<int32_t>(), n_chunks, M, total.as<int64_t>()));
-    std::vector<int64_t> tot(M), pptr(M + 1, 0);
-    FFTT_HIP(c, hipMemcpyAsync(tot.data(), total.p, M * sizeof(int64_t), hipMemcpyDeviceToHost,
+    FFTT_HIP(c, ccnt.alloc((size_t)std::max<int64_t>(n_chunks * G, 1) * sizeof(int32_t)));
+    FFTT_HIP(c, total.alloc((size_t)G * sizeof(int64_t)));
+    FFTT_HIP(c, hipMemsetAsync(ccnt.p, 0, (size_t)n_chunks * G * sizeof(int32_t), s));
+    FFTT_HIP(c, launch_group_count(s, c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(), n_act,
+                                   chunk, G, ccnt.as<int32_t>()));
+    FFTT_HIP(c, launch_chunk_scan(s, ccnt.as<int32_t>(), n_chunks, G, total.as<int64_t>()));
+    std::vector<int64_t> tot(G), gptr(G + 1, 0);
+    FFTT_HIP(c, hipMemcpyAsync(tot.data(), total.p, G * sizeof(int64_t), hipMemcpyDeviceToHost,
                                s));
     FFTT_HIP(c, hipStreamSynchronize(s));
-    for (int64_t p = 0; p < M; ++p) pptr[p + 1] = pptr[p] + tot[p];
-    if (pptr[M] != nnz) {
-        c->err = "internal: transposed index size mismatch";
-        return FFTT_E_DEVICE;
-    }
-    FFTT_HIP(c, c->d_pptr.alloc((M + 1) * sizeof(int64_t)));
-    FFTT_HIP(c, hipMemcpyAsync(c->d_pptr.p, pptr.data(), (M + 1) * sizeof(int64_t),
+    for (int64_t g = 0; g < G; ++g) gptr[g + 1] = gptr[g] + tot[g];
+    c->n_desc = gptr[G];
+    FFTT_HIP(c, c->d_gptr.alloc((G + 1) * sizeof(int64_t)));
+    FFTT_HIP(c, hipMemcpyAsync(c->d_gptr.p, gptr.data(), (G + 1) * sizeof(int64_t),
                                hipMemcpyHostToDevice, s));
-    FFTT_HIP(c, c->d_pidx.alloc((size_t)std::max<int64_t>(nnz, 1) * sizeof(int64_t)));
-    FFTT_HIP(c, launch_chunk_fill(s, c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(), n_act,
-                                  chunk, M, ccnt.as<int32_t>(), c->d_pptr.as<int64_t>(),
-                                  c->d_pidx.as<int64_t>()));
+    FFTT_HIP(c, c->d_desc.alloc((size_t)std::max<int64_t>(c->n_desc, 1) * 16));
+    FFTT_HIP(c, launch_group_fill(s, c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(), n_act,
+                                  chunk, G, ccnt.as<int32_t>(), c->d_gptr.as<int64_t>(),
+                                  c->d_desc.p));
     c->nnz = nnz;
 
     // exact work count (FP64 decision R < R_max)
@@ -218,6 +221,14 @@ hipError_t prof_end(fftt_ctx* c, hipEvent_t stop) {
     return stop ? hipEventRecord(stop, c->stream) : hipSuccess;
 }
 
+// The LDS-staged FP32 kernels apply when enabled and the tables plus one
+// float2 per (transducer, lane) fit in the workgroup's LDS.
+bool use_staged(const fftt_ctx* c, fftt_precision prec) {
+    if (!c->staged || prec == FFTT_FP64) return false;
+    return staged_lds_bytes(c->nb, c->ntab, prec == FFTT_FP32_BF16TABLE, c->n_tx,
+                            c->waves_per_block) <= c->lds_limit;
+}
+
 // dT [B][M] = J dc (caller order), one right-hand side; ensure_ready done.
 fftt_status apply_J_one(fftt_ctx* c, fftt_precision prec, const void* x, void* y) {
     const bool fp64 = prec == FFTT_FP64;
@@ -231,12 +242,18 @@ fftt_status apply_J_one(fftt_ctx* c, fftt_precision prec, const void* x, void* y
     a.x = x;
     hipEvent_t stop;
     FFTT_HIP(c, prof_begin(c, 0, &stop));
-    FFTT_HIP(c, launch_apply(c->stream, prec, false, a));
+    if (use_staged(c, prec)) {
+        a.unroll = c->unroll_js;
+        if (prec == FFTT_FP32) a.tab = c->d_tab32n.p;
+        FFTT_HIP(c, launch_apply_staged(c->stream, prec == FFTT_FP32_BF16TABLE, false, a));
+    } else {
+        FFTT_HIP(c, launch_apply(c->stream, prec, false, a));
+    }
     FFTT_HIP(c, prof_end(c, stop));
     FFTT_HIP(c, prof_begin(c, 2, &stop));
-    FFTT_HIP(c, launch_reduce(c->stream, fp64, c->d_part.p, c->nnz, c->d_pptr.as<int64_t>(),
-                              c->d_pidx.as<int64_t>(), c->d_C.as<double>(),
-                              c->d_porig.as<int32_t>(), c->M, c->nb, y));
+    FFTT_HIP(c, launch_reduce(c->stream, fp64, c->d_part.p, c->nnz, c->d_gptr.as<int64_t>(),
+                              c->d_desc.p, c->d_C.as<double>(), c->d_porig.as<int32_t>(), c->M,
+                              c->nb, y));
     FFTT_HIP(c, prof_end(c, stop));
     return FFTT_OK;
 }
@@ -255,7 +272,13 @@ fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* 
     FFTT_HIP(c, launch_fill(c->stream, fp64, x, c->N));
     hipEvent_t stop;
     FFTT_HIP(c, prof_begin(c, 1, &stop));
-    FFTT_HIP(c, launch_apply(c->stream, prec, true, a));
+    if (use_staged(c, prec)) {
+        a.unroll = c->unroll_jts;
+        if (prec == FFTT_FP32) a.tab = c->d_tab32n.p;
+        FFTT_HIP(c, launch_apply_staged(c->stream, prec == FFTT_FP32_BF16TABLE, true, a));
+    } else {
+        FFTT_HIP(c, launch_apply(c->stream, prec, true, a));
+    }
     FFTT_HIP(c, prof_end(c, stop));
     return FFTT_OK;
 }
@@ -301,6 +324,7 @@ fftt_status fftt_create(fftt_ctx** out, int device, void* hip_stream) {
         return FFTT_E_DEVICE;
     }
     c->n_cu = prop.multiProcessorCount;
+    c->lds_limit = prop.sharedMemPerBlock;
     *out = c;
     return FFTT_OK;
 }
@@ -535,6 +559,15 @@ fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
         case FFTT_TUNE_UNROLL_J:
             if (value != 1 && value != 2 && value != 4) FFTT_BAD(c, "unroll must be 1, 2 or 4");
             (key == FFTT_TUNE_UNROLL_J ? c->unroll_j : c->unroll_jt) = value;
+            return FFTT_OK;
+        case FFTT_TUNE_STAGED:
+            if (value != 0 && value != 1) FFTT_BAD(c, "staged must be 0 or 1");
+            c->staged = value;
+            return FFTT_OK;
+        case FFTT_TUNE_UNROLL_JT_STAGED:
+        case FFTT_TUNE_UNROLL_J_STAGED:
+            if (value != 1 && value != 2 && value != 4) FFTT_BAD(c, "unroll must be 1, 2 or 4");
+            (key == FFTT_TUNE_UNROLL_J_STAGED ? c->unroll_js : c->unroll_jts) = value;
             return FFTT_OK;
         case FFTT_TUNE_SPLIT_JT:
         case FFTT_TUNE_SPLIT_J:

@@ -99,13 +99,13 @@ hipError_t launch_cull(hipStream_t s, bool fill, const int32_t* tiles, int64_t n
                        const TxConst* txc, int64_t n_tx, const int32_t* ps, const int32_t* pr,
                        const double* L, int64_t M, const GridGeom& g, double r_cut,
                        int64_t* counts, const int64_t* tptr, Entry* ents);
-hipError_t launch_chunk_count(hipStream_t s, const int64_t* tptr, const Entry* ents,
-                              int64_t n_act, int64_t chunk, int64_t M, int32_t* cnt);
-hipError_t launch_chunk_scan(hipStream_t s, int32_t* cnt, int64_t n_chunks, int64_t M,
+hipError_t launch_chunk_scan(hipStream_t s, int32_t* cnt, int64_t n_chunks, int64_t K,
                              int64_t* total);
-hipError_t launch_chunk_fill(hipStream_t s, const int64_t* tptr, const Entry* ents,
-                             int64_t n_act, int64_t chunk, int64_t M, int32_t* cnt,
-                             const int64_t* pptr, int64_t* pidx);
+hipError_t launch_group_count(hipStream_t s, const int64_t* tptr, const Entry* ents,
+                              int64_t n_act, int64_t chunk, int64_t G, int32_t* cnt);
+hipError_t launch_group_fill(hipStream_t s, const int64_t* tptr, const Entry* ents,
+                             int64_t n_act, int64_t chunk, int64_t G, int32_t* cnt,
+                             const int64_t* gptr, void* desc);
 hipError_t launch_count_pv(hipStream_t s, const ApplyArgs& a, double r_max_all,
                            const double* L, const int32_t* ps, const int32_t* pr,
                            const double* tx, unsigned long long* pv,
@@ -115,8 +115,10 @@ hipError_t launch_weights(hipStream_t s, bool fp64, const void* dT, const int32_
 hipError_t launch_fill(hipStream_t s, bool fp64, void* p, int64_t n);
 hipError_t launch_apply(hipStream_t s, fftt_precision prec, bool transpose,
                         const ApplyArgs& a);
+hipError_t launch_apply_staged(hipStream_t s, bool bf16, bool transpose, const ApplyArgs& a);
+size_t staged_lds_bytes(int nb, int ntab, bool bf16, int64_t n_tx, int wpb);
 hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz,
-                         const int64_t* pptr, const int64_t* pidx, const double* C,
+                         const int64_t* gptr, const void* desc, const double* C,
                          const int32_t* porig, int64_t M, int nb, void* dT);
 
 // ---- solver building blocks (solve.hip) ----
@@ -165,14 +167,15 @@ struct fftt_ctx {
     std::vector<double> r_max;
     std::vector<bool> band_set;
     bool tab_dirty = true;
-    fftt::DevBuf d_tab32, d_tab64, d_tabbf;
+    fftt::DevBuf d_tab32, d_tab64, d_tabbf, d_tab32n;
 
     // culling lists
     bool lists_ok = false;
     double lists_rcut = 0;
     int64_t nnz = 0;
     int64_t pv = 0, lanes = 0;
-    fftt::DevBuf d_txc, d_tptr, d_ents, d_pptr, d_pidx;
+    fftt::DevBuf d_txc, d_tptr, d_ents, d_gptr, d_desc;
+    int64_t n_desc = 0;
 
     // launch shape of the operator kernels
     int waves_per_block = 16;
@@ -180,6 +183,9 @@ struct fftt_ctx {
     int unroll_jt = 2;
     int unroll_j = 4;
     int split_jt = 0, split_j = 1;
+    int staged = 1;            // use the LDS-staged kernels when they fit
+    int unroll_jts = 4, unroll_js = 4;
+    size_t lds_limit = 65536;
 
     // work buffers
     fftt::DevBuf d_w, d_part, d_solve, d_scal;

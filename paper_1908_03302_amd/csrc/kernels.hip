@@ -253,76 +253,29 @@ hipError_t launch_cull(hipStream_t s, bool fill, const int32_t* tiles, int64_t n
     return hipGetLastError();
 }
 
-// ------------------------------------------- pair-major (transposed) index
+// ------------------------------------------------ per-chunk count scan
 //
-// Positions of each pair's entries, in increasing entry (= tile) order, built
-// deterministically: tiles are grouped in chunks; a chunk counts its entries
-// per pair, the counts are scanned across chunks per pair, and each chunk
-// then hands out slots tile by tile (a pair occurs at most once per tile).
+// Deterministic compaction used by the reduction index: tiles are grouped in
+// chunks, each chunk counts per key, counts are scanned across chunks per key
+// (exclusive, in place) and the chunks later hand out slots tile by tile.
 
-__global__ void k_chunk_count(const int64_t* __restrict__ tptr, const Entry* __restrict__ ents,
-                              int64_t n_act, int64_t chunk, int64_t M, int32_t* __restrict__ cnt) {
-    const int64_t c = blockIdx.x;
-    const int64_t a0 = c * chunk;
-    const int64_t a1 = min(n_act, a0 + chunk);
-    int32_t* row = cnt + c * M;
-    for (int64_t e = tptr[a0] + threadIdx.x; e < tptr[a1]; e += blockDim.x)
-        atomicAdd(&row[ents[e].p], 1);
-}
-
-__global__ void k_chunk_scan(int32_t* __restrict__ cnt, int64_t n_chunks, int64_t M,
+__global__ void k_chunk_scan(int32_t* __restrict__ cnt, int64_t n_chunks, int64_t K,
                              int64_t* __restrict__ total) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= M) return;
+    if (p >= K) return;
     int64_t run = 0;
     for (int64_t c = 0; c < n_chunks; ++c) {
-        const int32_t v = cnt[c * M + p];
-        cnt[c * M + p] = (int32_t)run;
+        const int32_t v = cnt[c * K + p];
+        cnt[c * K + p] = (int32_t)run;
         run += v;
     }
     total[p] = run;
 }
 
-__global__ void k_chunk_fill(const int64_t* __restrict__ tptr, const Entry* __restrict__ ents,
-                             int64_t n_act, int64_t chunk, int64_t M, int32_t* __restrict__ cnt,
-                             const int64_t* __restrict__ pptr, int64_t* __restrict__ pidx) {
-    const int64_t c = blockIdx.x;
-    const int64_t a0 = c * chunk;
-    const int64_t a1 = min(n_act, a0 + chunk);
-    int32_t* row = cnt + c * M;
-    for (int64_t a = a0; a < a1; ++a) {
-        for (int64_t e = tptr[a] + threadIdx.x; e < tptr[a + 1]; e += blockDim.x) {
-            const int p = ents[e].p;
-            const int32_t slot = atomicAdd(&row[p], 1);
-            pidx[pptr[p] + slot] = e;
-        }
-        __syncthreads();
-    }
-}
-
-hipError_t launch_chunk_count(hipStream_t s, const int64_t* tptr, const Entry* ents,
-                              int64_t n_act, int64_t chunk, int64_t M, int32_t* cnt) {
-    const int64_t nc = (n_act + chunk - 1) / chunk;
-    if (nc == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)nc), dim3(256), 0, s, tptr, ents, n_act,
-                       chunk, M, cnt);
-    return hipGetLastError();
-}
-
-hipError_t launch_chunk_scan(hipStream_t s, int32_t* cnt, int64_t n_chunks, int64_t M,
+hipError_t launch_chunk_scan(hipStream_t s, int32_t* cnt, int64_t n_chunks, int64_t K,
                              int64_t* total) {
-    hipLaunchKernelGGL(k_chunk_scan, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, cnt,
-                       n_chunks, M, total);
-    return hipGetLastError();
-}
-
-hipError_t launch_chunk_fill(hipStream_t s, const int64_t* tptr, const Entry* ents,
-                             int64_t n_act, int64_t chunk, int64_t M, int32_t* cnt,
-                             const int64_t* pptr, int64_t* pidx) {
-    const int64_t nc = (n_act + chunk - 1) / chunk;
-    if (nc == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chunk_fill, dim3((unsigned)nc), dim3(256), 0, s, tptr, ents, n_act,
-                       chunk, M, cnt, pptr, pidx);
+    hipLaunchKernelGGL(k_chunk_scan, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, cnt,
+                       n_chunks, K, total);
     return hipGetLastError();
 }
 
@@ -468,6 +421,19 @@ __device__ __forceinline__ float lookup(const uint32_t* tab, float R, float inv_
     const float f = x - (float)k;
     const uint32_t e = tab[k];
     return fmaf(f, __uint_as_float(e & 0xffff0000u), __uint_as_float(e << 16));
+}
+
+// FP32 node table h_0..h_{n-1}, h_n = 0 (one float per node, half the LDS of
+// the (h, slope) layout): both nodes come from one ds_read2; the truncation
+// to zero for R >= r_max is an explicit select.
+__device__ __forceinline__ float lookup(const float* tab, float R, float inv_dr, float nm1) {
+    const float x = __builtin_amdgcn_fmed3f(R * inv_dr, 0.0f, nm1);
+    const int k = (int)x;
+    const float f = x - (float)k;
+    const float h0 = tab[k], h1 = tab[k + 1];
+    // mask multiply rather than a select, so the read is never predicated
+    const float keep = x < nm1 ? 1.0f : 0.0f;
+    return fmaf(f, h1 - h0, h0) * keep;
 }
 
 __device__ __forceinline__ double lookup(const double2* tab, double R, double inv_dr, double nm1) {
@@ -838,40 +804,410 @@ hipError_t launch_apply(hipStream_t s, fftt_precision prec, bool transpose, cons
     return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------ staged (separable) kernels
+//
+// A workgroup owns one tile.  First its wavefronts evaluate, for every lane
+// (voxel) and every transducer q, delta_q = R_xq - D0f_q and 1/R_xq once and
+// keep them in LDS ([q][lane] float2).  A pair (s, r) then needs only two LDS
+// reads: R = R0 + delta_s + delta_r, A ~ (1/R_xs)(1/R_xr).  The tile's pair
+// list is split over the wavefronts in contiguous ranges of multiples of U.
+// Used when the tables plus n_tx * 512 bytes fit in LDS.
+
+template <class TabT>
+__device__ __forceinline__ float2* staged_tx(const ApplyArgs& A, int nb) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    return reinterpret_cast<float2*>(smem + (((size_t)nb * A.ntab * sizeof(TabT) + 15) & ~(size_t)15));
+}
+
+__device__ __forceinline__ void stage_distances(const ApplyArgs& A, int64_t a, const LaneVox& V,
+                                                float2* sx, int lane) {
+    const TxConst* __restrict__ row = A.txc + a * A.n_tx;
+    const int W = (int)(blockDim.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int q = wave; q < (int)A.n_tx; q += W) {
+        float d, rs;
+        dist32(row[q], V.ux, V.uy, V.uz, V.uu, d, rs);
+        sx[q * 64 + lane] = make_float2(d, rs);
+    }
+    __syncthreads();
+}
+
+// Entries of one step, loaded as whole 16-byte records (one scalar batch).
+template <int U>
+struct StepEntries {
+    int p[U];
+    int s[U];
+    int r[U];
+    float R0[U];
+};
+
+template <int U>
+__device__ __forceinline__ StepEntries<U> load_entries(const Entry* __restrict__ ents, int64_t e) {
+    StepEntries<U> E;
+    const uint4* __restrict__ raw = reinterpret_cast<const uint4*>(ents + e);
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = raw[u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        E.p[u] = (int)v[u].x;
+        E.s[u] = (int)(v[u].y & 0xffffu);
+        E.r[u] = (int)(v[u].y >> 16);
+        E.R0[u] = __uint_as_float(v[u].z);
+    }
+    return E;
+}
+
+// Source distances of a step from the LDS stage.  Entries are sorted by
+// source, so usually all U share the current one (no LDS read); otherwise
+// every entry's source is read, in one batch.
+template <int U>
+struct StepSources {
+    float d[U];
+    float rs[U];
+};
+
+template <int U>
+__device__ __forceinline__ StepSources<U> staged_sources(const StepEntries<U>& E,
+                                                         const float2* sx, int lane, int& prev,
+                                                         float& cd, float& crs) {
+    StepSources<U> S;
+    bool same = true;
+#pragma unroll
+    for (int u = 0; u < U; ++u) same = same && (E.s[u] == prev);
+    if (same) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            S.d[u] = cd;
+            S.rs[u] = crs;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float2 v = sx[E.s[u] * 64 + lane];
+            S.d[u] = v.x;
+            S.rs[u] = v.y;
+        }
+        prev = E.s[U - 1];
+        cd = S.d[U - 1];
+        crs = S.rs[U - 1];
+    }
+    return S;
+}
+
+template <int NB, class TabT, int U>
+__device__ __forceinline__ void jt32s_step(const ApplyArgs& A, const TabT* st, const float2* sx,
+                                           const Entry* __restrict__ ents,
+                                           const float* __restrict__ w, float nm1, int lane,
+                                           int64_t e, int& prev, float& cd, float& crs,
+                                           float& acc) {
+    const StepEntries<U> E = load_entries<U>(ents, e);
+    float wu[U][NB];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) wu[u][b] = w[b * A.M + E.p[u]];
+    const StepSources<U> S = staged_sources<U>(E, sx, lane, prev, cd, crs);
+    float rd[U], rr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const float2 v = sx[E.r[u] * 64 + lane];
+        rd[u] = v.x;
+        rr[u] = v.y;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const float R = (S.d[u] + rd[u]) + E.R0[u];
+        float hw = 0.f;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            hw = fmaf(lookup(st + b * A.ntab, R, A.inv_dr[b], nm1), wu[u][b], hw);
+        acc = fmaf(hw, S.rs[u] * rr[u], acc);
+    }
+}
+
+template <int NB, class TabT, int U>
+__global__ __launch_bounds__(1024) void k_jt32s(ApplyArgs A) {
+    const TabT* st = stage_table<TabT>(A, NB);
+    float2* sx = staged_tx<TabT>(A, NB);
+    const int64_t a = blockIdx.x;
+    if (a >= A.n_act) return;
+    const int lane = threadIdx.x & 63;
+    const LaneVox V = lane_vox(A, a, lane);
+    stage_distances(A, a, V, sx, lane);
+    int64_t e0, e1;
+    {
+        const int W = (int)(blockDim.x >> 6);
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
+        int64_t chunk = (t1 - t0 + W - 1) / W;
+        chunk = (chunk + U - 1) / U * U;
+        e0 = min(t1, t0 + (int64_t)wave * chunk);
+        e1 = min(t1, e0 + chunk);
+    }
+    const float* __restrict__ w = static_cast<const float*>(A.w);
+    const float nm1 = (float)(A.ntab - 1);
+    float acc = 0.f, cd = 0.f, crs = 0.f;
+    int prev = -1;
+    int64_t e = e0;
+    for (; e + U <= e1; e += U)
+        jt32s_step<NB, TabT, U>(A, st, sx, A.ents, w, nm1, lane, e, prev, cd, crs, acc);
+    for (; e < e1; ++e)
+        jt32s_step<NB, TabT, 1>(A, st, sx, A.ents, w, nm1, lane, e, prev, cd, crs, acc);
+    // combine the wavefronts in order (the staged distances are no longer needed)
+    __syncthreads();
+    float* s_acc = reinterpret_cast<float*>(sx);
+    const int wave = (int)(threadIdx.x >> 6);
+    s_acc[wave * 64 + lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    const int W = (int)(blockDim.x >> 6);
+    float t = s_acc[lane];
+    for (int k = 1; k < W; ++k) t += s_acc[k * 64 + lane];
+    if (V.inside) static_cast<float*>(A.out)[V.vidx] = V.act ? t : 0.f;
+}
+
+template <int NB, class TabT, int U>
+__device__ __forceinline__ void j32s_step(const ApplyArgs& A, const TabT* st, const float2* sx,
+                                          const Entry* __restrict__ ents, float* __restrict__ part,
+                                          float xv, float nm1, int lane, int64_t e, int& prev,
+                                          float& cd, float& crs) {
+    const StepEntries<U> E = load_entries<U>(ents, e);
+    const StepSources<U> S = staged_sources<U>(E, sx, lane, prev, cd, crs);
+    float R[U], t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const float2 v = sx[E.r[u] * 64 + lane];
+        R[u] = (S.d[u] + v.x) + E.R0[u];
+        t[u] = (S.rs[u] * xv) * v.y;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = lookup(st + b * A.ntab, R[u], A.inv_dr[b], nm1) * t[u];
+        const float sum = multi_sum<U>(v, lane);
+        if (lane < U) part[b * A.nnz + e + lane] = sum;
+    }
+}
+
+template <int NB, class TabT, int U>
+__global__ __launch_bounds__(1024) void k_j32s(ApplyArgs A) {
+    const TabT* st = stage_table<TabT>(A, NB);
+    float2* sx = staged_tx<TabT>(A, NB);
+    const int64_t a = blockIdx.x;
+    if (a >= A.n_act) return;
+    const int lane = threadIdx.x & 63;
+    const LaneVox V = lane_vox(A, a, lane);
+    stage_distances(A, a, V, sx, lane);
+    int64_t e0, e1;
+    {
+        const int W = (int)(blockDim.x >> 6);
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
+        int64_t chunk = (t1 - t0 + W - 1) / W;
+        chunk = (chunk + U - 1) / U * U;
+        e0 = min(t1, t0 + (int64_t)wave * chunk);
+        e1 = min(t1, e0 + chunk);
+    }
+    float* __restrict__ part = static_cast<float*>(A.out);
+    const float xv = V.act ? static_cast<const float*>(A.x)[V.vidx] : 0.f;
+    const float nm1 = (float)(A.ntab - 1);
+    float cd = 0.f, crs = 0.f;
+    int prev = -1;
+    int64_t e = e0;
+    for (; e + U <= e1; e += U)
+        j32s_step<NB, TabT, U>(A, st, sx, A.ents, part, xv, nm1, lane, e, prev, cd, crs);
+    for (; e < e1; ++e)
+        j32s_step<NB, TabT, 1>(A, st, sx, A.ents, part, xv, nm1, lane, e, prev, cd, crs);
+}
+
+template <class K>
+static hipError_t launch_staged(K kern, hipStream_t s, const ApplyArgs& a, size_t table_bytes) {
+    if (a.n_act == 0) return hipSuccess;
+    const int wpb = a.waves_per_block;
+    const size_t tx_bytes = std::max<size_t>((size_t)a.n_tx * 64 * sizeof(float2),
+                                             (size_t)wpb * 64 * sizeof(float));
+    const size_t lds = ((table_bytes + 15) & ~(size_t)15) + tx_bytes;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)a.n_act), dim3(64 * wpb), lds, s, a);
+    return hipGetLastError();
+}
+
+size_t staged_lds_bytes(int nb, int ntab, bool bf16, int64_t n_tx, int wpb) {
+    const size_t tab = (size_t)nb * ntab * (bf16 ? sizeof(uint32_t) : sizeof(float));
+    return ((tab + 15) & ~(size_t)15) +
+           std::max<size_t>((size_t)n_tx * 64 * sizeof(float2), (size_t)wpb * 64 * sizeof(float));
+}
+
+template <int NB, int U>
+static hipError_t launch_staged_nbu(hipStream_t s, bool bf16, bool transpose, const ApplyArgs& a) {
+    const size_t n = (size_t)NB * a.ntab;
+    if (bf16)
+        return transpose ? launch_staged(k_jt32s<NB, uint32_t, U>, s, a, n * sizeof(uint32_t))
+                         : launch_staged(k_j32s<NB, uint32_t, U>, s, a, n * sizeof(uint32_t));
+    return transpose ? launch_staged(k_jt32s<NB, float, U>, s, a, n * sizeof(float))
+                     : launch_staged(k_j32s<NB, float, U>, s, a, n * sizeof(float));
+}
+
+template <int NB>
+static hipError_t launch_staged_nb(hipStream_t s, bool bf16, bool transpose, const ApplyArgs& a) {
+    switch (a.unroll) {
+        case 1: return launch_staged_nbu<NB, 1>(s, bf16, transpose, a);
+        case 2: return launch_staged_nbu<NB, 2>(s, bf16, transpose, a);
+        case 4: return launch_staged_nbu<NB, 4>(s, bf16, transpose, a);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_apply_staged(hipStream_t s, bool bf16, bool transpose, const ApplyArgs& a) {
+    switch (a.nb) {
+        case 1: return launch_staged_nb<1>(s, bf16, transpose, a);
+        case 2: return launch_staged_nb<2>(s, bf16, transpose, a);
+        case 3: return launch_staged_nb<3>(s, bf16, transpose, a);
+        case 4: return launch_staged_nb<4>(s, bf16, transpose, a);
+    }
+    return hipErrorInvalidValue;
+}
+
 // ------------------------------------------------------------ J reduction
 //
-// dT^b[porig[p]] = C_p * sum over the pair's partials, one wavefront per pair,
-// FP64 accumulation in a fixed order.
+// Pairs are grouped by 64 consecutive (internal) indices.  A tile's entry
+// list is sorted by pair, so a group's entries in one tile form a single
+// contiguous run; the pre-pass records, per group and in tile order, a
+// descriptor (first entry of the run, 64-bit mask of the group's pairs
+// present).  Lane i of the group's workgroup owns pair 64 g + i and reads its
+// partial at run start + popcount(mask below bit i): coalesced reads, FP64
+// sums in tile order, wavefronts combined in a fixed order.
+
+struct RunDesc {
+    int64_t start;
+    uint64_t mask;
+};
+
+__global__ void k_group_count(const int64_t* __restrict__ tptr, const Entry* __restrict__ ents,
+                              int64_t n_act, int64_t chunk, int64_t G, int32_t* __restrict__ cnt) {
+    const int64_t c = blockIdx.x;
+    const int64_t a0 = c * chunk;
+    const int64_t a1 = min(n_act, a0 + chunk);
+    int32_t* row = cnt + c * G;
+    for (int64_t a = a0; a < a1; ++a) {
+        const int64_t e0 = tptr[a], e1 = tptr[a + 1];
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            const int g = ents[e].p >> 6;
+            if (e == e0 || (ents[e - 1].p >> 6) != g) atomicAdd(&row[g], 1);
+        }
+    }
+}
+
+__global__ void k_group_fill(const int64_t* __restrict__ tptr, const Entry* __restrict__ ents,
+                             int64_t n_act, int64_t chunk, int64_t G, int32_t* __restrict__ cnt,
+                             const int64_t* __restrict__ gptr, RunDesc* __restrict__ desc) {
+    const int64_t c = blockIdx.x;
+    const int64_t a0 = c * chunk;
+    const int64_t a1 = min(n_act, a0 + chunk);
+    int32_t* row = cnt + c * G;
+    for (int64_t a = a0; a < a1; ++a) {
+        const int64_t e0 = tptr[a], e1 = tptr[a + 1];
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            const int g = ents[e].p >> 6;
+            if (e != e0 && (ents[e - 1].p >> 6) == g) continue;
+            uint64_t mask = 0;
+            for (int64_t k = e; k < e1 && (ents[k].p >> 6) == g; ++k)
+                mask |= 1ull << (ents[k].p & 63);
+            const int32_t slot = atomicAdd(&row[g], 1);
+            RunDesc d;
+            d.start = e;
+            d.mask = mask;
+            desc[gptr[g] + slot] = d;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_group_count(hipStream_t s, const int64_t* tptr, const Entry* ents,
+                              int64_t n_act, int64_t chunk, int64_t G, int32_t* cnt) {
+    const int64_t nc = (n_act + chunk - 1) / chunk;
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_group_count, dim3((unsigned)nc), dim3(256), 0, s, tptr, ents, n_act,
+                       chunk, G, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_fill(hipStream_t s, const int64_t* tptr, const Entry* ents,
+                             int64_t n_act, int64_t chunk, int64_t G, int32_t* cnt,
+                             const int64_t* gptr, void* desc) {
+    const int64_t nc = (n_act + chunk - 1) / chunk;
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_group_fill, dim3((unsigned)nc), dim3(256), 0, s, tptr, ents, n_act,
+                       chunk, G, cnt, gptr, static_cast<RunDesc*>(desc));
+    return hipGetLastError();
+}
+
+constexpr int kReduceWaves = 16;
 
 template <class T>
-__global__ __launch_bounds__(1024) void k_reduce(const T* __restrict__ part, int64_t nnz,
-                                                const int64_t* __restrict__ pptr,
-                                                const int64_t* __restrict__ pidx,
-                                                const double* __restrict__ C,
-                                                const int32_t* __restrict__ porig, int64_t M,
-                                                int nb, T* __restrict__ dT) {
-    const int64_t p = wave_tile();
+__global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
+    const T* __restrict__ part, int64_t nnz, const int64_t* __restrict__ gptr,
+    const RunDesc* __restrict__ desc, const double* __restrict__ C,
+    const int32_t* __restrict__ porig, int64_t M, int nb, T* __restrict__ dT) {
+    __shared__ double s_acc[kReduceWaves][64];
+    const int64_t g = blockIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    if (p >= M) return;
-    const int64_t k0 = pptr[p], k1 = pptr[p + 1];
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t d0 = gptr[g], d1 = gptr[g + 1];
+    const int64_t chunk = (d1 - d0 + kReduceWaves - 1) / kReduceWaves;
+    const int64_t k0 = min(d1, d0 + wave * chunk), k1 = min(d1, k0 + chunk);
+    const int64_t p = 64 * g + lane;
     for (int b = 0; b < nb; ++b) {
+        const T* __restrict__ pb = part + (int64_t)b * nnz;
         double acc = 0.0;
-        for (int64_t k = k0 + lane; k < k1; k += 64) acc += (double)part[b * nnz + pidx[k]];
-        acc = wave_sum(acc);
-        if (lane == 0) dT[b * M + porig[p]] = (T)(C[p] * acc);
+        int64_t k = k0;
+        // 8 descriptors per step: their gathers are issued together (the
+        // index is always valid, absent pairs add zero), summed in order
+        for (; k + 8 <= k1; k += 8) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const RunDesc d = desc[k + u];
+                const bool on = (d.mask >> lane) & 1ull;
+                const T x = pb[d.start + (on ? __popcll(d.mask & below) : 0)];
+                v[u] = on ? x : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += (double)v[u];
+        }
+        for (; k < k1; ++k) {
+            const RunDesc d = desc[k];
+            if ((d.mask >> lane) & 1ull) acc += (double)pb[d.start + __popcll(d.mask & below)];
+        }
+        s_acc[wave][lane] = acc;
+        __syncthreads();
+        if (wave == 0) {
+            double t = s_acc[0][lane];
+            for (int w = 1; w < kReduceWaves; ++w) t += s_acc[w][lane];
+            if (p < M) dT[(int64_t)b * M + porig[p]] = (T)(C[p] * t);
+        }
+        __syncthreads();
     }
 }
 
 hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz,
-                         const int64_t* pptr, const int64_t* pidx, const double* C,
+                         const int64_t* gptr, const void* desc, const double* C,
                          const int32_t* porig, int64_t M, int nb, void* dT) {
-    const unsigned nblk = (unsigned)((M + 15) / 16);
+    const int64_t G = (M + 63) / 64;
+    const RunDesc* d = static_cast<const RunDesc*>(desc);
     if (fp64)
-        hipLaunchKernelGGL(k_reduce<double>, dim3(nblk), dim3(64 * 16), 0, s,
-                           (const double*)part, nnz, pptr, pidx, C, porig, M, nb, (double*)dT);
+        hipLaunchKernelGGL(k_reduce<double>, dim3((unsigned)G), dim3(64 * kReduceWaves), 0, s,
+                           (const double*)part, nnz, gptr, d, C, porig, M, nb, (double*)dT);
     else
-        hipLaunchKernelGGL(k_reduce<float>, dim3(nblk), dim3(64 * 16), 0, s,
-                           (const float*)part, nnz, pptr, pidx, C, porig, M, nb, (float*)dT);
+        hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)G), dim3(64 * kReduceWaves), 0, s,
+                           (const float*)part, nnz, gptr, d, C, porig, M, nb, (float*)dT);
     return hipGetLastError();
 }
 
