@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--waves-per-block", type=int, default=None)
     ap.add_argument("--unroll-jt", type=int, default=None)
     ap.add_argument("--unroll-j", type=int, default=None)
+    ap.add_argument("--staged", type=int, default=None, choices=(0, 1),
+                    help="1: per-tile LDS-staged kernels (default), 0: per-wavefront kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the operators are not sharded); "
@@ -94,7 +96,8 @@ def main():
     w = I.ring2d()
     log("bench: workload", w.name, "M", w.m, "N", w.n)
     ctx = fftt.context_for_workload(w, device=0)
-    ctx.set_tuning(args.waves_per_block, args.unroll_jt, args.unroll_j)
+    ctx.set_tuning(args.waves_per_block, args.unroll_jt, args.unroll_j, staged=args.staged)
+    staged = args.staged is None or args.staged == 1
     t0 = time.perf_counter()
     ctx.prepare()
     pv, lanes = ctx.work_count()
@@ -136,7 +139,9 @@ def main():
     ms_step = ms / args.steps
     value = 2.0 * pv * args.steps / (ms * 1e-3)
     avg_j, avg_jt = ms_j / n_j, ms_jt / n_jt
-    dom, avg = ("J^T kernel (k_jt32)", avg_jt) if avg_jt >= avg_j else ("J kernel (k_j32)", avg_j)
+    sfx = "s" if staged else ""
+    dom, avg = (("J^T kernel (k_jt32%s)" % sfx, avg_jt) if avg_jt >= avg_j
+                else ("J kernel (k_j32%s)" % sfx, avg_j))
     achieved = pv * FLOPS_PER_PV / (avg * 1e-3) / 1e12
     log("bench: %.3f ms/step, J %.3f ms, J^T %.3f ms, reduce %.3f ms"
         % (ms_step, avg_j, avg_jt, ms_red / max(n_red, 1)))
