@@ -174,11 +174,16 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *   FFTT_TUNE_STAGED: 1 (default) = FP32/BF16 operators first evaluate every
  *     transducer distance of a tile into LDS when it fits (n_tx * 512 bytes
  *     plus the tables), 0 = never.
- *   FFTT_TUNE_UNROLL_JT_STAGED / FFTT_TUNE_UNROLL_J_STAGED: unroll of those.
+ *   FFTT_TUNE_UNROLL_JT_STAGED / FFTT_TUNE_UNROLL_J_STAGED: unroll of those:
+ *     1, 2, 4 or 8.
+ *   FFTT_TUNE_STAGED_TABLE: table layout of the staged FP32 kernels:
+ *     0 (default) = one float per node (4 bytes), 1 = (h_k, h_{k+1} - h_k)
+ *     pairs (8 bytes per node, fewer instructions, more LDS).
  * FFTT_E_INVALID for other keys or values. */
 enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_J = 2,
        FFTT_TUNE_SPLIT_JT = 3, FFTT_TUNE_SPLIT_J = 4, FFTT_TUNE_STAGED = 5,
-       FFTT_TUNE_UNROLL_JT_STAGED = 6, FFTT_TUNE_UNROLL_J_STAGED = 7 };
+       FFTT_TUNE_UNROLL_JT_STAGED = 6, FFTT_TUNE_UNROLL_J_STAGED = 7,
+       FFTT_TUNE_STAGED_TABLE = 8 };
 fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
 
 /* Measurement aid.  With enable != 0 every launch of the main operator

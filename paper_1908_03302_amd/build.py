@@ -3,8 +3,8 @@
     python -m paper_1908_03302_amd.build
 
 Every HIP source is compiled with packed-FP32 VALU instructions disabled
-(see the design doc); objects go to ``_build/`` and the shared library next to
-this file.
+(v_pk_*_f32 are never generated); objects go to ``_build/`` and the shared
+library next to this file.
 """
 from __future__ import annotations
 

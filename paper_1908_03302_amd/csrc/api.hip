@@ -118,6 +118,7 @@ ApplyArgs base_args(const fftt_ctx* c) {
     for (int b = 0; b < c->nb; ++b) {
         a.inv_dr64[b] = (double)(c->ntab - 1) / c->r_max[b];
         a.inv_dr[b] = (float)a.inv_dr64[b];
+        a.xr[b] = (float)(a.inv_dr64[b] / a.inv_dr64[0]);
     }
     return a;
 }
@@ -149,7 +150,10 @@ fftt_status build_lists(fftt_ctx* c) {
     FFTT_HIP(c, c->d_tptr.alloc((n_act + 1) * sizeof(int64_t)));
     FFTT_HIP(c, hipMemcpyAsync(c->d_tptr.p, tptr.data(), (n_act + 1) * sizeof(int64_t),
                                hipMemcpyHostToDevice, s));
-    FFTT_HIP(c, c->d_ents.alloc((size_t)std::max<int64_t>(nnz, 1) * sizeof(Entry)));
+    // kEntryPad zeroed entries past the end (pair 0, transducer 0): the
+    // operator kernels read one step ahead of the entry they evaluate
+    FFTT_HIP(c, c->d_ents.alloc((size_t)(nnz + kEntryPad) * sizeof(Entry)));
+    FFTT_HIP(c, hipMemsetAsync(c->d_ents.as<Entry>() + nnz, 0, kEntryPad * sizeof(Entry), s));
     FFTT_HIP(c, launch_cull(s, true, c->d_tiles.as<int32_t>(), n_act, c->d_txc.as<TxConst>(),
                             n_tx, c->d_ps.as<int32_t>(), c->d_pr.as<int32_t>(),
                             c->d_L.as<double>(), M, c->g, r_cut, nullptr,
@@ -221,12 +225,27 @@ hipError_t prof_end(fftt_ctx* c, hipEvent_t stop) {
     return stop ? hipEventRecord(stop, c->stream) : hipSuccess;
 }
 
+// Table format of the LDS-staged kernels for an FP32 / BF16-table apply.
+int staged_table(const fftt_ctx* c, fftt_precision prec) {
+    if (prec == FFTT_FP32_BF16TABLE) return STAB_BF16;
+    return c->staged_pair_table ? STAB_PAIR32 : STAB_NODE32;
+}
+
 // The LDS-staged FP32 kernels apply when enabled and the tables plus one
 // float2 per (transducer, lane) fit in the workgroup's LDS.
 bool use_staged(const fftt_ctx* c, fftt_precision prec) {
     if (!c->staged || prec == FFTT_FP64) return false;
-    return staged_lds_bytes(c->nb, c->ntab, prec == FFTT_FP32_BF16TABLE, c->n_tx,
+    return staged_lds_bytes(c->nb, c->ntab, staged_table(c, prec), c->n_tx,
                             c->waves_per_block) <= c->lds_limit;
+}
+
+// Device table of a staged launch.
+const void* staged_table_ptr(const fftt_ctx* c, int fmt) {
+    switch (fmt) {
+        case STAB_NODE32: return c->d_tab32n.p;
+        case STAB_PAIR32: return c->d_tab32.p;
+        default: return c->d_tabbf.p;
+    }
 }
 
 // dT [B][M] = J dc (caller order), one right-hand side; ensure_ready done.
@@ -244,8 +263,9 @@ fftt_status apply_J_one(fftt_ctx* c, fftt_precision prec, const void* x, void* y
     FFTT_HIP(c, prof_begin(c, 0, &stop));
     if (use_staged(c, prec)) {
         a.unroll = c->unroll_js;
-        if (prec == FFTT_FP32) a.tab = c->d_tab32n.p;
-        FFTT_HIP(c, launch_apply_staged(c->stream, prec == FFTT_FP32_BF16TABLE, false, a));
+        const int fmt = staged_table(c, prec);
+        a.tab = staged_table_ptr(c, fmt);
+        FFTT_HIP(c, launch_apply_staged(c->stream, fmt, false, a));
     } else {
         FFTT_HIP(c, launch_apply(c->stream, prec, false, a));
     }
@@ -274,8 +294,9 @@ fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* 
     FFTT_HIP(c, prof_begin(c, 1, &stop));
     if (use_staged(c, prec)) {
         a.unroll = c->unroll_jts;
-        if (prec == FFTT_FP32) a.tab = c->d_tab32n.p;
-        FFTT_HIP(c, launch_apply_staged(c->stream, prec == FFTT_FP32_BF16TABLE, true, a));
+        const int fmt = staged_table(c, prec);
+        a.tab = staged_table_ptr(c, fmt);
+        FFTT_HIP(c, launch_apply_staged(c->stream, fmt, true, a));
     } else {
         FFTT_HIP(c, launch_apply(c->stream, prec, true, a));
     }
@@ -566,8 +587,13 @@ fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
             return FFTT_OK;
         case FFTT_TUNE_UNROLL_JT_STAGED:
         case FFTT_TUNE_UNROLL_J_STAGED:
-            if (value != 1 && value != 2 && value != 4) FFTT_BAD(c, "unroll must be 1, 2 or 4");
+            if (value != 1 && value != 2 && value != 4 && value != 8)
+                FFTT_BAD(c, "staged unroll must be 1, 2, 4 or 8");
             (key == FFTT_TUNE_UNROLL_J_STAGED ? c->unroll_js : c->unroll_jts) = value;
+            return FFTT_OK;
+        case FFTT_TUNE_STAGED_TABLE:
+            if (value != 0 && value != 1) FFTT_BAD(c, "staged table must be 0 or 1");
+            c->staged_pair_table = value;
             return FFTT_OK;
         case FFTT_TUNE_SPLIT_JT:
         case FFTT_TUNE_SPLIT_J:

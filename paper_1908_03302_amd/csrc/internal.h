@@ -16,6 +16,7 @@ constexpr int kTileVox = 64;
 constexpr int kMaxBands = 4;
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxTable = 16384;
+constexpr int kEntryPad = 4;      // zeroed entries after the last (look-ahead reads)
 
 // Geometry of one transducer seen from one tile centre c (all exact in FP64
 // except the two FP32 roundings, which the kernels compensate):
@@ -59,6 +60,7 @@ struct ApplyArgs {
     int nb;
     int ntab;
     float inv_dr[kMaxBands];  // (n-1)/r_max per band
+    float xr[kMaxBands];      // inv_dr[b] / inv_dr[0] (staged kernels scale by band 0)
     double inv_dr64[kMaxBands];
     const void* tab;          // device table [nb][ntab] in the kernel's format
     const void* w;            // JT: [nb][M] weights C_p dT_p (internal pair order)
@@ -115,8 +117,14 @@ hipError_t launch_weights(hipStream_t s, bool fp64, const void* dT, const int32_
 hipError_t launch_fill(hipStream_t s, bool fp64, void* p, int64_t n);
 hipError_t launch_apply(hipStream_t s, fftt_precision prec, bool transpose,
                         const ApplyArgs& a);
-hipError_t launch_apply_staged(hipStream_t s, bool bf16, bool transpose, const ApplyArgs& a);
-size_t staged_lds_bytes(int nb, int ntab, bool bf16, int64_t n_tx, int wpb);
+// Table formats of the staged kernels.
+enum StagedTable {
+    STAB_NODE32 = 0,  // FP32 nodes h_k (4 bytes per node), cutoff by a select
+    STAB_PAIR32 = 1,  // FP32 (h_k, h_{k+1} - h_k) (8 bytes per node), cutoff by the clamp
+    STAB_BF16 = 2,    // packed BF16 (h_k, slope) (4 bytes per node)
+};
+hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a);
+size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, int wpb);
 hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz,
                          const int64_t* gptr, const void* desc, const double* C,
                          const int32_t* porig, int64_t M, int nb, void* dT);
@@ -184,7 +192,8 @@ struct fftt_ctx {
     int unroll_j = 4;
     int split_jt = 0, split_j = 1;
     int staged = 1;            // use the LDS-staged kernels when they fit
-    int unroll_jts = 4, unroll_js = 4;
+    int unroll_jts = 8, unroll_js = 8;
+    int staged_pair_table = 0; // FP32 staged kernels: 0 node table, 1 (h, slope) pairs
     size_t lds_limit = 65536;
 
     // work buffers

@@ -116,7 +116,7 @@ __device__ __forceinline__ T multi_sum(const T (&v)[U], int lane) {
         const T y = odd ? v[0] : v[1];
         x += dpp_f<0xb1>(y);
         x += dpp_f<0x4e>(x);
-    } else {
+    } else if constexpr (U == 4) {
         const bool odd = lane & 1, two = lane & 2;
         T a = odd ? v[1] : v[0];
         const T b = odd ? v[0] : v[1];
@@ -127,6 +127,26 @@ __device__ __forceinline__ T multi_sum(const T (&v)[U], int lane) {
         x = two ? c : a;
         const T y = two ? a : c;
         x += dpp_f<0x4e>(y);
+    } else {
+        static_assert(U == 8, "multi_sum: U in {1, 2, 4, 8}");
+        const bool odd = lane & 1, two = lane & 2, four = lane & 4;
+        T a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {   // a[k]: value 2k + bit 0 of the lane
+            a[k] = odd ? v[2 * k + 1] : v[2 * k];
+            a[k] += dpp_f<0xb1>(odd ? v[2 * k] : v[2 * k + 1]);
+        }
+        T c[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {   // c[k]: value 4k + (lane & 3)
+            c[k] = two ? a[2 * k + 1] : a[2 * k];
+            c[k] += dpp_f<0x4e>(two ? a[2 * k] : a[2 * k + 1]);
+        }
+        // the partner 4 lanes away in the row has bit 2 flipped: value lane & 7
+        x = four ? c[1] : c[0];
+        x += dpp_f<0x124>(four ? c[0] : c[1]);
+        x += dpp_f<0x128>(x);                 // row_ror:8
+        return add_halves(x);
     }
     x += dpp_f<0x124>(x);                     // row_ror:4
     x += dpp_f<0x128>(x);                     // row_ror:8
@@ -400,40 +420,46 @@ __device__ __forceinline__ void dist64(const TxConst& c, double ux, double uy, d
     delta = Rx - D;
 }
 
+// Table coordinate x = R / dR clamped to [0, n-1] (v_med3; a NaN maps into
+// range).  The lookups below take the clamped coordinate; the interpolation
+// weight is fract(x), exact for x >= 0.
+__device__ __forceinline__ float table_x(float x, float nm1) {
+    return __builtin_amdgcn_fmed3f(x, 0.0f, nm1);
+}
+
 // Linear interpolation in a table of nodes k = 0..n-1 over [0, r_max]; entry
 // k stores (h_k, h_{k+1} - h_k) and entry n-1 is (0, 0), so clamping the
 // coordinate to n-1 yields zero for every R >= r_max.
-// The coordinate is clamped to [0, n-1] (v_med3; a NaN maps into range).
-__device__ __forceinline__ float lookup(const float2* tab, float R, float inv_dr, float nm1) {
-    const float x = __builtin_amdgcn_fmed3f(R * inv_dr, 0.0f, nm1);
+__device__ __forceinline__ float lookup_x(const float2* tab, float x, float) {
     const int k = (int)x;
-    const float f = x - (float)k;
     const float2 t = tab[k];
-    return fmaf(f, t.y, t.x);
+    return fmaf(__builtin_amdgcn_fractf(x), t.y, t.x);
 }
 
 // BF16 table: entry k packs a = bf16(h_k) in the low half and
 // d = bf16(h_{k+1} - a) in the high half, so h = a + f d; the rounding of a
 // is fully felt at the node and fades linearly to the next node.
-__device__ __forceinline__ float lookup(const uint32_t* tab, float R, float inv_dr, float nm1) {
-    const float x = __builtin_amdgcn_fmed3f(R * inv_dr, 0.0f, nm1);
+__device__ __forceinline__ float lookup_x(const uint32_t* tab, float x, float) {
     const int k = (int)x;
-    const float f = x - (float)k;
     const uint32_t e = tab[k];
-    return fmaf(f, __uint_as_float(e & 0xffff0000u), __uint_as_float(e << 16));
+    return fmaf(__builtin_amdgcn_fractf(x), __uint_as_float(e & 0xffff0000u),
+                __uint_as_float(e << 16));
 }
 
 // FP32 node table h_0..h_{n-1}, h_n = 0 (one float per node, half the LDS of
 // the (h, slope) layout): both nodes come from one ds_read2; the truncation
-// to zero for R >= r_max is an explicit select.
-__device__ __forceinline__ float lookup(const float* tab, float R, float inv_dr, float nm1) {
-    const float x = __builtin_amdgcn_fmed3f(R * inv_dr, 0.0f, nm1);
+// to zero for R >= r_max is a select on the interpolated value (the reads
+// themselves are never predicated: k <= n-1 always).
+__device__ __forceinline__ float lookup_x(const float* tab, float x, float nm1) {
     const int k = (int)x;
-    const float f = x - (float)k;
     const float h0 = tab[k], h1 = tab[k + 1];
-    // mask multiply rather than a select, so the read is never predicated
-    const float keep = x < nm1 ? 1.0f : 0.0f;
-    return fmaf(f, h1 - h0, h0) * keep;
+    const float v = fmaf(__builtin_amdgcn_fractf(x), h1 - h0, h0);
+    return x < nm1 ? v : 0.0f;
+}
+
+template <class TabT>
+__device__ __forceinline__ float lookup(const TabT* tab, float R, float inv_dr, float nm1) {
+    return lookup_x(tab, table_x(R * inv_dr, nm1), nm1);
 }
 
 __device__ __forceinline__ double lookup(const double2* tab, double R, double inv_dr, double nm1) {
@@ -827,7 +853,7 @@ __device__ __forceinline__ void stage_distances(const ApplyArgs& A, int64_t a, c
     for (int q = wave; q < (int)A.n_tx; q += W) {
         float d, rs;
         dist32(row[q], V.ux, V.uy, V.uz, V.uu, d, rs);
-        sx[q * 64 + lane] = make_float2(d, rs);
+        sx[q * 64 + lane] = make_float2(d * A.inv_dr[0], rs);
     }
     __syncthreads();
 }
@@ -858,76 +884,95 @@ __device__ __forceinline__ StepEntries<U> load_entries(const Entry* __restrict__
     return E;
 }
 
-// Source distances of a step from the LDS stage.  Entries are sorted by
-// source, so usually all U share the current one (no LDS read); otherwise
-// every entry's source is read, in one batch.
-template <int U>
-struct StepSources {
-    float d[U];
-    float rs[U];
-};
-
-template <int U>
-__device__ __forceinline__ StepSources<U> staged_sources(const StepEntries<U>& E,
-                                                         const float2* sx, int lane, int& prev,
-                                                         float& cd, float& crs) {
-    StepSources<U> S;
+// Source terms of a step: the scaled detour part and 1/R_xs times a per-lane
+// factor (J: the model value of the voxel, J^T: 1).  Entries are sorted by
+// source within runs, so usually all U entries of a step share the cached
+// source (no LDS read, no multiply); otherwise every entry's source is read
+// in one batch.  The arithmetic of the step is instantiated in both arms so
+// that the cached values are used in place (no register copies).
+template <int U, bool SCALE, class F>
+__device__ __forceinline__ void with_sources(const StepEntries<U>& E, const float2* sx, int lane,
+                                             int& prev, float& cd, float& cg, float factor,
+                                             F&& body) {
     bool same = true;
 #pragma unroll
     for (int u = 0; u < U; ++u) same = same && (E.s[u] == prev);
     if (same) {
+        float d[U], g[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            S.d[u] = cd;
-            S.rs[u] = crs;
+            d[u] = cd;
+            g[u] = cg;
         }
+        body(d, g);
     } else {
+        float d[U], g[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const float2 v = sx[E.s[u] * 64 + lane];
-            S.d[u] = v.x;
-            S.rs[u] = v.y;
+            d[u] = v.x;
+            g[u] = SCALE ? v.y * factor : v.y;
         }
+        body(d, g);
         prev = E.s[U - 1];
-        cd = S.d[U - 1];
-        crs = S.rs[U - 1];
+        cd = d[U - 1];
+        cg = g[U - 1];
     }
-    return S;
+}
+
+template <int NB, int U>
+struct StepWeights {
+    float w[U][NB];
+};
+
+// The weights of a step go through the vector memory path: the pair index is
+// copied into a VGPR (identity DPP move), so the loads are counted by vmcnt
+// and their latency overlaps the step's LDS reads instead of adding a second
+// dependent scalar-memory round trip after the entries.
+template <int NB, int U>
+__device__ __forceinline__ StepWeights<NB, U> load_weights(const ApplyArgs& A,
+                                                          const float* __restrict__ w,
+                                                          const StepEntries<U>& E) {
+    StepWeights<NB, U> W;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int pv = __builtin_amdgcn_update_dpp(0, E.p[u], 0xe4, 0xf, 0xf, false);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) W.w[u][b] = w[b * A.M + pv];
+    }
+    return W;
 }
 
 template <int NB, class TabT, int U>
-__device__ __forceinline__ void jt32s_step(const ApplyArgs& A, const TabT* st, const float2* sx,
-                                           const Entry* __restrict__ ents,
-                                           const float* __restrict__ w, float nm1, int lane,
-                                           int64_t e, int& prev, float& cd, float& crs,
+__device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, const float2* sx,
+                                           const StepEntries<U>& E, const StepWeights<NB, U>& W,
+                                           float nm1, int lane, int& prev, float& cd, float& cg,
                                            float& acc) {
-    const StepEntries<U> E = load_entries<U>(ents, e);
-    float wu[U][NB];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) wu[u][b] = w[b * A.M + E.p[u]];
-    const StepSources<U> S = staged_sources<U>(E, sx, lane, prev, cd, crs);
-    float rd[U], rr[U];
+    float rd[U], rg[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const float2 v = sx[E.r[u] * 64 + lane];
         rd[u] = v.x;
-        rr[u] = v.y;
+        rg[u] = v.y;
     }
+    with_sources<U, false>(E, sx, lane, prev, cd, cg, 1.0f,
+                           [&](const float (&sd)[U], const float (&sg)[U]) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const float R = (S.d[u] + rd[u]) + E.R0[u];
-        float hw = 0.f;
+        for (int u = 0; u < U; ++u) {
+            // R / dR_0 = (delta_s + delta_r) / dR_0 + R0 / dR_0
+            const float x0 = fmaf(E.R0[u], A.inv_dr[0], sd[u] + rd[u]);
+            float hw = lookup_x(st, table_x(x0, nm1), nm1) * W.w[u][0];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            hw = fmaf(lookup(st + b * A.ntab, R, A.inv_dr[b], nm1), wu[u][b], hw);
-        acc = fmaf(hw, S.rs[u] * rr[u], acc);
-    }
+            for (int b = 1; b < NB; ++b)
+                hw = fmaf(lookup_x(st + b * A.ntab, table_x(x0 * A.xr[b], nm1), nm1), W.w[u][b],
+                          hw);
+            acc = fmaf(hw, sg[u] * rg[u], acc);
+        }
+    });
 }
 
 template <int NB, class TabT, int U>
-__global__ __launch_bounds__(1024) void k_jt32s(ApplyArgs A) {
+__global__ __launch_bounds__(1024, 8) void k_jt32s(ApplyArgs A) {
     const TabT* st = stage_table<TabT>(A, NB);
     float2* sx = staged_tx<TabT>(A, NB);
     const int64_t a = blockIdx.x;
@@ -947,13 +992,19 @@ __global__ __launch_bounds__(1024) void k_jt32s(ApplyArgs A) {
     }
     const float* __restrict__ w = static_cast<const float*>(A.w);
     const float nm1 = (float)(A.ntab - 1);
-    float acc = 0.f, cd = 0.f, crs = 0.f;
+    float acc = 0.f, cd = 0.f, cg = 0.f;
     int prev = -1;
     int64_t e = e0;
-    for (; e + U <= e1; e += U)
-        jt32s_step<NB, TabT, U>(A, st, sx, A.ents, w, nm1, lane, e, prev, cd, crs, acc);
-    for (; e < e1; ++e)
-        jt32s_step<NB, TabT, 1>(A, st, sx, A.ents, w, nm1, lane, e, prev, cd, crs, acc);
+    for (; e + U <= e1; e += U) {
+        const StepEntries<U> E = load_entries<U>(A.ents, e);
+        jt32s_body<NB, TabT, U>(A, st, sx, E, load_weights<NB, U>(A, w, E), nm1, lane, prev, cd,
+                                cg, acc);
+    }
+    for (; e < e1; ++e) {
+        const StepEntries<1> E = load_entries<1>(A.ents, e);
+        jt32s_body<NB, TabT, 1>(A, st, sx, E, load_weights<NB, 1>(A, w, E), nm1, lane, prev, cd,
+                                cg, acc);
+    }
     // combine the wavefronts in order (the staged distances are no longer needed)
     __syncthreads();
     float* s_acc = reinterpret_cast<float*>(sx);
@@ -968,31 +1019,42 @@ __global__ __launch_bounds__(1024) void k_jt32s(ApplyArgs A) {
 }
 
 template <int NB, class TabT, int U>
-__device__ __forceinline__ void j32s_step(const ApplyArgs& A, const TabT* st, const float2* sx,
-                                          const Entry* __restrict__ ents, float* __restrict__ part,
+__device__ __forceinline__ void j32s_body(const ApplyArgs& A, const TabT* st, const float2* sx,
+                                          const StepEntries<U>& E, float* __restrict__ part,
                                           float xv, float nm1, int lane, int64_t e, int& prev,
-                                          float& cd, float& crs) {
-    const StepEntries<U> E = load_entries<U>(ents, e);
-    const StepSources<U> S = staged_sources<U>(E, sx, lane, prev, cd, crs);
-    float R[U], t[U];
+                                          float& cd, float& cg) {
+    float rd[U], rg[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const float2 v = sx[E.r[u] * 64 + lane];
-        R[u] = (S.d[u] + v.x) + E.R0[u];
-        t[u] = (S.rs[u] * xv) * v.y;
+        rd[u] = v.x;
+        rg[u] = v.y;
     }
+    // source factor cached as dc_j / R_xs
+    with_sources<U, true>(E, sx, lane, prev, cd, cg, xv,
+                          [&](const float (&sd)[U], const float (&sg)[U]) {
+        float x0[U], t[U];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        float v[U];
+        for (int u = 0; u < U; ++u) {
+            x0[u] = fmaf(E.R0[u], A.inv_dr[0], sd[u] + rd[u]);
+            t[u] = sg[u] * rg[u];
+        }
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = lookup(st + b * A.ntab, R[u], A.inv_dr[b], nm1) * t[u];
-        const float sum = multi_sum<U>(v, lane);
-        if (lane < U) part[b * A.nnz + e + lane] = sum;
-    }
+        for (int b = 0; b < NB; ++b) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float xb = b == 0 ? x0[u] : x0[u] * A.xr[b];
+                v[u] = lookup_x(st + b * A.ntab, table_x(xb, nm1), nm1) * t[u];
+            }
+            const float sum = multi_sum<U>(v, lane);
+            if (lane < U) part[b * A.nnz + e + lane] = sum;
+        }
+    });
 }
 
 template <int NB, class TabT, int U>
-__global__ __launch_bounds__(1024) void k_j32s(ApplyArgs A) {
+__global__ __launch_bounds__(1024, 8) void k_j32s(ApplyArgs A) {
     const TabT* st = stage_table<TabT>(A, NB);
     float2* sx = staged_tx<TabT>(A, NB);
     const int64_t a = blockIdx.x;
@@ -1013,13 +1075,15 @@ __global__ __launch_bounds__(1024) void k_j32s(ApplyArgs A) {
     float* __restrict__ part = static_cast<float*>(A.out);
     const float xv = V.act ? static_cast<const float*>(A.x)[V.vidx] : 0.f;
     const float nm1 = (float)(A.ntab - 1);
-    float cd = 0.f, crs = 0.f;
+    float cd = 0.f, cg = 0.f;
     int prev = -1;
     int64_t e = e0;
     for (; e + U <= e1; e += U)
-        j32s_step<NB, TabT, U>(A, st, sx, A.ents, part, xv, nm1, lane, e, prev, cd, crs);
+        j32s_body<NB, TabT, U>(A, st, sx, load_entries<U>(A.ents, e), part, xv, nm1, lane, e,
+                               prev, cd, cg);
     for (; e < e1; ++e)
-        j32s_step<NB, TabT, 1>(A, st, sx, A.ents, part, xv, nm1, lane, e, prev, cd, crs);
+        j32s_body<NB, TabT, 1>(A, st, sx, load_entries<1>(A.ents, e), part, xv, nm1, lane, e,
+                               prev, cd, cg);
 }
 
 template <class K>
@@ -1038,38 +1102,51 @@ static hipError_t launch_staged(K kern, hipStream_t s, const ApplyArgs& a, size_
     return hipGetLastError();
 }
 
-size_t staged_lds_bytes(int nb, int ntab, bool bf16, int64_t n_tx, int wpb) {
-    const size_t tab = (size_t)nb * ntab * (bf16 ? sizeof(uint32_t) : sizeof(float));
+static size_t staged_entry_bytes(int tabfmt) {
+    return tabfmt == STAB_PAIR32 ? sizeof(float2) : sizeof(float);
+}
+
+size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, int wpb) {
+    const size_t tab = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
     return ((tab + 15) & ~(size_t)15) +
            std::max<size_t>((size_t)n_tx * 64 * sizeof(float2), (size_t)wpb * 64 * sizeof(float));
 }
 
-template <int NB, int U>
-static hipError_t launch_staged_nbu(hipStream_t s, bool bf16, bool transpose, const ApplyArgs& a) {
-    const size_t n = (size_t)NB * a.ntab;
-    if (bf16)
-        return transpose ? launch_staged(k_jt32s<NB, uint32_t, U>, s, a, n * sizeof(uint32_t))
-                         : launch_staged(k_j32s<NB, uint32_t, U>, s, a, n * sizeof(uint32_t));
-    return transpose ? launch_staged(k_jt32s<NB, float, U>, s, a, n * sizeof(float))
-                     : launch_staged(k_j32s<NB, float, U>, s, a, n * sizeof(float));
+template <class TabT, int NB, int U>
+static hipError_t launch_staged_t(hipStream_t s, bool transpose, const ApplyArgs& a) {
+    const size_t bytes = (size_t)NB * a.ntab * sizeof(TabT);
+    return transpose ? launch_staged(k_jt32s<NB, TabT, U>, s, a, bytes)
+                     : launch_staged(k_j32s<NB, TabT, U>, s, a, bytes);
 }
 
-template <int NB>
-static hipError_t launch_staged_nb(hipStream_t s, bool bf16, bool transpose, const ApplyArgs& a) {
-    switch (a.unroll) {
-        case 1: return launch_staged_nbu<NB, 1>(s, bf16, transpose, a);
-        case 2: return launch_staged_nbu<NB, 2>(s, bf16, transpose, a);
-        case 4: return launch_staged_nbu<NB, 4>(s, bf16, transpose, a);
+template <int NB, int U>
+static hipError_t launch_staged_nbu(hipStream_t s, int tabfmt, bool transpose,
+                                    const ApplyArgs& a) {
+    switch (tabfmt) {
+        case STAB_NODE32: return launch_staged_t<float, NB, U>(s, transpose, a);
+        case STAB_PAIR32: return launch_staged_t<float2, NB, U>(s, transpose, a);
+        case STAB_BF16: return launch_staged_t<uint32_t, NB, U>(s, transpose, a);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_apply_staged(hipStream_t s, bool bf16, bool transpose, const ApplyArgs& a) {
+template <int NB>
+static hipError_t launch_staged_nb(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a) {
+    switch (a.unroll) {
+        case 1: return launch_staged_nbu<NB, 1>(s, tabfmt, transpose, a);
+        case 2: return launch_staged_nbu<NB, 2>(s, tabfmt, transpose, a);
+        case 4: return launch_staged_nbu<NB, 4>(s, tabfmt, transpose, a);
+        case 8: return launch_staged_nbu<NB, 8>(s, tabfmt, transpose, a);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a) {
     switch (a.nb) {
-        case 1: return launch_staged_nb<1>(s, bf16, transpose, a);
-        case 2: return launch_staged_nb<2>(s, bf16, transpose, a);
-        case 3: return launch_staged_nb<3>(s, bf16, transpose, a);
-        case 4: return launch_staged_nb<4>(s, bf16, transpose, a);
+        case 1: return launch_staged_nb<1>(s, tabfmt, transpose, a);
+        case 2: return launch_staged_nb<2>(s, tabfmt, transpose, a);
+        case 3: return launch_staged_nb<3>(s, tabfmt, transpose, a);
+        case 4: return launch_staged_nb<4>(s, tabfmt, transpose, a);
     }
     return hipErrorInvalidValue;
 }

@@ -26,6 +26,7 @@ EXPORTS = ["fftt_create", "fftt_destroy", "fftt_last_error", "fftt_set_stream",
            "fftt_psf", "fftt_profile", "fftt_kernel_time", "fftt_set_tuning"]
 TUNE_WAVES_PER_BLOCK, TUNE_UNROLL_JT, TUNE_UNROLL_J, TUNE_SPLIT_JT, TUNE_SPLIT_J = 0, 1, 2, 3, 4
 TUNE_STAGED, TUNE_UNROLL_JT_STAGED, TUNE_UNROLL_J_STAGED = 5, 6, 7
+TUNE_STAGED_TABLE = 8
 
 
 class SolveOpts(C.Structure):
@@ -178,12 +179,14 @@ class Context:
         return pv.value, lanes.value
 
     def set_tuning(self, waves_per_block=None, unroll_jt=None, unroll_j=None, split_jt=None,
-                   split_j=None, staged=None, unroll_jt_staged=None, unroll_j_staged=None):
+                   split_j=None, staged=None, unroll_jt_staged=None, unroll_j_staged=None,
+                   staged_table=None):
         for key, v in ((TUNE_WAVES_PER_BLOCK, waves_per_block), (TUNE_UNROLL_JT, unroll_jt),
                        (TUNE_UNROLL_J, unroll_j), (TUNE_SPLIT_JT, split_jt),
                        (TUNE_SPLIT_J, split_j), (TUNE_STAGED, staged),
                        (TUNE_UNROLL_JT_STAGED, unroll_jt_staged),
-                       (TUNE_UNROLL_J_STAGED, unroll_j_staged)):
+                       (TUNE_UNROLL_J_STAGED, unroll_j_staged),
+                       (TUNE_STAGED_TABLE, staged_table)):
             if v is not None:
                 self._check(self.L.fftt_set_tuning(self.h, key, int(v)), "set_tuning")
 

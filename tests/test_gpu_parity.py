@@ -292,17 +292,21 @@ def test_ring2d_adjoint_fp32(ring2d):
 
 # ------------------------------------------------------------ launch shapes
 
-@pytest.mark.parametrize("wpb,unroll,split,staged", [
-    (1, 1, 0, 0), (4, 2, 0, 0), (8, 4, 0, 0), (16, 4, 0, 0), (4, 1, 1, 0), (8, 2, 1, 0),
-    (16, 4, 1, 0), (1, 1, 1, 1), (4, 2, 1, 1), (16, 4, 1, 1), (8, 1, 1, 1)])
-def test_launch_shapes_agree(ragged, wpb, unroll, split, staged):
+@pytest.mark.parametrize("wpb,unroll,split,staged,stab", [
+    (1, 1, 0, 0, 0), (4, 2, 0, 0, 0), (8, 4, 0, 0, 0), (16, 4, 0, 0, 0), (4, 1, 1, 0, 0),
+    (8, 2, 1, 0, 0), (16, 4, 1, 0, 0), (1, 1, 1, 1, 0), (4, 2, 1, 1, 0), (16, 4, 1, 1, 0),
+    (8, 1, 1, 1, 0), (16, 4, 1, 1, 1), (4, 2, 1, 1, 1), (1, 1, 1, 1, 1), (16, 8, 1, 1, 0),
+    (2, 8, 1, 1, 1)])
+def test_launch_shapes_agree(ragged, wpb, unroll, split, staged, stab):
     """Every tuning (tiles per workgroup, unroll, split of a tile's pairs over
-    a workgroup, LDS-staged distances) computes the same operator, within the
-    FP32/FP64 bars."""
+    a workgroup, LDS-staged distances, staged table layout) computes the same
+    operator, within the FP32/FP64 bars."""
     w, o, ot, ctx = ragged
     f = _fftt()
-    ctx.set_tuning(waves_per_block=wpb, unroll_jt=unroll, unroll_j=unroll, split_jt=split,
-                   split_j=split, staged=staged, unroll_jt_staged=unroll, unroll_j_staged=unroll)
+    u_ns = min(unroll, 4)   # the per-wavefront kernels take 1, 2 or 4
+    ctx.set_tuning(waves_per_block=wpb, unroll_jt=u_ns, unroll_j=u_ns, split_jt=split,
+                   split_j=split, staged=staged, unroll_jt_staged=unroll, unroll_j_staged=unroll,
+                   staged_table=stab)
     try:
         x = I.random_vector(w.n, 70) * 5.0
         yt = I.random_vector(2 * w.m, 71) * 1e-7
@@ -316,4 +320,4 @@ def test_launch_shapes_agree(ragged, wpb, unroll, split, staged):
                 assert rel(y, y_ref) < 1e-5 and rel(xg, x_ref) < 1e-5
     finally:
         ctx.set_tuning(waves_per_block=16, unroll_jt=2, unroll_j=4, split_jt=0, split_j=1,
-                       staged=1, unroll_jt_staged=4, unroll_j_staged=4)
+                       staged=1, unroll_jt_staged=8, unroll_j_staged=8, staged_table=0)
