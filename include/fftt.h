@@ -159,8 +159,16 @@ fftt_status fftt_solve(fftt_ctx *ctx, const fftt_solve_opts *opts,
                        const void *d_obs, void *x, fftt_solve_report *rep);
 
 /* Hessian point-spread functions (eq. resolution_2):
- * out[k] = J^T J e_{voxels[k]} / sigma^2, e_i = 1 m/s at voxel i.
- *   voxels: host [n] active voxel indices;  out: device [n][N]. */
+ * out[k] = J^T J e_{voxels[k]} / sigma^2, e_i = 1 m/s at voxel i, summed
+ * over bands.
+ *   voxels: host [n] active voxel indices;  out: device [n][N] (FP64 for
+ *   FFTT_FP64, FP32 otherwise), overwritten.
+ * FP32 / BF16-table precision with the staged kernels enabled (and the
+ * tables plus n_tx * 512 bytes within LDS): all n in one batch -- the J^T
+ * weights of every J e_k, then one launch that contracts the per-tile
+ * kernel values with them on the matrix cores (FP32 MFMA).  Otherwise one
+ * J and one J^T per voxel.  Library workspace: nb * M * ceil32(n) floats.
+ * Asynchronous except for the final wait of the batched path. */
 fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
                      int32_t n, double noise_sigma, void *out);
 
@@ -190,7 +198,8 @@ fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
  * kernels is bracketed by HIP events on the context's stream; enabling
  * clears the record.  fftt_kernel_time sums the recorded durations (ms) and
  * counts the launches of one kernel: which = 0 the J kernel, 1 the J^T
- * kernel, 2 the per-pair reduction of J.  Synchronises the stream. */
+ * kernel, 2 the per-pair reduction of J, 3 the batched point-spread
+ * functions (weights and matrix-core pass).  Synchronises the stream. */
 fftt_status fftt_profile(fftt_ctx *ctx, int32_t enable);
 fftt_status fftt_kernel_time(fftt_ctx *ctx, int32_t which, double *ms, int64_t *launches);
 

@@ -58,7 +58,7 @@ fftt_status upload_tables(fftt_ctx* c) {
     std::vector<float> t32((size_t)nb * n * 2);
     std::vector<double> t64((size_t)nb * n * 2);
     std::vector<uint32_t> tbf((size_t)nb * n);
-    std::vector<float> tnode((size_t)nb * n);
+    std::vector<float> tnode((size_t)nb * n + 1, 0.f);   // + h_n = 0 after the last band
     for (int b = 0; b < nb; ++b) {
         const std::vector<double>& h = c->h[b];
         for (int k = 0; k < n; ++k) {
@@ -246,6 +246,43 @@ const void* staged_table_ptr(const fftt_ctx* c, int fmt) {
         case STAB_PAIR32: return c->d_tab32.p;
         default: return c->d_tabbf.p;
     }
+}
+
+// Batched PSFs (FP32 / BF16 table): every voxel's J^T weights, then one
+// launch of the matrix-core kernel over all active tiles.
+fftt_status psf_batched(fftt_ctx* c, fftt_precision prec, const int64_t* voxels, int32_t n,
+                        double s2, float* out) {
+    const int64_t nx = c->g.dims[0], ny = c->g.dims[1];
+    std::vector<int32_t> desc(2 * (size_t)n);
+    for (int32_t k = 0; k < n; ++k) {
+        const int64_t v = voxels[k];
+        const int64_t x = v % nx, y = (v / nx) % ny, z = v / (nx * ny);
+        const int64_t t = x / kTile + c->g.ntile[0] * (y / kTile + c->g.ntile[1] * (z / kTile));
+        const auto it = std::lower_bound(c->act_tiles.begin(), c->act_tiles.end(), (int32_t)t);
+        if (it == c->act_tiles.end() || *it != t) FFTT_BAD(c, "psf: voxel outside active tiles");
+        desc[k] = (int32_t)(it - c->act_tiles.begin());
+        desc[n + k] = (int32_t)((x % kTile) + kTile * ((y % kTile) + kTile * (z % kTile)));
+    }
+    const int64_t ldw = ((int64_t)n + 31) / 32 * 32;
+    FFTT_HIP(c, c->d_psfd.alloc(desc.size() * sizeof(int32_t)));
+    FFTT_HIP(c, hipMemcpyAsync(c->d_psfd.p, desc.data(), desc.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, c->stream));
+    FFTT_HIP(c, c->d_psfw.alloc((size_t)c->nb * c->M * ldw * sizeof(float)));
+    FFTT_HIP(c, launch_fill(c->stream, false, c->d_psfw.p, (int64_t)c->nb * c->M * ldw));
+    FFTT_HIP(c, launch_fill(c->stream, false, out, (int64_t)n * c->N));
+    ApplyArgs a = base_args(c);
+    const int fmt = staged_table(c, prec);
+    a.tab = staged_table_ptr(c, fmt);
+    const void* col_tab = c->d_tab32.p;   // FP32 (h, slope) pairs
+    hipEvent_t stop;
+    FFTT_HIP(c, prof_begin(c, 3, &stop));
+    FFTT_HIP(c, launch_psf(c->stream, fmt, a, c->d_psfd.as<int32_t>(),
+                           c->d_psfd.as<int32_t>() + n, c->d_C.as<double>(), s2,
+                           c->d_psfw.as<float>(), ldw, n, out, col_tab));
+    FFTT_HIP(c, prof_end(c, stop));
+    // the host descriptor buffer must outlive the asynchronous copy
+    FFTT_HIP(c, hipStreamSynchronize(c->stream));
+    return FFTT_OK;
 }
 
 // dT [B][M] = J dc (caller order), one right-hand side; ensure_ready done.
@@ -613,7 +650,7 @@ fftt_status fftt_profile(fftt_ctx* c, int32_t enable) {
 
 fftt_status fftt_kernel_time(fftt_ctx* c, int32_t which, double* ms, int64_t* launches) {
     if (!c) return FFTT_E_INVALID;
-    if (which < 0 || which > 2 || !ms || !launches) FFTT_BAD(c, "kernel_time: bad argument");
+    if (which < 0 || which > 3 || !ms || !launches) FFTT_BAD(c, "kernel_time: bad argument");
     FFTT_HIP(c, hipStreamSynchronize(c->stream));
     double tot = 0.0;
     for (size_t i = 0; i < c->prof_used[which]; ++i) {
@@ -784,12 +821,15 @@ fftt_status fftt_psf(fftt_ctx* c, fftt_precision prec, const int64_t* voxels, in
         if (voxels[k] < 0 || voxels[k] >= c->N || !c->mask[voxels[k]])
             FFTT_BAD(c, "psf: voxel index out of range or not active");
     const bool fp64 = prec == FFTT_FP64;
+    const double s2 = 1.0 / (noise_sigma * noise_sigma);
+    if (!fp64 && c->staged &&
+        psf_lds_bytes(c->nb, c->ntab, staged_table(c, prec), c->n_tx) <= c->lds_limit)
+        return psf_batched(c, prec, voxels, n, s2, static_cast<float*>(out));
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
     const int64_t D = (int64_t)c->nb * c->M;
     FFTT_HIP(c, c->d_solve.alloc((size_t)(D + c->N) * es));
     void* dT = c->d_solve.p;
     void* e = c->d_solve.as<char>() + D * es;
-    const double s2 = 1.0 / (noise_sigma * noise_sigma);
     for (int32_t k = 0; k < n; ++k) {
         FFTT_HIP(c, solver_unit(c->stream, fp64, e, c->N, voxels[k]));
         st = apply_J_one(c, prec, e, dT);

@@ -125,6 +125,13 @@ enum StagedTable {
 };
 hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a);
 size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, int wpb);
+// Batched point-spread functions: W ([nb][M][ldw], zeroed) and out ([n][N],
+// zeroed) are filled for the n voxels given by (active tile, lane) pairs;
+// col_tab is the FP32 (h, slope) table used for the weights.
+hipError_t launch_psf(hipStream_t s, int tabfmt, const ApplyArgs& a, const int32_t* ptile,
+                      const int32_t* plane, const double* C, double s2, float* W, int64_t ldw,
+                      int n, float* out, const void* col_tab);
+size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx);
 hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz,
                          const int64_t* gptr, const void* desc, const double* C,
                          const int32_t* porig, int64_t M, int nb, void* dT);
@@ -198,11 +205,12 @@ struct fftt_ctx {
 
     // work buffers
     fftt::DevBuf d_w, d_part, d_solve, d_scal;
+    fftt::DevBuf d_psfw, d_psfd;   // batched PSF weights, (tile, lane) of each voxel
 
     // optional event timing of the main kernels (index: 0 J, 1 J^T, 2 reduction)
     bool prof = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[3];
-    size_t prof_used[3] = {0, 0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[4];
+    size_t prof_used[4] = {0, 0, 0, 0};
     ~fftt_ctx() {
         for (auto& v : prof_ev)
             for (auto& e : v) {

@@ -1288,4 +1288,178 @@ hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz
     return hipGetLastError();
 }
 
+
+// ----------------------------------------------- batched point-spread functions
+//
+// PSF_k = J^T J e_{v_k} / sigma^2 for a batch of voxels v_k (eq. resolution_2).
+//
+// Step 1 (k_psf_cols): the J^T weights of the data J e_{v_k} / sigma^2,
+//   W[b][p][k] = C_p^2 h_b(R_{p, v_k}) / (R_xs R_xr sigma^2),
+// are non-zero only for the entries of v_k's tile: one wavefront per voxel,
+// lanes over those entries.
+//
+// Step 2 (k_psf32): per tile, PSF[k][j] = sum_e H[j][e] W[e][k] with
+// H[j][e] = h(R) / (R_xs R_xr) for voxel j of the tile and entry e: a dense
+// (64 x E) (E x n) product, done on the matrix cores with
+// v_mfma_f32_32x32x2f32 (FP32 operands and accumulation).  Each wavefront
+// owns 32 right-hand sides (the N dimension) and walks all entries of the
+// tile two at a time (K = 2), so there is no cross-wave reduction; the 64
+// voxels are two M = 32 blocks.  H comes from the LDS-staged distances as in
+// the single-RHS kernels.
+
+using f32x16 = __attribute__((__vector_size__(16 * sizeof(float)))) float;
+
+template <int NB, class TabT>
+__global__ __launch_bounds__(64) void k_psf_cols(ApplyArgs A, const int32_t* __restrict__ ptile,
+                                                 const int32_t* __restrict__ plane,
+                                                 const double* __restrict__ C, double s2,
+                                                 float* __restrict__ W, int64_t ldw) {
+    const int k = blockIdx.x;
+    const int64_t a = ptile[k];
+    const int l = plane[k];
+    const double ux = ((double)(l & 3) - 1.5) * A.g.spacing[0];
+    const double uy = ((double)((l >> 2) & 3) - 1.5) * A.g.spacing[1];
+    const double uz = ((double)(l >> 4) - 1.5) * A.g.spacing[2];
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const TxConst* __restrict__ row = A.txc + a * A.n_tx;
+    const TabT* tab = static_cast<const TabT*>(A.tab);
+    const float nm1 = (float)(A.ntab - 1);
+    for (int64_t e = A.tptr[a] + threadIdx.x; e < A.tptr[a + 1]; e += 64) {
+        const Entry E = A.ents[e];
+        const int s = (int)(E.sr & 0xffffu), r = (int)(E.sr >> 16);
+        float ds, gs, dr, gr;
+        dist32(row[s], ux, uy, uz, uu, ds, gs);
+        dist32(row[r], ux, uy, uz, uu, dr, gr);
+        const float R = (ds + dr) + E.R0hi;
+        const double c = C[E.p];
+        const float f = (float)(c * c * s2) * (gs * gr);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            W[((int64_t)b * A.M + E.p) * ldw + k] =
+                lookup(tab + b * A.ntab, R, A.inv_dr[b], nm1) * f;
+    }
+}
+
+// H of one entry for every lane (voxel) of the tile, summed over bands with
+// the band's weight column folded in by the caller (one band per call).
+template <class TabT>
+__device__ __forceinline__ float psf_h(const ApplyArgs& A, const TabT* st, const float2* sx,
+                                       const Entry& E, int b, float nm1, int lane) {
+    const int s = (int)(E.sr & 0xffffu), r = (int)(E.sr >> 16);
+    const float2 vs = sx[s * 64 + lane], vr = sx[r * 64 + lane];
+    const float x0 = fmaf(E.R0hi, A.inv_dr[0], vs.x + vr.x);
+    const float xb = b == 0 ? x0 : x0 * A.xr[b];
+    return lookup_x(st + b * A.ntab, table_x(xb, nm1), nm1) * (vs.y * vr.y);
+}
+
+template <int NB, class TabT>
+__global__ __launch_bounds__(1024) void k_psf32(ApplyArgs A, const float* __restrict__ W,
+                                                int64_t ldw, int n, float* __restrict__ out) {
+    const TabT* st = stage_table<TabT>(A, NB);
+    float2* sx = staged_tx<TabT>(A, NB);
+    const int64_t a = blockIdx.x;
+    if (a >= A.n_act) return;
+    const int lane = threadIdx.x & 63;
+    const LaneVox V = lane_vox(A, a, lane);
+    stage_distances(A, a, V, sx, lane);   // ends with a barrier; none follow
+    const int W_ = (int)(blockDim.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int k0 = ((int)blockIdx.y * W_ + wave) * 32;
+    if (k0 >= n) return;
+    const float nm1 = (float)(A.ntab - 1);
+    const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
+    const int col = lane & 31;
+    const bool upper = lane >= 32;
+    f32x16 c_lo = {}, c_hi = {};
+    for (int64_t e = t0; e < t1; e += 2) {
+        const bool pair = e + 1 < t1;
+        const Entry E0 = A.ents[e];
+        const Entry E1 = A.ents[pair ? e + 1 : e];
+        // B operand: lanes 0-31 row e, lanes 32-63 row e+1 (zero past the end)
+        const int p = upper ? E1.p : E0.p;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            float bw = W[((int64_t)b * A.M + p) * ldw + k0 + col];
+            bw = (upper && !pair) ? 0.0f : bw;
+            const float h0 = psf_h(A, st, sx, E0, b, nm1, lane);
+            const float h1 = psf_h(A, st, sx, E1, b, nm1, lane);
+            // A operands: x = [h0(0..31), h1(0..31)] for voxels 0-31,
+            // y = [h0(32..63), h1(32..63)] for voxels 32-63
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(h0),
+                                                             __float_as_uint(h1), false, false);
+            c_lo = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(sw[0]), bw, c_lo, 0, 0, 0);
+            c_hi = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(sw[1]), bw, c_hi, 0, 0, 0);
+        }
+    }
+    // D layout of the 32x32 block: register q of lane l holds row
+    // 8 (q / 4) + 4 (l / 32) + q % 4, column l % 32.
+    if (k0 + col >= n) return;
+    float* __restrict__ o = out + (int64_t)(k0 + col) * A.g.dims[0] * A.g.dims[1] * A.g.dims[2];
+    const int64_t t = A.tiles[a];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = 8 * (q / 4) + 4 * (lane >> 5) + (q & 3);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bool inside, act;
+            int64_t vidx, v[3];
+            voxel_of_lane(A, t, i + 32 * h, inside, act, vidx, v);
+            if (inside) o[vidx] = act ? (h ? c_hi[q] : c_lo[q]) : 0.0f;
+        }
+    }
+}
+
+template <int NB>
+static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
+                                const int32_t* ptile, const int32_t* plane, const double* C,
+                                double s2, float* W, int64_t ldw, int n, float* out,
+                                const void* col_tab) {
+    // the weights (J e_k, cheap) always use the FP32 (h, slope) table, so a
+    // BF16 table only enters through the contraction
+    ApplyArgs ac = a;
+    ac.tab = col_tab;
+    hipLaunchKernelGGL((k_psf_cols<NB, float2>), dim3((unsigned)n), dim3(64), 0, s, ac, ptile,
+                       plane, C, s2, W, ldw);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess || a.n_act == 0) return err;
+    const int wpb = a.waves_per_block;
+    const unsigned nbat = (unsigned)((n + 32 * wpb - 1) / (32 * wpb));
+    const size_t tbytes = (size_t)NB * a.ntab * staged_entry_bytes(tabfmt);
+    const size_t lds = ((tbytes + 15) & ~(size_t)15) + (size_t)a.n_tx * 64 * sizeof(float2);
+    auto run = [&](auto kern) -> hipError_t {
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kern, dim3((unsigned)a.n_act, nbat), dim3(64 * wpb), lds, s, a, W,
+                           ldw, n, out);
+        return hipGetLastError();
+    };
+    switch (tabfmt) {
+        case STAB_NODE32: return run(k_psf32<NB, float>);
+        case STAB_PAIR32: return run(k_psf32<NB, float2>);
+        case STAB_BF16: return run(k_psf32<NB, uint32_t>);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_psf(hipStream_t s, int tabfmt, const ApplyArgs& a, const int32_t* ptile,
+                      const int32_t* plane, const double* C, double s2, float* W, int64_t ldw,
+                      int n, float* out, const void* col_tab) {
+    switch (a.nb) {
+        case 1: return launch_psf_nb<1>(s, tabfmt, a, ptile, plane, C, s2, W, ldw, n, out, col_tab);
+        case 2: return launch_psf_nb<2>(s, tabfmt, a, ptile, plane, C, s2, W, ldw, n, out, col_tab);
+        case 3: return launch_psf_nb<3>(s, tabfmt, a, ptile, plane, C, s2, W, ldw, n, out, col_tab);
+        case 4: return launch_psf_nb<4>(s, tabfmt, a, ptile, plane, C, s2, W, ldw, n, out, col_tab);
+    }
+    return hipErrorInvalidValue;
+}
+
+size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
+    const size_t tbytes = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
+    return ((tbytes + 15) & ~(size_t)15) + (size_t)n_tx * 64 * sizeof(float2);
+}
+
 }  // namespace fftt

@@ -1,0 +1,175 @@
+"""Batched Hessian point-spread functions (eq. resolution_2) through the C
+ABI against the CPU FP64 oracle: PSF_k = sum_b J_b^T J_b e_k / sigma^2.
+
+The FP32 / BF16-table PSFs are computed in one batch (weights of every
+J e_k, then a matrix-core contraction per tile).  References come from the
+oracle's dense J blocks, evaluated two ways: by frequency quadrature (the
+definition) and from the oracle's own linear table of the same size.
+
+Bars, norm-wise per PSF: against the table-evaluating oracle 1e-5 (FP32) and
+1e-3 (BF16 table); against quadrature, the table's own interpolation error
+(table oracle vs quadrature oracle, which a PSF doubles since it is a
+product of two operators) plus the same bar.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_03302_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _fftt():
+    from paper_1908_03302_amd import fftt
+    return fftt
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+SIGMA = 5e-9
+TOL = {"FP32": 1e-5, "FP32_BF16TABLE": 1e-3}
+
+
+def ragged_workload():
+    """Grid that is not a multiple of the 4^3 tile, masked, two bands."""
+    g = I.centred_grid((37, 29, 11), 1.0e-3)
+    tx = I.ring(24, 0.03, 0.0005, phase=0.1)
+    return I.Workload(
+        name="ragged", c0=1500.0, tx=tx, pairs=I.all_ordered_pairs(24), grid=g,
+        mask=I.cylinder_mask(g, 0.02),
+        pulses=[I.sampled_pulse(1e6, 1.0), I.sampled_pulse(2e6, 1.0)],
+        r_max=[I.R_MAX[1e6], I.R_MAX[2e6]], n_table=4096)
+
+
+@pytest.fixture(scope="module")
+def ragged_dense():
+    w = ragged_workload()
+    say("fixture ragged (dense oracle J per band, quadrature and table)")
+    o = oracle.Oracle.from_workload(w)
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    J = [o.block(band=b) for b in range(len(w.pulses))]
+    Jt = [ot.block(band=b) for b in range(len(w.pulses))]
+    ctx = _fftt().context_for_workload(w)
+    ctx.prepare()
+    return w, (J, Jt), ctx
+
+
+def check_psf(got, Jq, Jt, v, cols, bar):
+    """Errors of one PSF (restricted to cols) against the table-evaluating
+    and the quadrature oracle; returns (vs table, vs quadrature, table's own)."""
+    ref_q = sum(Jb[:, cols].T @ Jb[:, v] for Jb in Jq) / SIGMA ** 2
+    ref_t = sum(Jb[:, cols].T @ Jb[:, v] for Jb in Jt) / SIGMA ** 2
+    et, eq, e_tab = rel(got, ref_t), rel(got, ref_q), rel(ref_t, ref_q)
+    assert et < bar
+    assert eq < e_tab + bar
+    return et, eq, e_tab
+
+
+@pytest.mark.parametrize("prec_name", ["FP32", "FP32_BF16TABLE"])
+@pytest.mark.parametrize("wpb", [16, 1])
+def test_psf_batch_ragged_two_bands(ragged_dense, prec_name, wpb):
+    """70 PSFs (three blocks of 32 right-hand sides, the last partial) on a
+    masked grid with ragged tiles and two bands; inactive voxels are 0."""
+    w, (J, Jt), ctx = ragged_dense
+    f = _fftt()
+    prec = getattr(f, prec_name)
+    act = np.flatnonzero(w.mask)
+    vox = np.random.default_rng(5).choice(act, 70, replace=False)
+    ctx.set_tuning(waves_per_block=wpb)
+    try:
+        out = host(ctx.psf(vox, SIGMA, prec=prec)).reshape(len(vox), w.n)
+    finally:
+        ctx.set_tuning(waves_per_block=16)
+    worst = np.zeros(3)
+    for k, v in enumerate(vox):
+        worst = np.maximum(worst, check_psf(out[k], J, Jt, v, slice(None), TOL[prec_name]))
+        assert np.all(out[k][w.mask == 0] == 0.0)
+    say("ragged PSF batch", prec_name, "wpb", wpb,
+        "worst rel err vs table oracle %.2e, vs quadrature %.2e (table's own %.2e)" % tuple(worst))
+
+
+def test_psf_batch_matches_sequential_fp64(ragged_dense):
+    """The batched FP32 PSFs agree with the per-voxel FP64 path (J then J^T)."""
+    w, _, ctx = ragged_dense
+    f = _fftt()
+    vox = np.flatnonzero(w.mask)[[0, 17, 400, 999]]
+    a = host(ctx.psf(vox, SIGMA, prec=f.FP32)).reshape(len(vox), w.n)
+    b = host(ctx.psf(vox, SIGMA, prec=f.FP64)).reshape(len(vox), w.n)
+    for k in range(len(vox)):
+        assert rel(a[k], b[k]) < 1e-5
+
+
+@pytest.fixture(scope="module")
+def ring2d():
+    w = I.ring2d()
+    say("fixture ring2d")
+    ctx = _fftt().context_for_workload(w)
+    ctx.prepare()
+    o = oracle.Oracle.from_workload(w)
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    return w, (o, ot), ctx
+
+
+@pytest.mark.parametrize("prec_name", ["FP32", "FP32_BF16TABLE"])
+def test_psf_batch_512_ring2d_sampled(ring2d, prec_name):
+    """512 PSFs at random active voxels (seed 2) of the 128-element ring on
+    the 256x256x64 grid in one batch.  Four PSFs of voxels within 8 mm of the
+    ring plane are checked against the oracle on a 7x7x3 neighbourhood plus 64
+    random active voxels.  A voxel 23.5 mm or more off the plane is seen by
+    no pair: its smallest detour, over a diameter chord (L = 0.22 m), is
+    2 (sqrt(L^2/4 + z^2) - L/2) = 4.96 mm > R_max = 4.77 mm, so its PSF is
+    exactly 0."""
+    w, (o, ot), ctx = ring2d
+    f = _fftt()
+    prec = getattr(f, prec_name)
+    act = np.flatnonzero(w.mask)
+    vox = np.random.default_rng(2).choice(act, 512, replace=False)
+    out = torch.empty(len(vox) * w.n, dtype=torch.float32, device="cuda:0")
+    ctx.psf(vox, SIGMA, out=out, prec=prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.psf(vox, SIGMA, out=out, prec=prec)
+    torch.cuda.synchronize()
+    say("ring2d 512 PSFs", prec_name, "%.1f ms" % (1e3 * (time.perf_counter() - t0)))
+    out = out.view(len(vox), w.n)
+    nx, ny, nz = w.grid.dims
+    zc = w.grid.origin[2] + (vox // (nx * ny)) * w.grid.spacing[2]
+    far = np.flatnonzero(np.abs(zc) > 0.0235)
+    if far.size:
+        assert float(out[int(far[0])].abs().max()) == 0.0
+    rng = np.random.default_rng(22)
+    for k in np.flatnonzero(np.abs(zc) < 0.008)[:4]:
+        v = int(vox[k])
+        x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
+        near = [xx + nx * (yy + ny * zz)
+                for zz in range(max(z - 1, 0), min(z + 2, nz))
+                for yy in range(max(y - 3, 0), min(y + 4, ny))
+                for xx in range(max(x - 3, 0), min(x + 4, nx))]
+        cols = np.unique(np.concatenate([np.array(near), rng.choice(act, 64, replace=False)]))
+        cols = cols[w.mask[cols] != 0]
+        sel = np.concatenate([[v], cols])
+        got = host(out[k][torch.as_tensor(cols, device="cuda:0")])
+        e = check_psf(got, [o.block(cols=sel)], [ot.block(cols=sel)], 0,
+                      np.arange(1, sel.size), TOL[prec_name])
+        say("ring2d PSF", k, "voxel", v, prec_name,
+            "rel err vs table oracle %.2e, vs quadrature %.2e (table's own %.2e)" % e)
