@@ -1340,8 +1340,7 @@ __global__ __launch_bounds__(64) void k_psf_cols(ApplyArgs A, const int32_t* __r
     }
 }
 
-// H of one entry for every lane (voxel) of the tile, summed over bands with
-// the band's weight column folded in by the caller (one band per call).
+// H of one entry and band for every lane (voxel) of the tile.
 template <class TabT>
 __device__ __forceinline__ float psf_h(const ApplyArgs& A, const TabT* st, const float2* sx,
                                        const Entry& E, int b, float nm1, int lane) {
@@ -1352,53 +1351,153 @@ __device__ __forceinline__ float psf_h(const ApplyArgs& A, const TabT* st, const
     return lookup_x(st + b * A.ntab, table_x(xb, nm1), nm1) * (vs.y * vr.y);
 }
 
+// Entries per chunk of the PSF contraction (H of a chunk is shared in LDS).
+template <int NB>
+constexpr int psf_chunk() { return NB == 1 ? 64 : (NB == 2 ? 32 : (NB == 3 ? 16 : 8)); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Runs of kXcdRun consecutive tiles, which share most of their
+// pairs, go to one XCD (one L2); the runs are dealt out round-robin so that
+// every XCD sees every part of the volume (entry counts vary strongly with
+// the distance from the transducers).  The grid is padded to whole rounds;
+// blocks past the last tile return at once.
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 64;
+
+__device__ __forceinline__ int64_t xcd_tile(int64_t b) {
+    const int64_t x = b % kXcds, i = b / kXcds;
+    return (i / kXcdRun) * (kXcds * kXcdRun) + x * kXcdRun + i % kXcdRun;
+}
+
+inline int64_t xcd_grid(int64_t n) {
+    const int64_t round = (int64_t)kXcds * kXcdRun;
+    return (n + round - 1) / round * round;
+}
+
+// H (and the pair index) of chunk entries c0 .. c0 + CH - 1 into one buffer;
+// the workgroup's waves split the entries.
+template <int NB, int CH, class TabT>
+__device__ __forceinline__ void psf_chunk_h(const ApplyArgs& A, const TabT* st, const float2* sx,
+                                            float* hb, int* pb, int64_t c0, int64_t t0,
+                                            int64_t t1, float nm1, int wave, int W_, int lane) {
+    for (int i = wave; i < CH; i += W_) {
+        const int64_t e = c0 + i;
+        const bool ok = e < t1;
+        const Entry E = A.ents[ok ? e : t0];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            hb[(b * CH + i) * 64 + lane] = ok ? psf_h(A, st, sx, E, b, nm1, lane) : 0.0f;
+        if (lane == 0) pb[i] = ok ? E.p : -1;
+    }
+}
+
 template <int NB, class TabT>
 __global__ __launch_bounds__(1024) void k_psf32(ApplyArgs A, const float* __restrict__ W,
                                                 int64_t ldw, int n, float* __restrict__ out) {
+    constexpr int CH = psf_chunk<NB>();
+    constexpr int HB = NB * CH * 64;   // floats of one H buffer
     const TabT* st = stage_table<TabT>(A, NB);
     float2* sx = staged_tx<TabT>(A, NB);
-    const int64_t a = blockIdx.x;
+    // after the staged distances: two H buffers [NB][CH][64] and two index
+    // buffers [CH] (chunk c in buffer c % 2)
+    float* hbuf = reinterpret_cast<float*>(sx + A.n_tx * 64);
+    int* pbuf = reinterpret_cast<int*>(hbuf + 2 * HB);
+    const int64_t a = xcd_tile(blockIdx.x);
     if (a >= A.n_act) return;
     const int lane = threadIdx.x & 63;
     const LaneVox V = lane_vox(A, a, lane);
-    stage_distances(A, a, V, sx, lane);   // ends with a barrier; none follow
+    stage_distances(A, a, V, sx, lane);
     const int W_ = (int)(blockDim.x >> 6);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int k0 = ((int)blockIdx.y * W_ + wave) * 32;
-    if (k0 >= n) return;
+    const bool active = k0 < n;   // wave-uniform; idle waves still help with H
     const float nm1 = (float)(A.ntab - 1);
     const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
     const int col = lane & 31;
-    const bool upper = lane >= 32;
+    const int up = lane >> 5;
     f32x16 c_lo = {}, c_hi = {};
-    for (int64_t e = t0; e < t1; e += 2) {
-        const bool pair = e + 1 < t1;
-        const Entry E0 = A.ents[e];
-        const Entry E1 = A.ents[pair ? e + 1 : e];
-        // B operand: lanes 0-31 row e, lanes 32-63 row e+1 (zero past the end)
-        const int p = upper ? E1.p : E0.p;
+    if (t0 < t1)
+        psf_chunk_h<NB, CH>(A, st, sx, hbuf, pbuf, t0, t0, t1, nm1, wave, W_, lane);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t c0 = t0; c0 < t1; c0 += CH, buf ^= 1) {
+        const float* hb = hbuf + buf * HB;
+        const int* pb = pbuf + buf * CH;
+        // this chunk's weights (requested first), the next chunk's H (into
+        // the other buffer), then this chunk's matrix-core steps
+        float bw[NB][CH / 2];
+        if (active) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            float bw = W[((int64_t)b * A.M + p) * ldw + k0 + col];
-            bw = (upper && !pair) ? 0.0f : bw;
-            const float h0 = psf_h(A, st, sx, E0, b, nm1, lane);
-            const float h1 = psf_h(A, st, sx, E1, b, nm1, lane);
-            // A operands: x = [h0(0..31), h1(0..31)] for voxels 0-31,
-            // y = [h0(32..63), h1(32..63)] for voxels 32-63
-            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(h0),
-                                                             __float_as_uint(h1), false, false);
-            c_lo = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(sw[0]), bw, c_lo, 0, 0, 0);
-            c_hi = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(sw[1]), bw, c_hi, 0, 0, 0);
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int j = 0; j < CH / 2; ++j) {
+                    // unconditional load (row 0 for padding), selected after,
+                    // so the loads stay in flight together
+                    const int p = pb[2 * j + up];
+                    const float v = W[((int64_t)b * A.M + max(p, 0)) * ldw + k0 + col];
+                    bw[b][j] = p >= 0 ? v : 0.0f;
+                }
         }
+        if (c0 + CH < t1)
+            psf_chunk_h<NB, CH>(A, st, sx, hbuf + (buf ^ 1) * HB, pbuf + (buf ^ 1) * CH, c0 + CH,
+                                t0, t1, nm1, wave, W_, lane);
+        if (active) {
+            // A of voxels 0-31: lanes 0-31 entry 2j, lanes 32-63 entry 2j+1;
+            // voxels 32-63 likewise, 32 floats further on.  The operands of
+            // the next group of K-steps are read while the current group's
+            // matrix-core steps run.
+            constexpr int KS = CH / 2, G = KS < 8 ? KS : 8;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float* hb0 = hb + b * CH * 64 + up * 64 + col;
+                float al[G], ah[G];
+#pragma unroll
+                for (int jj = 0; jj < G; ++jj) {
+                    al[jj] = hb0[2 * jj * 64];
+                    ah[jj] = hb0[2 * jj * 64 + 32];
+                }
+#pragma unroll
+                for (int g = 0; g < KS / G; ++g) {
+                    float nl[G], nh[G];
+                    if (g + 1 < KS / G) {
+#pragma unroll
+                        for (int jj = 0; jj < G; ++jj) {
+                            nl[jj] = hb0[2 * ((g + 1) * G + jj) * 64];
+                            nh[jj] = hb0[2 * ((g + 1) * G + jj) * 64 + 32];
+                        }
+                    }
+                    // keep the reads above and the matrix-core steps below in
+                    // this order (the scheduler would otherwise sink each read
+                    // to its use and expose its latency)
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int jj = 0; jj < G; ++jj) {
+                        c_lo = __builtin_amdgcn_mfma_f32_32x32x2f32(al[jj], bw[b][g * G + jj],
+                                                                    c_lo, 0, 0, 0);
+                        c_hi = __builtin_amdgcn_mfma_f32_32x32x2f32(ah[jj], bw[b][g * G + jj],
+                                                                    c_hi, 0, 0, 0);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (g + 1 < KS / G) {
+#pragma unroll
+                        for (int jj = 0; jj < G; ++jj) {
+                            al[jj] = nl[jj];
+                            ah[jj] = nh[jj];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
     }
     // D layout of the 32x32 block: register q of lane l holds row
     // 8 (q / 4) + 4 (l / 32) + q % 4, column l % 32.
-    if (k0 + col >= n) return;
+    if (!active || k0 + col >= n) return;
     float* __restrict__ o = out + (int64_t)(k0 + col) * A.g.dims[0] * A.g.dims[1] * A.g.dims[2];
     const int64_t t = A.tiles[a];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const int i = 8 * (q / 4) + 4 * (lane >> 5) + (q & 3);
+        const int i = 8 * (q / 4) + 4 * up + (q & 3);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             bool inside, act;
@@ -1407,6 +1506,14 @@ __global__ __launch_bounds__(1024) void k_psf32(ApplyArgs A, const float* __rest
             if (inside) o[vidx] = act ? (h ? c_hi[q] : c_lo[q]) : 0.0f;
         }
     }
+}
+
+size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
+    const size_t tbytes = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
+    const int ch = nb == 1 ? psf_chunk<1>()
+                 : (nb == 2 ? psf_chunk<2>() : (nb == 3 ? psf_chunk<3>() : psf_chunk<4>()));
+    return ((tbytes + 15) & ~(size_t)15) + (size_t)n_tx * 64 * sizeof(float2) +
+           2 * ((size_t)nb * ch * 64 * sizeof(float) + (size_t)ch * sizeof(int));
 }
 
 template <int NB>
@@ -1424,8 +1531,7 @@ static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
     if (err != hipSuccess || a.n_act == 0) return err;
     const int wpb = a.waves_per_block;
     const unsigned nbat = (unsigned)((n + 32 * wpb - 1) / (32 * wpb));
-    const size_t tbytes = (size_t)NB * a.ntab * staged_entry_bytes(tabfmt);
-    const size_t lds = ((tbytes + 15) & ~(size_t)15) + (size_t)a.n_tx * 64 * sizeof(float2);
+    const size_t lds = psf_lds_bytes(NB, a.ntab, tabfmt, a.n_tx);
     auto run = [&](auto kern) -> hipError_t {
         if (lds > 65536) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -1433,8 +1539,8 @@ static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
                                                (int)lds);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(kern, dim3((unsigned)a.n_act, nbat), dim3(64 * wpb), lds, s, a, W,
-                           ldw, n, out);
+        const unsigned grid = (unsigned)xcd_grid(a.n_act);
+        hipLaunchKernelGGL(kern, dim3(grid, nbat), dim3(64 * wpb), lds, s, a, W, ldw, n, out);
         return hipGetLastError();
     };
     switch (tabfmt) {
@@ -1457,9 +1563,6 @@ hipError_t launch_psf(hipStream_t s, int tabfmt, const ApplyArgs& a, const int32
     return hipErrorInvalidValue;
 }
 
-size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
-    const size_t tbytes = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
-    return ((tbytes + 15) & ~(size_t)15) + (size_t)n_tx * 64 * sizeof(float2);
-}
+
 
 }  // namespace fftt
