@@ -8,30 +8,62 @@ inputs resident in HBM.  value = pair-voxel kernel evaluations per second
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 Prints one JSON line.  Extra fields: roofline of the dominant kernel (from
-HIP events recorded on the launch stream), CPU-oracle baseline on a bounded
-sample, and CG time to a fixed misfit for the mixed and FP64 paths.
+HIP events recorded on the launch stream; HBM traffic from the committed
+counter summary while the kernel source is unchanged), CPU-oracle baseline
+on a bounded sample, and the other workloads on the same GPU: CG time to a
+fixed misfit for the mixed and FP64 paths (128-ring and 32-ring), the
+four-band operators, and 512 batched point-spread functions.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOPS_PER_PV = 32          # 23 + B (7 + 2 Rh) with one band, one right-hand side
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (and FP32 matrix) peak
+KERNEL_SRC = os.path.join(ROOT, "paper_1908_03302_amd", "csrc", "kernels.hip")
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "ring128_J_JT_hbm_counters.md")
+
+
+def flops_per_pv(bands, rhs):
+    """Algorithmic flops per pair-voxel evaluation: two distances (20), the
+    detour (2), 1/(R_xs R_xr) (1), per band the interpolation and scale (7)
+    and per band and right-hand side one FMA (2)."""
+    return 23 + bands * (7 + 2 * rhs)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the counter summary, or None if
+    the summary is missing or was taken with a different kernel source."""
+    try:
+        text = open(TRAFFIC_MD).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel source sha256\[:16\]: ([0-9a-f]{16})", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"^\| %s \|[^\n]*?\| ([0-9.]+) GB \|" % re.escape(kernel), text, re.M)
+    return float(m.group(1)) * 1e9 if m else None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, budget_s=15.0):
+def cpu_baseline(w, budget_s=30.0):
     """FP64 oracle on a bounded sample of rows of J (whole grid per row)."""
     import numpy as np
     import oracle
@@ -74,6 +106,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-misfit legs")
+    ap.add_argument("--no-psf", action="store_true", help="skip the batched PSF leg")
+    ap.add_argument("--no-multiband", action="store_true", help="skip the four-band leg")
     ap.add_argument("--cg-iters", type=int, default=20)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
@@ -140,9 +174,10 @@ def main():
     value = 2.0 * pv * args.steps / (ms * 1e-3)
     avg_j, avg_jt = ms_j / n_j, ms_jt / n_jt
     sfx = "s" if staged else ""
-    dom, avg = (("J^T kernel (k_jt32%s)" % sfx, avg_jt) if avg_jt >= avg_j
-                else ("J kernel (k_j32%s)" % sfx, avg_j))
-    achieved = pv * FLOPS_PER_PV / (avg * 1e-3) / 1e12
+    dom, avg = (("k_jt32%s" % sfx, avg_jt) if avg_jt >= avg_j else ("k_j32%s" % sfx, avg_j))
+    fpv = flops_per_pv(1, 1)
+    achieved = pv * fpv / (avg * 1e-3) / 1e12
+    traffic = recorded_traffic(dom)
     log("bench: %.3f ms/step, J %.3f ms, J^T %.3f ms, reduce %.3f ms"
         % (ms_step, avg_j, avg_jt, ms_red / max(n_red, 1)))
 
@@ -165,15 +200,92 @@ def main():
         "kernels_ms": {"J": avg_j, "JT": avg_jt, "J_reduce": ms_red / max(n_red, 1)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "flops_per_pv": FLOPS_PER_PV},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "flops_per_pv": fpv, "pv_per_launch": pv,
+                     "launch_ms": avg, "kernel_source": kernel_source_hash()},
     }
     if not args.no_cg:
         out["cg"] = cg_time_to_misfit(ctx, w, fftt, torch, args.cg_iters)
+        ws = I.small_fp64()
+        cs = fftt.context_for_workload(ws, device=0)
+        cs.prepare()
+        out["cg_small"] = cg_time_to_misfit(cs, ws, fftt, torch, ws.extra["cg_iters"])
+        out["cg_small"]["workload"] = ws.name
+        del cs
+    if not args.no_psf:
+        out["psf"] = psf_leg(ctx, w, fftt, torch, pv)
+    del dc, dT, dc2
+    if not args.no_multiband:
+        out["multiband"] = multiband_leg(fftt, torch)
     if not args.no_cpu:
         log("bench: CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
+
+
+def psf_leg(ctx, w, fftt, torch, pv, reps=3):
+    """512 point-spread functions J^T J e_k / sigma^2 at random active voxels
+    (seed 2) in one batch; FP32 and BF16 table.  Roofline of the batched
+    kernel against the FP32 matrix peak: pv x (23 + 7 + 2 x 512) flops."""
+    from paper_1908_03302_amd import inputs as I
+    vox = I.pick_voxels(w.mask, 512, seed=2)
+    out = torch.empty(len(vox) * w.n, dtype=torch.float32, device="cuda:0")
+    res = {"n_psf": len(vox), "voxels_seed": 2, "noise_sigma": w.noise_sigma}
+    fpv = flops_per_pv(1, len(vox))
+    for name, prec in (("fp32", fftt.FP32), ("bf16_table", fftt.FP32_BF16TABLE)):
+        ctx.psf(vox, w.noise_sigma, out=out, prec=prec)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.psf(vox, w.noise_sigma, out=out, prec=prec)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps * 1e3
+        kms, nl = ctx.kernel_time(3)
+        ctx.profile(False)
+        kms /= nl
+        tf = pv * fpv / (kms * 1e-3) / 1e12
+        res[name] = {"ms": wall, "kernel_ms": kms, "psf_per_s": len(vox) / (wall * 1e-3),
+                     "pv_rhs_per_s": pv * len(vox) / (wall * 1e-3),
+                     "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_FP32_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS,
+                                  "flops_per_pv": fpv}}
+        log("bench: 512 PSFs %s: %.1f ms (kernels %.1f ms), %.1f TFLOP/s"
+            % (name, wall, kms, tf))
+    del out
+    return res
+
+
+def multiband_leg(fftt, torch, reps=10):
+    """J and J^T with four bands (0.5, 1, 1.5, 2 MHz) in one launch on the
+    128-ring grid: every pv with a detour below the largest R_max evaluates
+    all four tables, 23 + 4 (7 + 2) flops."""
+    from paper_1908_03302_amd import inputs as I
+    w = I.multiband()
+    ctx = fftt.context_for_workload(w, device=0)
+    ctx.prepare()
+    pv, lanes = ctx.work_count()
+    dev = torch.device("cuda:0")
+    dc = torch.tensor(w.model, dtype=torch.float32, device=dev)
+    dT = torch.empty(4 * w.m, dtype=torch.float32, device=dev)
+    dc2 = torch.empty(w.n, dtype=torch.float32, device=dev)
+    for _ in range(2):
+        ctx.apply_J(dc, dT)
+        ctx.apply_JT(dT, dc2)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.apply_J(dc, dT)
+        ctx.apply_JT(dT, dc2)
+    j, jt = ctx.kernel_time(0), ctx.kernel_time(1)
+    ctx.profile(False)
+    ms_j, ms_jt = j[0] / j[1], jt[0] / jt[1]
+    fpv = flops_per_pv(4, 1)
+    log("bench: four bands: pv %d, J %.3f ms, J^T %.3f ms" % (pv, ms_j, ms_jt))
+    return {"workload": w.name, "bands": 4, "pv_per_apply": pv, "J_ms": ms_j, "JT_ms": ms_jt,
+            "pv_per_s": 2 * pv / ((ms_j + ms_jt) * 1e-3), "flops_per_pv": fpv,
+            "J_tflops": pv * fpv / (ms_j * 1e-3) / 1e12,
+            "JT_tflops": pv * fpv / (ms_jt * 1e-3) / 1e12}
 
 
 def cg_time_to_misfit(ctx, w, fftt, torch, iters):
