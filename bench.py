@@ -2,8 +2,11 @@
 
 One step = one J dc plus one J^T dT on the 128-element ring / 256x256x64
 grid workload (1 MHz pulse, 0.5-1.5 MHz band, 4096-entry FP32 table),
-inputs resident in HBM.  value = pair-voxel kernel evaluations per second
-(pv counted exactly: pairs x active voxels with detour below R_max).
+inputs resident in HBM.  value = pair-voxel terms of the two products per
+second over all ordered pairs (pv counted exactly: pairs x active voxels with
+detour below R_max); the kernels evaluate a pair and its reverse once
+(reciprocity), reported as value_evaluated, with the step re-timed with every
+ordered pair evaluated under reciprocity_off.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -134,9 +137,9 @@ def main():
     staged = args.staged is None or args.staged == 1
     t0 = time.perf_counter()
     ctx.prepare()
-    pv, lanes = ctx.work_count()
-    log("bench: prepare %.2f s, pv %d, lanes %d (%.1f%% useful)"
-        % (time.perf_counter() - t0, pv, lanes, 100.0 * pv / max(lanes, 1)))
+    pv_op, pv, lanes = ctx.work_count()
+    log("bench: prepare %.2f s, operator pv %d, evaluated pv %d, lanes %d (%.1f%% useful)"
+        % (time.perf_counter() - t0, pv_op, pv, lanes, 100.0 * pv / max(lanes, 1)))
     dev = torch.device("cuda:0")
     dc = torch.tensor(w.model, dtype=torch.float32, device=dev)
     dT = torch.empty(w.m, dtype=torch.float32, device=dev)
@@ -153,26 +156,32 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    ms_j, n_j = ctx.kernel_time(0)
-    ms_jt, n_jt = ctx.kernel_time(1)
-    ms_red, n_red = ctx.kernel_time(2)
-    ctx.profile(False)
-    ms_step = ms / args.steps
-    value = 2.0 * pv * args.steps / (ms * 1e-3)
-    avg_j, avg_jt = ms_j / n_j, ms_jt / n_jt
+    def timed(steps, warmup):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        kt = [ctx.kernel_time(k) for k in range(3)]
+        ctx.profile(False)
+        return ms / steps, [t / max(n, 1) for t, n in kt]
+
+    ms_step, (avg_j, avg_jt, avg_red) = timed(args.steps, args.warmup)
+    ms = ms_step * args.steps
+    # value: whole-job throughput, the pair-voxel terms of J dc and J^T dT over
+    # every ordered pair per second.  A pair and its reverse share one row of
+    # J (reciprocity), so the kernels evaluate pv_evaluated of them; that rate
+    # is value_evaluated, and the roofline counts only evaluated work.
+    value = 2.0 * pv_op * args.steps / (ms * 1e-3)
+    ms_red, n_red = avg_red, 1
     sfx = "s" if staged else ""
     dom, avg = (("k_jt32%s" % sfx, avg_jt) if avg_jt >= avg_j else ("k_j32%s" % sfx, avg_j))
     fpv = flops_per_pv(1, 1)
@@ -196,7 +205,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "pairs": w.m, "voxels": w.n,
                    "active_voxels": int(w.mask.sum()), "bands": 1, "table": w.n_table,
-                   "pv_per_apply": pv, "step": "1 J + 1 J^T"},
+                   "pv_per_apply": pv_op, "pv_evaluated_per_apply": pv,
+                   "reciprocity": True, "step": "1 J + 1 J^T"},
+        "value_evaluated": 2.0 * pv / (ms_step * 1e-3),
         "kernels_ms": {"J": avg_j, "JT": avg_jt, "J_reduce": ms_red / max(n_red, 1)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -204,6 +215,18 @@ def main():
                      "flops_per_pv": fpv, "pv_per_launch": pv,
                      "launch_ms": avg, "kernel_source": kernel_source_hash()},
     }
+    # the same step with every ordered pair evaluated
+    ctx.set_tuning(reciprocity=0)
+    ctx.prepare()
+    pv_off = ctx.work_count()[1]
+    ms_off, (j_off, jt_off, red_off) = timed(max(args.steps // 2, 1), 2)
+    ctx.set_tuning(reciprocity=1)
+    ctx.prepare()
+    out["reciprocity_off"] = {"ms_per_step": ms_off, "value": 2.0 * pv_op / (ms_off * 1e-3),
+                              "pv_evaluated_per_apply": pv_off,
+                              "kernels_ms": {"J": j_off, "JT": jt_off, "J_reduce": red_off}}
+    log("bench: every ordered pair evaluated: %.3f ms/step, J %.3f ms, J^T %.3f ms"
+        % (ms_off, j_off, jt_off))
     if not args.no_cg:
         out["cg"] = cg_time_to_misfit(ctx, w, fftt, torch, args.cg_iters)
         ws = I.small_fp64()
@@ -264,7 +287,7 @@ def multiband_leg(fftt, torch, reps=10):
     w = I.multiband()
     ctx = fftt.context_for_workload(w, device=0)
     ctx.prepare()
-    pv, lanes = ctx.work_count()
+    _, pv, lanes = ctx.work_count()
     dev = torch.device("cuda:0")
     dc = torch.tensor(w.model, dtype=torch.float32, device=dev)
     dT = torch.empty(4 * w.m, dtype=torch.float32, device=dev)
@@ -281,8 +304,9 @@ def multiband_leg(fftt, torch, reps=10):
     ctx.profile(False)
     ms_j, ms_jt = j[0] / j[1], jt[0] / jt[1]
     fpv = flops_per_pv(4, 1)
-    log("bench: four bands: pv %d, J %.3f ms, J^T %.3f ms" % (pv, ms_j, ms_jt))
-    return {"workload": w.name, "bands": 4, "pv_per_apply": pv, "J_ms": ms_j, "JT_ms": ms_jt,
+    log("bench: four bands: evaluated pv %d, J %.3f ms, J^T %.3f ms" % (pv, ms_j, ms_jt))
+    return {"workload": w.name, "bands": 4, "pv_evaluated_per_apply": pv, "J_ms": ms_j,
+            "JT_ms": ms_jt,
             "pv_per_s": 2 * pv / ((ms_j + ms_jt) * 1e-3), "flops_per_pv": fpv,
             "J_tflops": pv * fpv / (ms_j * 1e-3) / 1e12,
             "JT_tflops": pv * fpv / (ms_jt * 1e-3) / 1e12}

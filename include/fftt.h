@@ -108,10 +108,15 @@ fftt_status fftt_build_table_from_pulse(double c0, const double *f, int64_t nt,
  * Synchronises the stream. */
 fftt_status fftt_prepare(fftt_ctx *ctx);
 
-/* Work counts after prepare: pv = number of (pair, active voxel) combinations
- * with detour below the largest r_max (decided in FP64); lanes = evaluation
- * slots the kernels execute per band (>= pv, includes culling slack). */
-fftt_status fftt_work_count(fftt_ctx *ctx, int64_t *pv, int64_t *lanes);
+/* Work counts after prepare: pv = number of (pair, active voxel)
+ * combinations of the operator with detour below the largest r_max (decided
+ * in FP64, over the caller's pairs); pv_evaluated = the same over the pairs
+ * the kernels evaluate (pairs with identical rows of J are evaluated once,
+ * see FFTT_TUNE_RECIPROCITY); lanes = evaluation slots the kernels execute
+ * per band (>= pv_evaluated, includes culling slack).  Any pointer may be
+ * NULL. */
+fftt_status fftt_work_count(fftt_ctx *ctx, int64_t *pv, int64_t *pv_evaluated,
+                            int64_t *lanes);
 
 /* dT = J dc (eq. forward_compact) for n_rhs right-hand sides.
  *   dc: device [n_rhs][N];  dT: device [n_rhs][B][M] (overwritten). */
@@ -187,11 +192,17 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *   FFTT_TUNE_STAGED_TABLE: table layout of the staged FP32 kernels:
  *     0 (default) = one float per node (4 bytes), 1 = (h_k, h_{k+1} - h_k)
  *     pairs (8 bytes per node, fewer instructions, more LDS).
+ *   FFTT_TUNE_RECIPROCITY: 1 (default) = a pair (s, r) and its reverse
+ *     (r, s) have the same row of J (source-receiver reciprocity, Sec. II-B;
+ *     the detour and L are symmetric), so each unordered pair is evaluated
+ *     once: J writes the row to both, J^T uses the summed data; 0 = every
+ *     ordered pair is evaluated (only exact repeats share a row).  Outputs
+ *     agree within rounding; changing it re-runs the set-up on next use.
  * FFTT_E_INVALID for other keys or values. */
 enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_J = 2,
        FFTT_TUNE_SPLIT_JT = 3, FFTT_TUNE_SPLIT_J = 4, FFTT_TUNE_STAGED = 5,
        FFTT_TUNE_UNROLL_JT_STAGED = 6, FFTT_TUNE_UNROLL_J_STAGED = 7,
-       FFTT_TUNE_STAGED_TABLE = 8 };
+       FFTT_TUNE_STAGED_TABLE = 8, FFTT_TUNE_RECIPROCITY = 9 };
 fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
 
 /* Measurement aid.  With enable != 0 every launch of the main operator

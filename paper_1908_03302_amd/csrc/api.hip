@@ -98,6 +98,65 @@ fftt_status upload_tables(fftt_ctx* c) {
     return FFTT_OK;
 }
 
+// Kernel pairs from the caller's pairs.  Rows of J depend on the pair only
+// through R_xs + R_xr - L and L, both symmetric in source and receiver
+// (source-receiver reciprocity), so with reciprocity on, (s, r) and (r, s)
+// -- and repeats -- form one group evaluated once; with it off, only
+// repeats of the same ordered pair are grouped.
+fftt_status build_pairs(fftt_ctx* c) {
+    const int64_t M = c->M;
+    const int32_t* pin = c->pairs_in.data();
+    auto key = [&](int64_t i) {
+        const int32_t s = pin[2 * i], r = pin[2 * i + 1];
+        return c->reciprocity ? std::make_pair(std::min(s, r), std::max(s, r))
+                              : std::make_pair(s, r);
+    };
+    std::vector<int32_t> order(M);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return key(x) < key(y); });
+    c->ps.clear();
+    c->pr.clear();
+    c->kptr.assign(1, 0);
+    c->kidx = order;
+    for (int64_t i = 0; i < M; ++i) {
+        if (i == 0 || key(order[i]) != key(order[i - 1])) {
+            c->ps.push_back(key(order[i]).first);
+            c->pr.push_back(key(order[i]).second);
+            if (i) c->kptr.push_back((int32_t)i);
+        }
+    }
+    c->kptr.push_back((int32_t)M);
+    const int64_t Mk = (int64_t)c->ps.size();
+    c->Mk = Mk;
+    c->L.resize(Mk);
+    c->C.resize(Mk);
+    const double c0 = c->c0;
+    for (int64_t k = 0; k < Mk; ++k) {
+        const double* a = c->tx.data() + 3 * c->ps[k];
+        const double* b = c->tx.data() + 3 * c->pr[k];
+        const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+        c->L[k] = std::sqrt(dx * dx + dy * dy + dz * dz);
+        c->C[k] = -c->L[k] * c->dV / (2.0 * M_PI * c0 * c0 * c0);
+    }
+    FFTT_HIP(c, c->d_ps.alloc(Mk * sizeof(int32_t)));
+    FFTT_HIP(c, c->d_pr.alloc(Mk * sizeof(int32_t)));
+    FFTT_HIP(c, c->d_kptr.alloc((Mk + 1) * sizeof(int32_t)));
+    FFTT_HIP(c, c->d_kidx.alloc(M * sizeof(int32_t)));
+    FFTT_HIP(c, c->d_L.alloc(Mk * sizeof(double)));
+    FFTT_HIP(c, c->d_C.alloc(Mk * sizeof(double)));
+    FFTT_HIP(c, hipMemcpy(c->d_ps.p, c->ps.data(), Mk * sizeof(int32_t), hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_pr.p, c->pr.data(), Mk * sizeof(int32_t), hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_kptr.p, c->kptr.data(), (Mk + 1) * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_kidx.p, c->kidx.data(), M * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_L.p, c->L.data(), Mk * sizeof(double), hipMemcpyHostToDevice));
+    FFTT_HIP(c, hipMemcpy(c->d_C.p, c->C.data(), Mk * sizeof(double), hipMemcpyHostToDevice));
+    c->lists_ok = false;
+    return FFTT_OK;
+}
+
 ApplyArgs base_args(const fftt_ctx* c) {
     ApplyArgs a{};
     a.tiles = c->d_tiles.as<int32_t>();
@@ -107,7 +166,7 @@ ApplyArgs base_args(const fftt_ctx* c) {
     a.txc = c->d_txc.as<TxConst>();
     a.n_tx = c->n_tx;
     a.nnz = c->nnz;
-    a.M = c->M;
+    a.M = c->Mk;
     a.g = c->g;
     a.mask = c->d_mask.as<uint8_t>();
     a.nb = c->nb;
@@ -125,7 +184,7 @@ ApplyArgs base_args(const fftt_ctx* c) {
 
 fftt_status build_lists(fftt_ctx* c) {
     const int64_t n_act = (int64_t)c->act_tiles.size();
-    const int64_t n_tx = c->n_tx, M = c->M;
+    const int64_t n_tx = c->n_tx, M = c->Mk;
     const double r_cut = r_max_all(c) + 1e-7;
     hipStream_t s = c->stream;
     c->lists_ok = false;
@@ -185,18 +244,21 @@ fftt_status build_lists(fftt_ctx* c) {
                                   c->d_desc.p));
     c->nnz = nnz;
 
-    // exact work count (FP64 decision R < R_max)
+    // exact work counts (FP64 decision R < R_max): over caller pairs and
+    // over the evaluated kernel pairs
     DevBuf pvb;
-    FFTT_HIP(c, pvb.alloc(sizeof(unsigned long long)));
-    FFTT_HIP(c, hipMemsetAsync(pvb.p, 0, sizeof(unsigned long long), s));
+    FFTT_HIP(c, pvb.alloc(2 * sizeof(unsigned long long)));
+    FFTT_HIP(c, hipMemsetAsync(pvb.p, 0, 2 * sizeof(unsigned long long), s));
     ApplyArgs a = base_args(c);
     FFTT_HIP(c, launch_count_pv(s, a, r_max_all(c), c->d_L.as<double>(), c->d_ps.as<int32_t>(),
                                 c->d_pr.as<int32_t>(), c->d_tx.as<double>(),
-                                pvb.as<unsigned long long>(), nullptr));
-    unsigned long long pv = 0;
-    FFTT_HIP(c, hipMemcpyAsync(&pv, pvb.p, sizeof(pv), hipMemcpyDeviceToHost, s));
+                                c->d_kptr.as<int32_t>(), pvb.as<unsigned long long>(),
+                                pvb.as<unsigned long long>() + 1));
+    unsigned long long pv[2] = {0, 0};
+    FFTT_HIP(c, hipMemcpyAsync(pv, pvb.p, sizeof(pv), hipMemcpyDeviceToHost, s));
     FFTT_HIP(c, hipStreamSynchronize(s));
-    c->pv = (int64_t)pv;
+    c->pv = (int64_t)pv[0];
+    c->pv_eval = (int64_t)pv[1];
     c->lanes = nnz * kTileVox;
     c->lists_rcut = r_cut;
     c->lists_ok = true;
@@ -267,8 +329,8 @@ fftt_status psf_batched(fftt_ctx* c, fftt_precision prec, const int64_t* voxels,
     FFTT_HIP(c, c->d_psfd.alloc(desc.size() * sizeof(int32_t)));
     FFTT_HIP(c, hipMemcpyAsync(c->d_psfd.p, desc.data(), desc.size() * sizeof(int32_t),
                                hipMemcpyHostToDevice, c->stream));
-    FFTT_HIP(c, c->d_psfw.alloc((size_t)c->nb * c->M * ldw * sizeof(float)));
-    FFTT_HIP(c, launch_fill(c->stream, false, c->d_psfw.p, (int64_t)c->nb * c->M * ldw));
+    FFTT_HIP(c, c->d_psfw.alloc((size_t)c->nb * c->Mk * ldw * sizeof(float)));
+    FFTT_HIP(c, launch_fill(c->stream, false, c->d_psfw.p, (int64_t)c->nb * c->Mk * ldw));
     FFTT_HIP(c, launch_fill(c->stream, false, out, (int64_t)n * c->N));
     ApplyArgs a = base_args(c);
     const int fmt = staged_table(c, prec);
@@ -277,7 +339,8 @@ fftt_status psf_batched(fftt_ctx* c, fftt_precision prec, const int64_t* voxels,
     hipEvent_t stop;
     FFTT_HIP(c, prof_begin(c, 3, &stop));
     FFTT_HIP(c, launch_psf(c->stream, fmt, a, c->d_psfd.as<int32_t>(),
-                           c->d_psfd.as<int32_t>() + n, c->d_C.as<double>(), s2,
+                           c->d_psfd.as<int32_t>() + n, c->d_C.as<double>(),
+                           c->d_kptr.as<int32_t>(), s2,
                            c->d_psfw.as<float>(), ldw, n, out, col_tab));
     FFTT_HIP(c, prof_end(c, stop));
     // the host descriptor buffer must outlive the asynchronous copy
@@ -308,9 +371,12 @@ fftt_status apply_J_one(fftt_ctx* c, fftt_precision prec, const void* x, void* y
     }
     FFTT_HIP(c, prof_end(c, stop));
     FFTT_HIP(c, prof_begin(c, 2, &stop));
+    const int S = reduce_slices(c->Mk, c->n_cu);
+    FFTT_HIP(c, c->d_red.alloc((size_t)c->nb * S * std::max<int64_t>(c->Mk, 1) * sizeof(double)));
     FFTT_HIP(c, launch_reduce(c->stream, fp64, c->d_part.p, c->nnz, c->d_gptr.as<int64_t>(),
-                              c->d_desc.p, c->d_C.as<double>(), c->d_porig.as<int32_t>(), c->M,
-                              c->nb, y));
+                              c->d_desc.p, c->d_C.as<double>(), c->d_kptr.as<int32_t>(),
+                              c->d_kidx.as<int32_t>(), c->Mk, c->M, c->nb, S,
+                              c->d_red.as<double>(), y));
     FFTT_HIP(c, prof_end(c, stop));
     return FFTT_OK;
 }
@@ -319,13 +385,14 @@ fftt_status apply_J_one(fftt_ctx* c, fftt_precision prec, const void* x, void* y
 fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* x) {
     const bool fp64 = prec == FFTT_FP64;
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
-    FFTT_HIP(c, c->d_w.alloc((size_t)c->nb * c->M * es));
+    FFTT_HIP(c, c->d_w.alloc((size_t)c->nb * c->Mk * es));
     ApplyArgs a = base_args(c);
     a.tab = fp64 ? c->d_tab64.p : (prec == FFTT_FP32 ? c->d_tab32.p : c->d_tabbf.p);
     a.w = c->d_w.p;
     a.out = x;
-    FFTT_HIP(c, launch_weights(c->stream, fp64, y, c->d_porig.as<int32_t>(), c->d_C.as<double>(),
-                               c->M, c->nb, c->d_w.p));
+    FFTT_HIP(c, launch_weights(c->stream, fp64, y, c->d_kptr.as<int32_t>(),
+                               c->d_kidx.as<int32_t>(), c->d_C.as<double>(), c->Mk, c->M, c->nb,
+                               c->d_w.p));
     FFTT_HIP(c, launch_fill(c->stream, fp64, x, c->N));
     hipEvent_t stop;
     FFTT_HIP(c, prof_begin(c, 1, &stop));
@@ -455,28 +522,8 @@ fftt_status fftt_set_geometry(fftt_ctx* c, double c0, const double* tx_xyz, int6
     c->M = n_pairs;
     c->N = N;
     c->tx.assign(tx_xyz, tx_xyz + 3 * n_tx);
-    std::vector<int32_t> order(n_pairs);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-        if (pairs[2 * x] != pairs[2 * y]) return pairs[2 * x] < pairs[2 * y];
-        return pairs[2 * x + 1] < pairs[2 * y + 1];
-    });
-    c->ps.resize(n_pairs);
-    c->pr.resize(n_pairs);
-    c->porig = order;
-    c->L.resize(n_pairs);
-    c->C.resize(n_pairs);
+    c->pairs_in.assign(pairs, pairs + 2 * n_pairs);
     c->dV = spacing[0] * spacing[1] * spacing[2];
-    for (int64_t i = 0; i < n_pairs; ++i) {
-        const int32_t o = order[i];
-        c->ps[i] = pairs[2 * o];
-        c->pr[i] = pairs[2 * o + 1];
-        const double* a = tx_xyz + 3 * c->ps[i];
-        const double* b = tx_xyz + 3 * c->pr[i];
-        const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
-        c->L[i] = std::sqrt(dx * dx + dy * dy + dz * dz);
-        c->C[i] = -c->L[i] * c->dV / (2.0 * M_PI * c0 * c0 * c0);
-    }
     for (int k = 0; k < 3; ++k) {
         c->g.dims[k] = dims[k];
         c->g.origin[k] = origin[k];
@@ -496,29 +543,16 @@ fftt_status fftt_set_geometry(fftt_ctx* c, double c0, const double* tx_xyz, int6
         if (tact[t]) c->act_tiles.push_back((int32_t)t);
 
     FFTT_HIP(c, c->d_tx.alloc(c->tx.size() * sizeof(double)));
-    FFTT_HIP(c, c->d_ps.alloc(n_pairs * sizeof(int32_t)));
-    FFTT_HIP(c, c->d_pr.alloc(n_pairs * sizeof(int32_t)));
-    FFTT_HIP(c, c->d_porig.alloc(n_pairs * sizeof(int32_t)));
-    FFTT_HIP(c, c->d_L.alloc(n_pairs * sizeof(double)));
-    FFTT_HIP(c, c->d_C.alloc(n_pairs * sizeof(double)));
     FFTT_HIP(c, c->d_mask.alloc((size_t)N));
     FFTT_HIP(c, c->d_tiles.alloc(std::max<size_t>(c->act_tiles.size(), 1) * sizeof(int32_t)));
     FFTT_HIP(c, hipMemcpy(c->d_tx.p, c->tx.data(), c->tx.size() * sizeof(double),
-                          hipMemcpyHostToDevice));
-    FFTT_HIP(c, hipMemcpy(c->d_ps.p, c->ps.data(), n_pairs * sizeof(int32_t),
-                          hipMemcpyHostToDevice));
-    FFTT_HIP(c, hipMemcpy(c->d_pr.p, c->pr.data(), n_pairs * sizeof(int32_t),
-                          hipMemcpyHostToDevice));
-    FFTT_HIP(c, hipMemcpy(c->d_porig.p, c->porig.data(), n_pairs * sizeof(int32_t),
-                          hipMemcpyHostToDevice));
-    FFTT_HIP(c, hipMemcpy(c->d_L.p, c->L.data(), n_pairs * sizeof(double),
-                          hipMemcpyHostToDevice));
-    FFTT_HIP(c, hipMemcpy(c->d_C.p, c->C.data(), n_pairs * sizeof(double),
                           hipMemcpyHostToDevice));
     FFTT_HIP(c, hipMemcpy(c->d_mask.p, c->mask.data(), (size_t)N, hipMemcpyHostToDevice));
     if (!c->act_tiles.empty())
         FFTT_HIP(c, hipMemcpy(c->d_tiles.p, c->act_tiles.data(),
                               c->act_tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    st = build_pairs(c);
+    if (st != FFTT_OK) return st;
     c->has_geom = true;
     return FFTT_OK;
 }
@@ -564,11 +598,12 @@ fftt_status fftt_prepare(fftt_ctx* c) {
     return ensure_ready(c);
 }
 
-fftt_status fftt_work_count(fftt_ctx* c, int64_t* pv, int64_t* lanes) {
+fftt_status fftt_work_count(fftt_ctx* c, int64_t* pv, int64_t* pv_evaluated, int64_t* lanes) {
     if (!c) return FFTT_E_INVALID;
     fftt_status st = ensure_ready(c);
     if (st != FFTT_OK) return st;
     if (pv) *pv = c->pv;
+    if (pv_evaluated) *pv_evaluated = c->pv_eval;
     if (lanes) *lanes = c->lanes;
     return FFTT_OK;
 }
@@ -627,6 +662,18 @@ fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
             if (value != 1 && value != 2 && value != 4 && value != 8)
                 FFTT_BAD(c, "staged unroll must be 1, 2, 4 or 8");
             (key == FFTT_TUNE_UNROLL_J_STAGED ? c->unroll_js : c->unroll_jts) = value;
+            return FFTT_OK;
+        case FFTT_TUNE_RECIPROCITY:
+            if (value != 0 && value != 1) FFTT_BAD(c, "reciprocity must be 0 or 1");
+            if (value != c->reciprocity) {
+                c->reciprocity = value;
+                if (c->has_geom) {
+                    fftt_status st = set_device(c);
+                    if (st != FFTT_OK) return st;
+                    st = build_pairs(c);
+                    if (st != FFTT_OK) return st;
+                }
+            }
             return FFTT_OK;
         case FFTT_TUNE_STAGED_TABLE:
             if (value != 0 && value != 1) FFTT_BAD(c, "staged table must be 0 or 1");

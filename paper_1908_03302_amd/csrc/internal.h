@@ -110,10 +110,11 @@ hipError_t launch_group_fill(hipStream_t s, const int64_t* tptr, const Entry* en
                              const int64_t* gptr, void* desc);
 hipError_t launch_count_pv(hipStream_t s, const ApplyArgs& a, double r_max_all,
                            const double* L, const int32_t* ps, const int32_t* pr,
-                           const double* tx, unsigned long long* pv,
-                           unsigned long long* lanes);
-hipError_t launch_weights(hipStream_t s, bool fp64, const void* dT, const int32_t* porig,
-                          const double* C, int64_t M, int nb, void* w);
+                           const double* tx, const int32_t* kptr, unsigned long long* pv_op,
+                           unsigned long long* pv_eval);
+hipError_t launch_weights(hipStream_t s, bool fp64, const void* dT, const int32_t* kptr,
+                          const int32_t* kidx, const double* C, int64_t Mk, int64_t M, int nb,
+                          void* w);
 hipError_t launch_fill(hipStream_t s, bool fp64, void* p, int64_t n);
 hipError_t launch_apply(hipStream_t s, fftt_precision prec, bool transpose,
                         const ApplyArgs& a);
@@ -129,12 +130,16 @@ size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, int wpb);
 // zeroed) are filled for the n voxels given by (active tile, lane) pairs;
 // col_tab is the FP32 (h, slope) table used for the weights.
 hipError_t launch_psf(hipStream_t s, int tabfmt, const ApplyArgs& a, const int32_t* ptile,
-                      const int32_t* plane, const double* C, double s2, float* W, int64_t ldw,
-                      int n, float* out, const void* col_tab);
+                      const int32_t* plane, const double* C, const int32_t* kptr, double s2,
+                      float* W, int64_t ldw, int n, float* out, const void* col_tab);
 size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx);
+// J per-pair sum: S slices per 64-pair group (reduce_slices), FP64 scratch
+// red [nb][S][Mk], then the rows of every caller pair of a group.
+int reduce_slices(int64_t Mk, int n_cu);
 hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz,
                          const int64_t* gptr, const void* desc, const double* C,
-                         const int32_t* porig, int64_t M, int nb, void* dT);
+                         const int32_t* kptr, const int32_t* kidx, int64_t Mk, int64_t M, int nb,
+                         int S, double* red, void* dT);
 
 // ---- solver building blocks (solve.hip) ----
 hipError_t solver_dot(hipStream_t s, bool fp64, const void* a, const void* b, int64_t n,
@@ -165,15 +170,22 @@ struct fftt_ctx {
     double c0 = 0;
     int64_t n_tx = 0, M = 0, N = 0;
     std::vector<double> tx;
-    std::vector<int32_t> ps, pr, porig;   // internal pair order: sorted by (source, receiver)
-    std::vector<double> L, C;             // per internal pair: length, -L dV / (2 pi c0^3)
+    std::vector<int32_t> pairs_in;        // the caller's pairs [M][2]
+    // Kernel pairs: caller pairs with identical rows of J form one group
+    // (same unordered transducer pair when reciprocity is used, else the
+    // same ordered pair), evaluated once.  Sorted by (source, receiver);
+    // group k holds caller pairs kidx[kptr[k] .. kptr[k+1]).
+    int64_t Mk = 0;
+    int reciprocity = 1;
+    std::vector<int32_t> ps, pr, kptr, kidx;
+    std::vector<double> L, C;             // per kernel pair: length, -L dV / (2 pi c0^3)
     fftt::GridGeom g{};
     double dV = 0;
     std::vector<uint8_t> mask;
     std::vector<int32_t> act_tiles;
 
     // geometry (device)
-    fftt::DevBuf d_tx, d_ps, d_pr, d_porig, d_L, d_C, d_mask, d_tiles;
+    fftt::DevBuf d_tx, d_ps, d_pr, d_kptr, d_kidx, d_L, d_C, d_mask, d_tiles;
 
     // kernel tables
     int nb = 0;
@@ -188,7 +200,7 @@ struct fftt_ctx {
     bool lists_ok = false;
     double lists_rcut = 0;
     int64_t nnz = 0;
-    int64_t pv = 0, lanes = 0;
+    int64_t pv = 0, pv_eval = 0, lanes = 0;
     fftt::DevBuf d_txc, d_tptr, d_ents, d_gptr, d_desc;
     int64_t n_desc = 0;
 
@@ -204,7 +216,7 @@ struct fftt_ctx {
     size_t lds_limit = 65536;
 
     // work buffers
-    fftt::DevBuf d_w, d_part, d_solve, d_scal;
+    fftt::DevBuf d_w, d_part, d_red, d_solve, d_scal;
     fftt::DevBuf d_psfw, d_psfd;   // batched PSF weights, (tile, lane) of each voxel
 
     // optional event timing of the main kernels (index: 0 J, 1 J^T, 2 reduction)

@@ -314,12 +314,17 @@ __device__ __forceinline__ void voxel_of_lane(const ApplyArgs& A, int64_t t, int
     act = inside && A.mask[vidx] != 0;
 }
 
+// pv_eval counts the (kernel pair, active voxel) evaluations with detour
+// below rmax; pv_op the same over caller pairs (a kernel pair stands for
+// kptr[p+1] - kptr[p] caller pairs with identical rows).
 __global__ __launch_bounds__(256) void k_count_pv(ApplyArgs A, double rmax,
                                                   const double* __restrict__ L,
                                                   const int32_t* __restrict__ ps,
                                                   const int32_t* __restrict__ pr,
                                                   const double* __restrict__ tx,
-                                                  unsigned long long* pv) {
+                                                  const int32_t* __restrict__ kptr,
+                                                  unsigned long long* pv_op,
+                                                  unsigned long long* pv_eval) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int64_t a = (int64_t)blockIdx.x * kWavesPerBlock + wave;
@@ -330,7 +335,7 @@ __global__ __launch_bounds__(256) void k_count_pv(ApplyArgs A, double rmax,
     const double x = A.g.origin[0] + (double)v[0] * A.g.spacing[0];
     const double y = A.g.origin[1] + (double)v[1] * A.g.spacing[1];
     const double z = A.g.origin[2] + (double)v[2] * A.g.spacing[2];
-    unsigned long long cnt = 0;
+    unsigned long long cnt = 0, cop = 0;
     for (int64_t e = A.tptr[a]; e < A.tptr[a + 1]; ++e) {
         const int p = A.ents[e].p;
         const double* xs = tx + 3 * ps[p];
@@ -340,43 +345,55 @@ __global__ __launch_bounds__(256) void k_count_pv(ApplyArgs A, double rmax,
         const double Rr = sqrt((x - xr[0]) * (x - xr[0]) + (y - xr[1]) * (y - xr[1]) +
                                (z - xr[2]) * (z - xr[2]));
         const bool in = act && (Rs + Rr - L[p] < rmax);
-        cnt += __popcll(__ballot(in));
+        const unsigned long long k = __popcll(__ballot(in));
+        cnt += k;
+        cop += k * (unsigned long long)(kptr[p + 1] - kptr[p]);
     }
-    if (lane == 0) atomicAdd(pv, cnt);
+    if (lane == 0) {
+        atomicAdd(pv_eval, cnt);
+        atomicAdd(pv_op, cop);
+    }
 }
 
 hipError_t launch_count_pv(hipStream_t s, const ApplyArgs& a, double r_max_all,
                            const double* L, const int32_t* ps, const int32_t* pr,
-                           const double* tx, unsigned long long* pv,
-                           unsigned long long* /*lanes*/) {
+                           const double* tx, const int32_t* kptr, unsigned long long* pv_op,
+                           unsigned long long* pv_eval) {
     if (a.n_act == 0) return hipSuccess;
     const unsigned nblk = (unsigned)((a.n_act + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL(k_count_pv, dim3(nblk), dim3(64 * kWavesPerBlock), 0, s, a, r_max_all, L,
-                       ps, pr, tx, pv);
+                       ps, pr, tx, kptr, pv_op, pv_eval);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------- small vector kernels
 
+// J^T weights of the kernel pairs: w[b][k] = C_k sum of dT[b][i] over the
+// caller pairs i of group k (pairs with identical rows, e.g. (s, r) and
+// (r, s)), summed in FP64 in group order.
 template <class T>
-__global__ void k_weights(const T* __restrict__ dT, const int32_t* __restrict__ porig,
-                          const double* __restrict__ C, int64_t M, int nb, T* __restrict__ w) {
+__global__ void k_weights(const T* __restrict__ dT, const int32_t* __restrict__ kptr,
+                          const int32_t* __restrict__ kidx, const double* __restrict__ C,
+                          int64_t Mk, int64_t M, int nb, T* __restrict__ w) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M * nb) return;
-    const int64_t b = i / M, p = i - b * M;
-    w[i] = (T)(C[p] * (double)dT[b * M + porig[p]]);
+    if (i >= Mk * nb) return;
+    const int64_t b = i / Mk, k = i - b * Mk;
+    double t = 0.0;
+    for (int32_t j = kptr[k]; j < kptr[k + 1]; ++j) t += (double)dT[b * M + kidx[j]];
+    w[i] = (T)(C[k] * t);
 }
 
-hipError_t launch_weights(hipStream_t s, bool fp64, const void* dT, const int32_t* porig,
-                          const double* C, int64_t M, int nb, void* w) {
-    const int64_t n = M * nb;
+hipError_t launch_weights(hipStream_t s, bool fp64, const void* dT, const int32_t* kptr,
+                          const int32_t* kidx, const double* C, int64_t Mk, int64_t M, int nb,
+                          void* w) {
+    const int64_t n = Mk * nb;
     const unsigned nblk = (unsigned)((n + 255) / 256);
     if (fp64)
         hipLaunchKernelGGL(k_weights<double>, dim3(nblk), dim3(256), 0, s, (const double*)dT,
-                           porig, C, M, nb, (double*)w);
+                           kptr, kidx, C, Mk, M, nb, (double*)w);
     else
         hipLaunchKernelGGL(k_weights<float>, dim3(nblk), dim3(256), 0, s, (const float*)dT,
-                           porig, C, M, nb, (float*)w);
+                           kptr, kidx, C, Mk, M, nb, (float*)w);
     return hipGetLastError();
 }
 
@@ -850,7 +867,21 @@ __device__ __forceinline__ void stage_distances(const ApplyArgs& A, int64_t a, c
     const TxConst* __restrict__ row = A.txc + a * A.n_tx;
     const int W = (int)(blockDim.x >> 6);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    for (int q = wave; q < (int)A.n_tx; q += W) {
+    const int n = (int)A.n_tx;
+    int q = wave;
+    // four transducers per step: their constants are requested together
+    for (; q + 3 * W < n; q += 4 * W) {
+        TxConst c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = row[q + k * W];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float d, rs;
+            dist32(c[k], V.ux, V.uy, V.uz, V.uu, d, rs);
+            sx[(q + k * W) * 64 + lane] = make_float2(d * A.inv_dr[0], rs);
+        }
+    }
+    for (; q < n; q += W) {
         float d, rs;
         dist32(row[q], V.ux, V.uy, V.uz, V.uu, d, rs);
         sx[q * 64 + lane] = make_float2(d * A.inv_dr[0], rs);
@@ -1227,19 +1258,24 @@ hipError_t launch_group_fill(hipStream_t s, const int64_t* tptr, const Entry* en
 
 constexpr int kReduceWaves = 16;
 
+// Each 64-pair group is split into S slices of its descriptor list (one
+// workgroup each, so that small pair counts still fill the device); a slice
+// writes its FP64 sums to red[b][slice][p], and k_reduce_final adds the S
+// slices in order.
 template <class T>
 __global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
     const T* __restrict__ part, int64_t nnz, const int64_t* __restrict__ gptr,
-    const RunDesc* __restrict__ desc, const double* __restrict__ C,
-    const int32_t* __restrict__ porig, int64_t M, int nb, T* __restrict__ dT) {
+    const RunDesc* __restrict__ desc, int64_t Mk, int nb, int S, double* __restrict__ red) {
     __shared__ double s_acc[kReduceWaves][64];
     const int64_t g = blockIdx.x;
+    const int sl = (int)blockIdx.y;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
-    const int64_t d0 = gptr[g], d1 = gptr[g + 1];
-    const int64_t chunk = (d1 - d0 + kReduceWaves - 1) / kReduceWaves;
-    const int64_t k0 = min(d1, d0 + wave * chunk), k1 = min(d1, k0 + chunk);
+    const int64_t d0 = gptr[g], len = gptr[g + 1] - d0;
+    const int64_t s0 = d0 + len * sl / S, s1 = d0 + len * (sl + 1) / S;
+    const int64_t chunk = (s1 - s0 + kReduceWaves - 1) / kReduceWaves;
+    const int64_t k0 = min(s1, s0 + wave * chunk), k1 = min(s1, k0 + chunk);
     const int64_t p = 64 * g + lane;
     for (int b = 0; b < nb; ++b) {
         const T* __restrict__ pb = part + (int64_t)b * nnz;
@@ -1265,26 +1301,57 @@ __global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
         }
         s_acc[wave][lane] = acc;
         __syncthreads();
-        if (wave == 0) {
+        if (wave == 0 && p < Mk) {
             double t = s_acc[0][lane];
             for (int w = 1; w < kReduceWaves; ++w) t += s_acc[w][lane];
-            if (p < M) dT[(int64_t)b * M + porig[p]] = (T)(C[p] * t);
+            red[((int64_t)b * S + sl) * Mk + p] = t;
         }
         __syncthreads();
     }
 }
 
+// dT[b][i] = C_p * sum of the slices, for every caller pair i of group p.
+template <class T>
+__global__ void k_reduce_final(const double* __restrict__ red, int64_t Mk, int64_t M, int nb,
+                               int S, const double* __restrict__ C,
+                               const int32_t* __restrict__ kptr,
+                               const int32_t* __restrict__ kidx, T* __restrict__ dT) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Mk * nb) return;
+    const int64_t b = i / Mk, p = i - b * Mk;
+    double t = 0.0;
+    for (int sl = 0; sl < S; ++sl) t += red[(b * S + sl) * Mk + p];
+    const T y = (T)(C[p] * t);
+    for (int32_t j = kptr[p]; j < kptr[p + 1]; ++j) dT[b * M + kidx[j]] = y;
+}
+
+int reduce_slices(int64_t Mk, int n_cu) {
+    const int64_t G = (Mk + 63) / 64;
+    const int64_t want = (2 * (int64_t)std::max(n_cu, 1) + G - 1) / std::max<int64_t>(G, 1);
+    return (int)std::min<int64_t>(std::max<int64_t>(want, 1), 16);
+}
+
 hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz,
                          const int64_t* gptr, const void* desc, const double* C,
-                         const int32_t* porig, int64_t M, int nb, void* dT) {
-    const int64_t G = (M + 63) / 64;
+                         const int32_t* kptr, const int32_t* kidx, int64_t Mk, int64_t M, int nb,
+                         int S, double* red, void* dT) {
+    const int64_t G = (Mk + 63) / 64;
+    if (G == 0) return hipSuccess;
     const RunDesc* d = static_cast<const RunDesc*>(desc);
-    if (fp64)
-        hipLaunchKernelGGL(k_reduce<double>, dim3((unsigned)G), dim3(64 * kReduceWaves), 0, s,
-                           (const double*)part, nnz, gptr, d, C, porig, M, nb, (double*)dT);
-    else
-        hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)G), dim3(64 * kReduceWaves), 0, s,
-                           (const float*)part, nnz, gptr, d, C, porig, M, nb, (float*)dT);
+    const unsigned nf = (unsigned)((Mk * nb + 255) / 256);
+    if (fp64) {
+        hipLaunchKernelGGL(k_reduce<double>, dim3((unsigned)G, (unsigned)S),
+                           dim3(64 * kReduceWaves), 0, s, (const double*)part, nnz, gptr, d, Mk,
+                           nb, S, red);
+        hipLaunchKernelGGL(k_reduce_final<double>, dim3(nf), dim3(256), 0, s, red, Mk, M, nb, S,
+                           C, kptr, kidx, (double*)dT);
+    } else {
+        hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)G, (unsigned)S),
+                           dim3(64 * kReduceWaves), 0, s, (const float*)part, nnz, gptr, d, Mk,
+                           nb, S, red);
+        hipLaunchKernelGGL(k_reduce_final<float>, dim3(nf), dim3(256), 0, s, red, Mk, M, nb, S,
+                           C, kptr, kidx, (float*)dT);
+    }
     return hipGetLastError();
 }
 
@@ -1312,7 +1379,8 @@ using f32x16 = __attribute__((__vector_size__(16 * sizeof(float)))) float;
 template <int NB, class TabT>
 __global__ __launch_bounds__(64) void k_psf_cols(ApplyArgs A, const int32_t* __restrict__ ptile,
                                                  const int32_t* __restrict__ plane,
-                                                 const double* __restrict__ C, double s2,
+                                                 const double* __restrict__ C,
+                                                 const int32_t* __restrict__ kptr, double s2,
                                                  float* __restrict__ W, int64_t ldw) {
     const int k = blockIdx.x;
     const int64_t a = ptile[k];
@@ -1331,8 +1399,10 @@ __global__ __launch_bounds__(64) void k_psf_cols(ApplyArgs A, const int32_t* __r
         dist32(row[s], ux, uy, uz, uu, ds, gs);
         dist32(row[r], ux, uy, uz, uu, dr, gr);
         const float R = (ds + dr) + E.R0hi;
+        // a kernel pair stands for kptr[p+1] - kptr[p] identical rows of J
         const double c = C[E.p];
-        const float f = (float)(c * c * s2) * (gs * gr);
+        const double m = (double)(kptr[E.p + 1] - kptr[E.p]);
+        const float f = (float)(c * c * m * s2) * (gs * gr);
 #pragma unroll
         for (int b = 0; b < NB; ++b)
             W[((int64_t)b * A.M + E.p) * ldw + k] =
@@ -1519,14 +1589,14 @@ size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
 template <int NB>
 static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
                                 const int32_t* ptile, const int32_t* plane, const double* C,
-                                double s2, float* W, int64_t ldw, int n, float* out,
-                                const void* col_tab) {
+                                const int32_t* kptr, double s2, float* W, int64_t ldw, int n,
+                                float* out, const void* col_tab) {
     // the weights (J e_k, cheap) always use the FP32 (h, slope) table, so a
     // BF16 table only enters through the contraction
     ApplyArgs ac = a;
     ac.tab = col_tab;
     hipLaunchKernelGGL((k_psf_cols<NB, float2>), dim3((unsigned)n), dim3(64), 0, s, ac, ptile,
-                       plane, C, s2, W, ldw);
+                       plane, C, kptr, s2, W, ldw);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess || a.n_act == 0) return err;
     const int wpb = a.waves_per_block;
@@ -1552,13 +1622,17 @@ static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
 }
 
 hipError_t launch_psf(hipStream_t s, int tabfmt, const ApplyArgs& a, const int32_t* ptile,
-                      const int32_t* plane, const double* C, double s2, float* W, int64_t ldw,
-                      int n, float* out, const void* col_tab) {
+                      const int32_t* plane, const double* C, const int32_t* kptr, double s2,
+                      float* W, int64_t ldw, int n, float* out, const void* col_tab) {
     switch (a.nb) {
-        case 1: return launch_psf_nb<1>(s, tabfmt, a, ptile, plane, C, s2, W, ldw, n, out, col_tab);
-        case 2: return launch_psf_nb<2>(s, tabfmt, a, ptile, plane, C, s2, W, ldw, n, out, col_tab);
-        case 3: return launch_psf_nb<3>(s, tabfmt, a, ptile, plane, C, s2, W, ldw, n, out, col_tab);
-        case 4: return launch_psf_nb<4>(s, tabfmt, a, ptile, plane, C, s2, W, ldw, n, out, col_tab);
+        case 1: return launch_psf_nb<1>(s, tabfmt, a, ptile, plane, C, kptr, s2, W, ldw, n, out,
+                                        col_tab);
+        case 2: return launch_psf_nb<2>(s, tabfmt, a, ptile, plane, C, kptr, s2, W, ldw, n, out,
+                                        col_tab);
+        case 3: return launch_psf_nb<3>(s, tabfmt, a, ptile, plane, C, kptr, s2, W, ldw, n, out,
+                                        col_tab);
+        case 4: return launch_psf_nb<4>(s, tabfmt, a, ptile, plane, C, kptr, s2, W, ldw, n, out,
+                                        col_tab);
     }
     return hipErrorInvalidValue;
 }

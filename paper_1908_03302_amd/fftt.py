@@ -27,6 +27,7 @@ EXPORTS = ["fftt_create", "fftt_destroy", "fftt_last_error", "fftt_set_stream",
 TUNE_WAVES_PER_BLOCK, TUNE_UNROLL_JT, TUNE_UNROLL_J, TUNE_SPLIT_JT, TUNE_SPLIT_J = 0, 1, 2, 3, 4
 TUNE_STAGED, TUNE_UNROLL_JT_STAGED, TUNE_UNROLL_J_STAGED = 5, 6, 7
 TUNE_STAGED_TABLE = 8
+TUNE_RECIPROCITY = 9
 
 
 class SolveOpts(C.Structure):
@@ -71,7 +72,8 @@ def load():
     L.fftt_build_table_from_pulse.argtypes = [C.c_double, dp, i64, C.c_double, i64, C.c_double,
                                               dp, dp]
     L.fftt_prepare.argtypes = [vp]
-    L.fftt_work_count.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.fftt_work_count.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64)]
     L.fftt_apply_J.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
     L.fftt_apply_JT.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
     L.fftt_solve.argtypes = [vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveReport)]
@@ -173,20 +175,23 @@ class Context:
         self._check(self.L.fftt_prepare(self.h), "prepare")
 
     def work_count(self):
-        pv, lanes = C.c_int64(), C.c_int64()
+        """(pv of the operator, pv the kernels evaluate, evaluated lanes)."""
+        pv, pve, lanes = C.c_int64(), C.c_int64(), C.c_int64()
         self._bind_stream()
-        self._check(self.L.fftt_work_count(self.h, C.byref(pv), C.byref(lanes)), "work_count")
-        return pv.value, lanes.value
+        self._check(self.L.fftt_work_count(self.h, C.byref(pv), C.byref(pve), C.byref(lanes)),
+                    "work_count")
+        return pv.value, pve.value, lanes.value
 
     def set_tuning(self, waves_per_block=None, unroll_jt=None, unroll_j=None, split_jt=None,
                    split_j=None, staged=None, unroll_jt_staged=None, unroll_j_staged=None,
-                   staged_table=None):
+                   staged_table=None, reciprocity=None):
         for key, v in ((TUNE_WAVES_PER_BLOCK, waves_per_block), (TUNE_UNROLL_JT, unroll_jt),
                        (TUNE_UNROLL_J, unroll_j), (TUNE_SPLIT_JT, split_jt),
                        (TUNE_SPLIT_J, split_j), (TUNE_STAGED, staged),
                        (TUNE_UNROLL_JT_STAGED, unroll_jt_staged),
                        (TUNE_UNROLL_J_STAGED, unroll_j_staged),
-                       (TUNE_STAGED_TABLE, staged_table)):
+                       (TUNE_STAGED_TABLE, staged_table),
+                       (TUNE_RECIPROCITY, reciprocity)):
             if v is not None:
                 self._check(self.L.fftt_set_tuning(self.h, key, int(v)), "set_tuning")
 

@@ -86,10 +86,13 @@ def ragged():
 # ------------------------------------------------------------ small (config 1)
 
 def test_small_work_count_exact(small):
+    """The operator's pv equals the oracle's brute-force count; with every
+    pair's reverse present, the kernels evaluate exactly half of it."""
     w, o, ot, ctx = small
-    pv, lanes = ctx.work_count()
+    pv, pv_eval, lanes = ctx.work_count()
     assert pv == o.count_pv()
-    assert lanes >= pv
+    assert 2 * pv_eval == pv
+    assert lanes >= pv_eval
 
 
 @pytest.mark.parametrize("prec_name", ["FP64", "FP32", "FP32_BF16TABLE"])
@@ -216,7 +219,7 @@ def test_ragged_two_bands(ragged, prec_name):
         assert ej < 1e-5 and et < 1e-5
     else:
         assert ej < 1e-3 and et < 1e-3
-    pv, _ = ctx.work_count()
+    pv, _, _ = ctx.work_count()
     assert pv == o.count_pv()
 
 
