@@ -184,14 +184,20 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *     inner-loop step of the J^T / J kernel: 1, 2 or 4.
  *   FFTT_TUNE_SPLIT_JT / FFTT_TUNE_SPLIT_J: 0 = every wavefront owns a tile;
  *     1 = a workgroup owns a tile and its wavefronts split the tile's pairs.
- *   FFTT_TUNE_STAGED: 1 (default) = FP32/BF16 operators first evaluate every
- *     transducer distance of a tile into LDS when it fits (n_tx * 512 bytes
- *     plus the tables), 0 = never.
+ *   FFTT_TUNE_STAGED: 1 (default) = FP32/BF16 operators first evaluate the
+ *     transducer distances of a tile into LDS (Q * 512 bytes plus the
+ *     tables, see FFTT_TUNE_STAGED_BLOCK), 0 = never.
  *   FFTT_TUNE_UNROLL_JT_STAGED / FFTT_TUNE_UNROLL_J_STAGED: unroll of those:
  *     1, 2, 4 or 8.
  *   FFTT_TUNE_STAGED_TABLE: table layout of the staged FP32 kernels:
  *     0 (default) = one float per node (4 bytes), 1 = (h_k, h_{k+1} - h_k)
  *     pairs (8 bytes per node, fewer instructions, more LDS).
+ *   FFTT_TUNE_STAGED_BLOCK: the staged kernels stage transducers in aligned
+ *     blocks of Q (a power of two: the smallest covering all transducers,
+ *     halved until it fits LDS); a tile's entries are processed one block
+ *     at a time, which requires every pair to lie in one block (else the
+ *     per-wavefront kernels run).  0 (default) = automatic, otherwise an
+ *     upper bound on Q (a power of two >= 16).
  *   FFTT_TUNE_RECIPROCITY: 1 (default) = a pair (s, r) and its reverse
  *     (r, s) have the same row of J (source-receiver reciprocity, Sec. II-B;
  *     the detour and L are symmetric), so each unordered pair is evaluated
@@ -202,7 +208,8 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
 enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_J = 2,
        FFTT_TUNE_SPLIT_JT = 3, FFTT_TUNE_SPLIT_J = 4, FFTT_TUNE_STAGED = 5,
        FFTT_TUNE_UNROLL_JT_STAGED = 6, FFTT_TUNE_UNROLL_J_STAGED = 7,
-       FFTT_TUNE_STAGED_TABLE = 8, FFTT_TUNE_RECIPROCITY = 9 };
+       FFTT_TUNE_STAGED_TABLE = 8, FFTT_TUNE_RECIPROCITY = 9,
+       FFTT_TUNE_STAGED_BLOCK = 10 };
 fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
 
 /* Measurement aid.  With enable != 0 every launch of the main operator

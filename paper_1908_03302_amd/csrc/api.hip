@@ -153,6 +153,7 @@ fftt_status build_pairs(fftt_ctx* c) {
                           hipMemcpyHostToDevice));
     FFTT_HIP(c, hipMemcpy(c->d_L.p, c->L.data(), Mk * sizeof(double), hipMemcpyHostToDevice));
     FFTT_HIP(c, hipMemcpy(c->d_C.p, c->C.data(), Mk * sizeof(double), hipMemcpyHostToDevice));
+    c->blk_q = 0;
     c->lists_ok = false;
     return FFTT_OK;
 }
@@ -293,12 +294,29 @@ int staged_table(const fftt_ctx* c, fftt_precision prec) {
     return c->staged_pair_table ? STAB_PAIR32 : STAB_NODE32;
 }
 
-// The LDS-staged FP32 kernels apply when enabled and the tables plus one
-// float2 per (transducer, lane) fit in the workgroup's LDS.
-bool use_staged(const fftt_ctx* c, fftt_precision prec) {
-    if (!c->staged || prec == FFTT_FP64) return false;
-    return staged_lds_bytes(c->nb, c->ntab, staged_table(c, prec), c->n_tx,
-                            c->waves_per_block) <= c->lds_limit;
+// Transducers per staged block for an FP32 / BF16-table apply: the
+// smallest power of two covering all transducers, halved until the tables
+// plus one float2 per (transducer, lane) of the block fit in LDS; 0 when
+// staging is off, nothing fits, or a kernel pair spans two blocks (the
+// per-wavefront kernels run then).
+int staged_q(fftt_ctx* c, fftt_precision prec) {
+    if (!c->staged || prec == FFTT_FP64) return 0;
+    const int fmt = staged_table(c, prec);
+    int q = 16;
+    while (q < c->n_tx) q *= 2;
+    while (q >= 16 && ((c->staged_block_max && q > c->staged_block_max) ||
+                       staged_lds_bytes(c->nb, c->ntab, fmt, q, c->waves_per_block) >
+                           c->lds_limit))
+        q /= 2;
+    if (q < 16) return 0;
+    if (q >= c->n_tx) return q;
+    if (c->blk_q != q) {
+        c->blk_q = q;
+        c->blk_ok = true;
+        for (int64_t k = 0; k < c->Mk && c->blk_ok; ++k)
+            c->blk_ok = c->ps[k] / q == c->pr[k] / q;
+    }
+    return c->blk_ok ? q : 0;
 }
 
 // Device table of a staged launch.
@@ -335,6 +353,7 @@ fftt_status psf_batched(fftt_ctx* c, fftt_precision prec, const int64_t* voxels,
     ApplyArgs a = base_args(c);
     const int fmt = staged_table(c, prec);
     a.tab = staged_table_ptr(c, fmt);
+    a.stage_q = (int)c->n_tx;             // one block: every transducer staged
     const void* col_tab = c->d_tab32.p;   // FP32 (h, slope) pairs
     hipEvent_t stop;
     FFTT_HIP(c, prof_begin(c, 3, &stop));
@@ -361,7 +380,8 @@ fftt_status apply_J_one(fftt_ctx* c, fftt_precision prec, const void* x, void* y
     a.x = x;
     hipEvent_t stop;
     FFTT_HIP(c, prof_begin(c, 0, &stop));
-    if (use_staged(c, prec)) {
+    if (const int q = staged_q(c, prec)) {
+        a.stage_q = q;
         a.unroll = c->unroll_js;
         const int fmt = staged_table(c, prec);
         a.tab = staged_table_ptr(c, fmt);
@@ -396,7 +416,8 @@ fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* 
     FFTT_HIP(c, launch_fill(c->stream, fp64, x, c->N));
     hipEvent_t stop;
     FFTT_HIP(c, prof_begin(c, 1, &stop));
-    if (use_staged(c, prec)) {
+    if (const int q = staged_q(c, prec)) {
+        a.stage_q = q;
         a.unroll = c->unroll_jts;
         const int fmt = staged_table(c, prec);
         a.tab = staged_table_ptr(c, fmt);
@@ -662,6 +683,11 @@ fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
             if (value != 1 && value != 2 && value != 4 && value != 8)
                 FFTT_BAD(c, "staged unroll must be 1, 2, 4 or 8");
             (key == FFTT_TUNE_UNROLL_J_STAGED ? c->unroll_js : c->unroll_jts) = value;
+            return FFTT_OK;
+        case FFTT_TUNE_STAGED_BLOCK:
+            if (value != 0 && (value < 16 || (value & (value - 1)) != 0))
+                FFTT_BAD(c, "staged block must be 0 or a power of two >= 16");
+            c->staged_block_max = value;
             return FFTT_OK;
         case FFTT_TUNE_RECIPROCITY:
             if (value != 0 && value != 1) FFTT_BAD(c, "reciprocity must be 0 or 1");

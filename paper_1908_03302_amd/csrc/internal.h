@@ -70,6 +70,7 @@ struct ApplyArgs {
     int n_cu;                 // compute units of the device (persistent grid size)
     int unroll;               // entries per inner-loop step (1, 2, 4)
     int split;                // 1: a workgroup shares one tile, its waves split the entries
+    int stage_q;              // staged kernels: transducers per staged block (power of 2)
 };
 
 struct DevBuf {
@@ -125,7 +126,8 @@ enum StagedTable {
     STAB_BF16 = 2,    // packed BF16 (h_k, slope) (4 bytes per node)
 };
 hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a);
-size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, int wpb);
+// LDS of a staged launch: tables plus q staged transducers (q * 512 bytes).
+size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t q, int wpb);
 // Batched point-spread functions: W ([nb][M][ldw], zeroed) and out ([n][N],
 // zeroed) are filled for the n voxels given by (active tile, lane) pairs;
 // col_tab is the FP32 (h, slope) table used for the weights.
@@ -179,6 +181,8 @@ struct fftt_ctx {
     int reciprocity = 1;
     std::vector<int32_t> ps, pr, kptr, kidx;
     std::vector<double> L, C;             // per kernel pair: length, -L dV / (2 pi c0^3)
+    int blk_q = 0;                        // block size last checked for the staged layout
+    bool blk_ok = false;                  // every kernel pair inside one block of blk_q
     fftt::GridGeom g{};
     double dV = 0;
     std::vector<uint8_t> mask;
@@ -213,6 +217,7 @@ struct fftt_ctx {
     int staged = 1;            // use the LDS-staged kernels when they fit
     int unroll_jts = 8, unroll_js = 8;
     int staged_pair_table = 0; // FP32 staged kernels: 0 node table, 1 (h, slope) pairs
+    int staged_block_max = 0;  // cap on the staged block size (0: LDS decides)
     size_t lds_limit = 65536;
 
     // work buffers

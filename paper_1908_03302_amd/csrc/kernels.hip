@@ -862,12 +862,12 @@ __device__ __forceinline__ float2* staged_tx(const ApplyArgs& A, int nb) {
     return reinterpret_cast<float2*>(smem + (((size_t)nb * A.ntab * sizeof(TabT) + 15) & ~(size_t)15));
 }
 
+// Stages transducers q0 .. q0 + n - 1 into sx[q - q0][lane].
 __device__ __forceinline__ void stage_distances(const ApplyArgs& A, int64_t a, const LaneVox& V,
-                                                float2* sx, int lane) {
-    const TxConst* __restrict__ row = A.txc + a * A.n_tx;
+                                                float2* sx, int lane, int q0, int n) {
+    const TxConst* __restrict__ row = A.txc + a * A.n_tx + q0;
     const int W = (int)(blockDim.x >> 6);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int n = (int)A.n_tx;
     int q = wave;
     // four transducers per step: their constants are requested together
     for (; q + 3 * W < n; q += 4 * W) {
@@ -898,8 +898,10 @@ struct StepEntries {
     float R0[U];
 };
 
+// Transducer indices are returned relative to the staged block's first one.
 template <int U>
-__device__ __forceinline__ StepEntries<U> load_entries(const Entry* __restrict__ ents, int64_t e) {
+__device__ __forceinline__ StepEntries<U> load_entries(const Entry* __restrict__ ents, int64_t e,
+                                                       int base) {
     StepEntries<U> E;
     const uint4* __restrict__ raw = reinterpret_cast<const uint4*>(ents + e);
     uint4 v[U];
@@ -908,11 +910,53 @@ __device__ __forceinline__ StepEntries<U> load_entries(const Entry* __restrict__
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         E.p[u] = (int)v[u].x;
-        E.s[u] = (int)(v[u].y & 0xffffu);
-        E.r[u] = (int)(v[u].y >> 16);
+        E.s[u] = (int)(v[u].y & 0xffffu) - base;
+        E.r[u] = (int)(v[u].y >> 16) - base;
         E.R0[u] = __uint_as_float(v[u].z);
     }
     return E;
+}
+
+// Transducer blocks of the staged kernels: aligned index ranges
+// [b Q, b Q + Q).  Every kernel pair lies in one block (checked on the host)
+// and a tile's entries are sorted by source, so they form one run per block;
+// the workgroup stages one block at a time.  First entry in [e, t1) whose
+// source is at least q (uniform binary search).
+__device__ __forceinline__ int64_t first_source_at_least(const Entry* __restrict__ ents,
+                                                        int64_t e, int64_t t1, int q) {
+    int64_t lo = e, hi = t1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int)(ents[mid].sr & 0xffffu) < q)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Runs body(q0, e0, e1) for each transducer block of tile a after staging
+// it; e0 .. e1 is this wavefront's share of the block's entries (multiples of
+// U).  The staged values are valid inside body only.
+template <int U, class F>
+__device__ __forceinline__ void for_each_block(const ApplyArgs& A, int64_t a, const LaneVox& V,
+                                               float2* sx, int lane, F&& body) {
+    const int Q = A.stage_q;
+    const int W = (int)(blockDim.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
+    for (int64_t b0 = t0; b0 < t1;) {
+        const int q0 = (int)(A.ents[b0].sr & 0xffffu) / Q * Q;
+        const int64_t b1 = first_source_at_least(A.ents, b0, t1, q0 + Q);
+        stage_distances(A, a, V, sx, lane, q0, min(Q, (int)A.n_tx - q0));
+        int64_t chunk = (b1 - b0 + W - 1) / W;
+        chunk = (chunk + U - 1) / U * U;
+        const int64_t e0 = min(b1, b0 + (int64_t)wave * chunk);
+        const int64_t e1 = min(b1, e0 + chunk);
+        body(q0, e0, e1);
+        __syncthreads();   // before the next block is staged over this one
+        b0 = b1;
+    }
 }
 
 // Source terms of a step: the scaled detour part and 1/R_xs times a per-lane
@@ -1010,34 +1054,26 @@ __global__ __launch_bounds__(1024, 8) void k_jt32s(ApplyArgs A) {
     if (a >= A.n_act) return;
     const int lane = threadIdx.x & 63;
     const LaneVox V = lane_vox(A, a, lane);
-    stage_distances(A, a, V, sx, lane);
-    int64_t e0, e1;
-    {
-        const int W = (int)(blockDim.x >> 6);
-        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-        const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
-        int64_t chunk = (t1 - t0 + W - 1) / W;
-        chunk = (chunk + U - 1) / U * U;
-        e0 = min(t1, t0 + (int64_t)wave * chunk);
-        e1 = min(t1, e0 + chunk);
-    }
     const float* __restrict__ w = static_cast<const float*>(A.w);
     const float nm1 = (float)(A.ntab - 1);
-    float acc = 0.f, cd = 0.f, cg = 0.f;
-    int prev = -1;
-    int64_t e = e0;
-    for (; e + U <= e1; e += U) {
-        const StepEntries<U> E = load_entries<U>(A.ents, e);
-        jt32s_body<NB, TabT, U>(A, st, sx, E, load_weights<NB, U>(A, w, E), nm1, lane, prev, cd,
-                                cg, acc);
-    }
-    for (; e < e1; ++e) {
-        const StepEntries<1> E = load_entries<1>(A.ents, e);
-        jt32s_body<NB, TabT, 1>(A, st, sx, E, load_weights<NB, 1>(A, w, E), nm1, lane, prev, cd,
-                                cg, acc);
-    }
-    // combine the wavefronts in order (the staged distances are no longer needed)
-    __syncthreads();
+    float acc = 0.f;
+    for_each_block<U>(A, a, V, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
+        float cd = 0.f, cg = 0.f;
+        int prev = -1;
+        int64_t e = e0;
+        for (; e + U <= e1; e += U) {
+            const StepEntries<U> E = load_entries<U>(A.ents, e, q0);
+            jt32s_body<NB, TabT, U>(A, st, sx, E, load_weights<NB, U>(A, w, E), nm1, lane, prev,
+                                    cd, cg, acc);
+        }
+        for (; e < e1; ++e) {
+            const StepEntries<1> E = load_entries<1>(A.ents, e, q0);
+            jt32s_body<NB, TabT, 1>(A, st, sx, E, load_weights<NB, 1>(A, w, E), nm1, lane, prev,
+                                    cd, cg, acc);
+        }
+    });
+    // combine the wavefronts in order (the staged distances are no longer
+    // needed; the block loop ended with a barrier)
     float* s_acc = reinterpret_cast<float*>(sx);
     const int wave = (int)(threadIdx.x >> 6);
     s_acc[wave * 64 + lane] = acc;
@@ -1092,36 +1128,27 @@ __global__ __launch_bounds__(1024, 8) void k_j32s(ApplyArgs A) {
     if (a >= A.n_act) return;
     const int lane = threadIdx.x & 63;
     const LaneVox V = lane_vox(A, a, lane);
-    stage_distances(A, a, V, sx, lane);
-    int64_t e0, e1;
-    {
-        const int W = (int)(blockDim.x >> 6);
-        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-        const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
-        int64_t chunk = (t1 - t0 + W - 1) / W;
-        chunk = (chunk + U - 1) / U * U;
-        e0 = min(t1, t0 + (int64_t)wave * chunk);
-        e1 = min(t1, e0 + chunk);
-    }
     float* __restrict__ part = static_cast<float*>(A.out);
     const float xv = V.act ? static_cast<const float*>(A.x)[V.vidx] : 0.f;
     const float nm1 = (float)(A.ntab - 1);
-    float cd = 0.f, cg = 0.f;
-    int prev = -1;
-    int64_t e = e0;
-    for (; e + U <= e1; e += U)
-        j32s_body<NB, TabT, U>(A, st, sx, load_entries<U>(A.ents, e), part, xv, nm1, lane, e,
-                               prev, cd, cg);
-    for (; e < e1; ++e)
-        j32s_body<NB, TabT, 1>(A, st, sx, load_entries<1>(A.ents, e), part, xv, nm1, lane, e,
-                               prev, cd, cg);
+    for_each_block<U>(A, a, V, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
+        float cd = 0.f, cg = 0.f;
+        int prev = -1;
+        int64_t e = e0;
+        for (; e + U <= e1; e += U)
+            j32s_body<NB, TabT, U>(A, st, sx, load_entries<U>(A.ents, e, q0), part, xv, nm1, lane,
+                                   e, prev, cd, cg);
+        for (; e < e1; ++e)
+            j32s_body<NB, TabT, 1>(A, st, sx, load_entries<1>(A.ents, e, q0), part, xv, nm1, lane,
+                                   e, prev, cd, cg);
+    });
 }
 
 template <class K>
 static hipError_t launch_staged(K kern, hipStream_t s, const ApplyArgs& a, size_t table_bytes) {
     if (a.n_act == 0) return hipSuccess;
     const int wpb = a.waves_per_block;
-    const size_t tx_bytes = std::max<size_t>((size_t)a.n_tx * 64 * sizeof(float2),
+    const size_t tx_bytes = std::max<size_t>((size_t)a.stage_q * 64 * sizeof(float2),
                                              (size_t)wpb * 64 * sizeof(float));
     const size_t lds = ((table_bytes + 15) & ~(size_t)15) + tx_bytes;
     if (lds > 65536) {
@@ -1137,10 +1164,10 @@ static size_t staged_entry_bytes(int tabfmt) {
     return tabfmt == STAB_PAIR32 ? sizeof(float2) : sizeof(float);
 }
 
-size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, int wpb) {
+size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t q, int wpb) {
     const size_t tab = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
     return ((tab + 15) & ~(size_t)15) +
-           std::max<size_t>((size_t)n_tx * 64 * sizeof(float2), (size_t)wpb * 64 * sizeof(float));
+           std::max<size_t>((size_t)q * 64 * sizeof(float2), (size_t)wpb * 64 * sizeof(float));
 }
 
 template <class TabT, int NB, int U>
@@ -1476,7 +1503,7 @@ __global__ __launch_bounds__(1024) void k_psf32(ApplyArgs A, const float* __rest
     if (a >= A.n_act) return;
     const int lane = threadIdx.x & 63;
     const LaneVox V = lane_vox(A, a, lane);
-    stage_distances(A, a, V, sx, lane);
+    stage_distances(A, a, V, sx, lane, 0, (int)A.n_tx);   // one block: all transducers
     const int W_ = (int)(blockDim.x >> 6);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int k0 = ((int)blockIdx.y * W_ + wave) * 32;

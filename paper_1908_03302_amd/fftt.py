@@ -28,6 +28,7 @@ TUNE_WAVES_PER_BLOCK, TUNE_UNROLL_JT, TUNE_UNROLL_J, TUNE_SPLIT_JT, TUNE_SPLIT_J
 TUNE_STAGED, TUNE_UNROLL_JT_STAGED, TUNE_UNROLL_J_STAGED = 5, 6, 7
 TUNE_STAGED_TABLE = 8
 TUNE_RECIPROCITY = 9
+TUNE_STAGED_BLOCK = 10
 
 
 class SolveOpts(C.Structure):
@@ -184,14 +185,15 @@ class Context:
 
     def set_tuning(self, waves_per_block=None, unroll_jt=None, unroll_j=None, split_jt=None,
                    split_j=None, staged=None, unroll_jt_staged=None, unroll_j_staged=None,
-                   staged_table=None, reciprocity=None):
+                   staged_table=None, reciprocity=None, staged_block=None):
         for key, v in ((TUNE_WAVES_PER_BLOCK, waves_per_block), (TUNE_UNROLL_JT, unroll_jt),
                        (TUNE_UNROLL_J, unroll_j), (TUNE_SPLIT_JT, split_jt),
                        (TUNE_SPLIT_J, split_j), (TUNE_STAGED, staged),
                        (TUNE_UNROLL_JT_STAGED, unroll_jt_staged),
                        (TUNE_UNROLL_J_STAGED, unroll_j_staged),
                        (TUNE_STAGED_TABLE, staged_table),
-                       (TUNE_RECIPROCITY, reciprocity)):
+                       (TUNE_RECIPROCITY, reciprocity),
+                       (TUNE_STAGED_BLOCK, staged_block)):
             if v is not None:
                 self._check(self.L.fftt_set_tuning(self.h, key, int(v)), "set_tuning")
 
