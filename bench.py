@@ -111,6 +111,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-misfit legs")
     ap.add_argument("--no-psf", action="store_true", help="skip the batched PSF leg")
     ap.add_argument("--no-multiband", action="store_true", help="skip the four-band leg")
+    ap.add_argument("--no-slices", action="store_true", help="skip the 16-height slice leg")
     ap.add_argument("--cg-iters", type=int, default=20)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
@@ -240,6 +241,8 @@ def main():
     del dc, dT, dc2
     if not args.no_multiband:
         out["multiband"] = multiband_leg(fftt, torch)
+    if not args.no_slices:
+        out["slices"] = slices_leg(fftt, torch)
     if not args.no_cpu:
         log("bench: CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)
@@ -310,6 +313,54 @@ def multiband_leg(fftt, torch, reps=10):
             "pv_per_s": 2 * pv / ((ms_j + ms_jt) * 1e-3), "flops_per_pv": fpv,
             "J_tflops": pv * fpv / (ms_j * 1e-3) / 1e12,
             "JT_tflops": pv * fpv / (ms_jt * 1e-3) / 1e12}
+
+
+def slices_leg(fftt, torch, reps=3, lsqr_iters=50):
+    """256-element ring at 16 heights (1 044 480 pairs within rings) on the
+    256x256x160 grid: J and J^T in FP32, then LSQR (FP32) for 50 iterations
+    on noise-free data d = J dc (FP64 operator), undamped."""
+    from paper_1908_03302_amd import inputs as I
+    t0 = time.perf_counter()
+    w = I.slices3d()
+    ctx = fftt.context_for_workload(w, device=0)
+    t1 = time.perf_counter()
+    ctx.prepare()
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t1
+    pv_op, pv, lanes = ctx.work_count()
+    dev = torch.device("cuda:0")
+    dc = torch.tensor(w.model, dtype=torch.float32, device=dev)
+    dT = torch.empty(w.m, dtype=torch.float32, device=dev)
+    dc2 = torch.empty(w.n, dtype=torch.float32, device=dev)
+    ctx.apply_J(dc, dT)
+    ctx.apply_JT(dT, dc2)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.apply_J(dc, dT)
+        ctx.apply_JT(dT, dc2)
+    j, jt, rd = ctx.kernel_time(0), ctx.kernel_time(1), ctx.kernel_time(2)
+    ctx.profile(False)
+    ms_j, ms_jt, ms_rd = j[0] / j[1], jt[0] / jt[1], rd[0] / rd[1]
+    d64 = ctx.apply_J(torch.tensor(w.model, dtype=torch.float64, device=dev), prec=fftt.FP64)
+    d = d64.float()
+    x = torch.zeros(w.n, dtype=torch.float32, device=dev)
+    r = ctx.solve(d, x, method=1, prec=fftt.FP32, alpha=0.0, noise_sigma=1.0,
+                  max_iter=lsqr_iters)
+    fpv = flops_per_pv(1, 1)
+    log("bench: slices: prepare %.2f s, evaluated pv %d, J %.2f ms, J^T %.2f ms, "
+        "LSQR %d its %.0f ms" % (t_prep, pv, ms_j, ms_jt, r["iters"], r["time_ms"]))
+    out = {"workload": w.name, "pairs": w.m, "voxels": w.n, "active_voxels": int(w.mask.sum()),
+           "pv_per_apply": pv_op, "pv_evaluated_per_apply": pv, "prepare_s": t_prep,
+           "inputs_s": t1 - t0, "J_ms": ms_j, "JT_ms": ms_jt, "J_reduce_ms": ms_rd,
+           "pv_per_s": 2 * pv_op / ((ms_j + ms_jt + ms_rd) * 1e-3),
+           "J_tflops": pv * fpv / (ms_j * 1e-3) / 1e12,
+           "JT_tflops": pv * fpv / (ms_jt * 1e-3) / 1e12,
+           "lsqr": {"iters": r["iters"], "ms": r["time_ms"], "rel_resid": r["rel_resid"],
+                    "prec": "fp32", "damp": 0.0}}
+    del ctx, dc, dT, dc2, d64, d, x
+    torch.cuda.empty_cache()
+    return out
 
 
 def cg_time_to_misfit(ctx, w, fftt, torch, iters):

@@ -939,16 +939,21 @@ __device__ __forceinline__ int64_t first_source_at_least(const Entry* __restrict
 // it; e0 .. e1 is this wavefront's share of the block's entries (multiples of
 // U).  The staged values are valid inside body only.
 template <int U, class F>
-__device__ __forceinline__ void for_each_block(const ApplyArgs& A, int64_t a, const LaneVox& V,
-                                               float2* sx, int lane, F&& body) {
+__device__ __forceinline__ void for_each_block(const ApplyArgs& A, int64_t a, float2* sx,
+                                               int lane, F&& body) {
     const int Q = A.stage_q;
     const int W = (int)(blockDim.x >> 6);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
     for (int64_t b0 = t0; b0 < t1;) {
         const int q0 = (int)(A.ents[b0].sr & 0xffffu) / Q * Q;
-        const int64_t b1 = first_source_at_least(A.ents, b0, t1, q0 + Q);
-        stage_distances(A, a, V, sx, lane, q0, min(Q, (int)A.n_tx - q0));
+        // usually one block holds all of the tile's remaining entries
+        const int64_t b1 = (int)(A.ents[t1 - 1].sr & 0xffffu) < q0 + Q
+                               ? t1
+                               : first_source_at_least(A.ents, b0, t1, q0 + Q);
+        // the lane's voxel offsets are recomputed per block rather than kept
+        // live through the entry loop
+        stage_distances(A, a, lane_vox(A, a, lane), sx, lane, q0, min(Q, (int)A.n_tx - q0));
         int64_t chunk = (b1 - b0 + W - 1) / W;
         chunk = (chunk + U - 1) / U * U;
         const int64_t e0 = min(b1, b0 + (int64_t)wave * chunk);
@@ -1011,9 +1016,14 @@ __device__ __forceinline__ StepWeights<NB, U> load_weights(const ApplyArgs& A,
     StepWeights<NB, U> W;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int pv = __builtin_amdgcn_update_dpp(0, E.p[u], 0xe4, 0xf, 0xf, false);
+        // 32-bit byte offset, scaled on the scalar side; the band's base stays
+        // in scalar registers
+        const uint32_t off =
+            __builtin_amdgcn_update_dpp(0u, (uint32_t)E.p[u] << 2, 0xe4, 0xf, 0xf, false);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) W.w[u][b] = w[b * A.M + pv];
+        for (int b = 0; b < NB; ++b)
+            W.w[u][b] = *reinterpret_cast<const float*>(
+                reinterpret_cast<const char*>(w + (size_t)b * A.M) + off);
     }
     return W;
 }
@@ -1047,17 +1057,16 @@ __device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, c
 }
 
 template <int NB, class TabT, int U>
-__global__ __launch_bounds__(1024, 8) void k_jt32s(ApplyArgs A) {
+__global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_jt32s(ApplyArgs A) {
     const TabT* st = stage_table<TabT>(A, NB);
     float2* sx = staged_tx<TabT>(A, NB);
     const int64_t a = blockIdx.x;
     if (a >= A.n_act) return;
     const int lane = threadIdx.x & 63;
-    const LaneVox V = lane_vox(A, a, lane);
     const float* __restrict__ w = static_cast<const float*>(A.w);
     const float nm1 = (float)(A.ntab - 1);
     float acc = 0.f;
-    for_each_block<U>(A, a, V, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
+    for_each_block<U>(A, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
         float cd = 0.f, cg = 0.f;
         int prev = -1;
         int64_t e = e0;
@@ -1082,7 +1091,10 @@ __global__ __launch_bounds__(1024, 8) void k_jt32s(ApplyArgs A) {
     const int W = (int)(blockDim.x >> 6);
     float t = s_acc[lane];
     for (int k = 1; k < W; ++k) t += s_acc[k * 64 + lane];
-    if (V.inside) static_cast<float*>(A.out)[V.vidx] = V.act ? t : 0.f;
+    bool inside, act;
+    int64_t vidx, v[3];
+    voxel_of_lane(A, A.tiles[a], lane, inside, act, vidx, v);
+    if (inside) static_cast<float*>(A.out)[vidx] = act ? t : 0.f;
 }
 
 template <int NB, class TabT, int U>
@@ -1121,17 +1133,22 @@ __device__ __forceinline__ void j32s_body(const ApplyArgs& A, const TabT* st, co
 }
 
 template <int NB, class TabT, int U>
-__global__ __launch_bounds__(1024, 8) void k_j32s(ApplyArgs A) {
+__global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_j32s(ApplyArgs A) {
     const TabT* st = stage_table<TabT>(A, NB);
     float2* sx = staged_tx<TabT>(A, NB);
     const int64_t a = blockIdx.x;
     if (a >= A.n_act) return;
     const int lane = threadIdx.x & 63;
-    const LaneVox V = lane_vox(A, a, lane);
     float* __restrict__ part = static_cast<float*>(A.out);
-    const float xv = V.act ? static_cast<const float*>(A.x)[V.vidx] : 0.f;
+    float xv;
+    {
+        bool inside, act;
+        int64_t vidx, v[3];
+        voxel_of_lane(A, A.tiles[a], lane, inside, act, vidx, v);
+        xv = act ? static_cast<const float*>(A.x)[vidx] : 0.f;
+    }
     const float nm1 = (float)(A.ntab - 1);
-    for_each_block<U>(A, a, V, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
+    for_each_block<U>(A, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
         float cd = 0.f, cg = 0.f;
         int prev = -1;
         int64_t e = e0;

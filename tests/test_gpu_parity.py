@@ -324,3 +324,37 @@ def test_launch_shapes_agree(ragged, wpb, unroll, split, staged, stab):
     finally:
         ctx.set_tuning(waves_per_block=16, unroll_jt=2, unroll_j=4, split_jt=0, split_j=1,
                        staged=1, unroll_jt_staged=8, unroll_j_staged=8, staged_table=0)
+
+
+# ------------------------------------------------ slice-by-slice (full size)
+
+@pytest.fixture(scope="module")
+def slices3d():
+    w = I.slices3d()
+    say("fixture slices3d:", w.name, "M", w.m, "N", w.n)
+    ctx = _fftt().context_for_workload(w)
+    ctx.prepare()
+    o = oracle.Oracle.from_workload(w)
+    return w, o, ctx
+
+
+def test_slices3d_sampled_rows_and_columns(slices3d):
+    """256 transducers at 16 heights (1 044 480 pairs) on the 256x256x160
+    grid, FP32 (staged by ring-sized transducer blocks) and BF16 table:
+    sampled rows of J dc (the blob phantom) and sampled columns of J^T dT
+    against the oracle; the operator's work count against the oracle's."""
+    w, o, ctx = slices3d
+    f = _fftt()
+    rng = np.random.default_rng(19)
+    rows = np.sort(rng.choice(w.m, 24, replace=False))
+    act = np.flatnonzero(w.mask)
+    cols = np.sort(rng.choice(act, 256, replace=False))
+    yt = I.random_vector(w.m, 20) * 1e-7
+    y_ref = o.rows(rows, w.model)
+    x_ref = o.cols(cols, yt)
+    for prec, bar in ((f.FP32, 1e-5), (f.FP32_BF16TABLE, 1e-3)):
+        y = host(ctx.apply_J(dev(w.model, f.FP32), prec=prec))
+        xg = host(ctx.apply_JT(dev(yt, f.FP32), prec=prec))
+        ej, et = rel(y[rows], y_ref), rel(xg[cols], x_ref)
+        say("slices3d", prec, "sampled rows", ej, "cols", et)
+        assert ej < bar and et < bar
