@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--no-psf", action="store_true", help="skip the batched PSF leg")
     ap.add_argument("--no-multiband", action="store_true", help="skip the four-band leg")
     ap.add_argument("--no-slices", action="store_true", help="skip the 16-height slice leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch shapes instead of the autotuner's")
     ap.add_argument("--cg-iters", type=int, default=20)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
@@ -141,6 +143,11 @@ def main():
     pv_op, pv, lanes = ctx.work_count()
     log("bench: prepare %.2f s, operator pv %d, evaluated pv %d, lanes %d (%.1f%% useful)"
         % (time.perf_counter() - t0, pv_op, pv, lanes, 100.0 * pv / max(lanes, 1)))
+    tuning = None
+    if not args.no_autotune and args.waves_per_block is None and args.staged is None:
+        t0 = time.perf_counter()
+        tuning = ctx.autotune(prec=fftt.FP32, max_seconds=3.0)
+        log("bench: autotune %.1f s: %s" % (time.perf_counter() - t0, tuning))
     dev = torch.device("cuda:0")
     dc = torch.tensor(w.model, dtype=torch.float32, device=dev)
     dT = torch.empty(w.m, dtype=torch.float32, device=dev)
@@ -183,6 +190,7 @@ def main():
     # is value_evaluated, and the roofline counts only evaluated work.
     value = 2.0 * pv_op * args.steps / (ms * 1e-3)
     ms_red, n_red = avg_red, 1
+    staged = ctx.get_tuning()["staged"] == 1
     sfx = "s" if staged else ""
     dom, avg = (("k_jt32%s" % sfx, avg_jt) if avg_jt >= avg_j else ("k_j32%s" % sfx, avg_j))
     fpv = flops_per_pv(1, 1)
@@ -209,6 +217,7 @@ def main():
                    "pv_per_apply": pv_op, "pv_evaluated_per_apply": pv,
                    "reciprocity": True, "step": "1 J + 1 J^T"},
         "value_evaluated": 2.0 * pv / (ms_step * 1e-3),
+        "launch_shape": ctx.get_tuning(), "autotuned": tuning is not None,
         "kernels_ms": {"J": avg_j, "JT": avg_jt, "J_reduce": ms_red / max(n_red, 1)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -328,6 +337,7 @@ def slices_leg(fftt, torch, reps=3, lsqr_iters=50):
     torch.cuda.synchronize()
     t_prep = time.perf_counter() - t1
     pv_op, pv, lanes = ctx.work_count()
+    tuning = ctx.autotune(prec=fftt.FP32, max_seconds=5.0)
     dev = torch.device("cuda:0")
     dc = torch.tensor(w.model, dtype=torch.float32, device=dev)
     dT = torch.empty(w.m, dtype=torch.float32, device=dev)
@@ -357,7 +367,8 @@ def slices_leg(fftt, torch, reps=3, lsqr_iters=50):
            "J_tflops": pv * fpv / (ms_j * 1e-3) / 1e12,
            "JT_tflops": pv * fpv / (ms_jt * 1e-3) / 1e12,
            "lsqr": {"iters": r["iters"], "ms": r["time_ms"], "rel_resid": r["rel_resid"],
-                    "prec": "fp32", "damp": 0.0}}
+                    "prec": "fp32", "damp": 0.0},
+           "launch_shape": tuning}
     del ctx, dc, dT, dc2, d64, d, x
     torch.cuda.empty_cache()
     return out

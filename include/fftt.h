@@ -212,6 +212,18 @@ enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_
        FFTT_TUNE_STAGED_BLOCK = 10 };
 fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
 
+/* Current value of a tuning key (FFTT_E_INVALID for an unknown key). */
+fftt_status fftt_get_tuning(fftt_ctx *ctx, int32_t key, int32_t *value);
+
+/* Launch-shape autotuner: on the current geometry and tables, times the
+ * J and J^T kernels (HIP events, library scratch vectors) under candidate
+ * shapes -- staged or per-wavefront kernels, wavefronts per workgroup
+ * (chosen for J + J^T together), unroll and split per operator, FP32 table
+ * layout -- and keeps the fastest.  Stops trying new candidates after
+ * max_seconds (> 0).  Results of the operators do not depend on the shape.
+ * Synchronises the stream; FFTT_E_STATE before geometry and tables. */
+fftt_status fftt_autotune(fftt_ctx *ctx, fftt_precision prec, double max_seconds);
+
 /* Measurement aid.  With enable != 0 every launch of the main operator
  * kernels is bracketed by HIP events on the context's stream; enabling
  * clears the record.  fftt_kernel_time sums the recorded durations (ms) and

@@ -661,6 +661,139 @@ fftt_status fftt_apply_JT(fftt_ctx* c, fftt_precision prec, const void* dT, void
     return FFTT_OK;
 }
 
+fftt_status fftt_get_tuning(fftt_ctx* c, int32_t key, int32_t* value) {
+    if (!c || !value) return FFTT_E_INVALID;
+    switch (key) {
+        case FFTT_TUNE_WAVES_PER_BLOCK: *value = c->waves_per_block; return FFTT_OK;
+        case FFTT_TUNE_UNROLL_JT: *value = c->unroll_jt; return FFTT_OK;
+        case FFTT_TUNE_UNROLL_J: *value = c->unroll_j; return FFTT_OK;
+        case FFTT_TUNE_SPLIT_JT: *value = c->split_jt; return FFTT_OK;
+        case FFTT_TUNE_SPLIT_J: *value = c->split_j; return FFTT_OK;
+        case FFTT_TUNE_STAGED: *value = c->staged; return FFTT_OK;
+        case FFTT_TUNE_UNROLL_JT_STAGED: *value = c->unroll_jts; return FFTT_OK;
+        case FFTT_TUNE_UNROLL_J_STAGED: *value = c->unroll_js; return FFTT_OK;
+        case FFTT_TUNE_STAGED_TABLE: *value = c->staged_pair_table; return FFTT_OK;
+        case FFTT_TUNE_RECIPROCITY: *value = c->reciprocity; return FFTT_OK;
+        case FFTT_TUNE_STAGED_BLOCK: *value = c->staged_block_max; return FFTT_OK;
+    }
+    FFTT_BAD(c, "unknown tuning key");
+}
+
+// Mean time (ms) of `reps` launches of one operator's main kernel, after one
+// untimed launch, under the current launch shape.
+static fftt_status time_operator(fftt_ctx* c, fftt_precision prec, bool transpose, const void* x,
+                                 void* y, int reps, double* ms) {
+    fftt_status st = transpose ? apply_JT_one(c, prec, y, const_cast<void*>(x))
+                               : apply_J_one(c, prec, x, y);
+    if (st != FFTT_OK) return st;
+    hipEvent_t e0, e1;
+    FFTT_HIP(c, hipEventCreate(&e0));
+    FFTT_HIP(c, hipEventCreate(&e1));
+    FFTT_HIP(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps && st == FFTT_OK; ++r)
+        st = transpose ? apply_JT_one(c, prec, y, const_cast<void*>(x)) : apply_J_one(c, prec, x, y);
+    FFTT_HIP(c, hipEventRecord(e1, c->stream));
+    FFTT_HIP(c, hipEventSynchronize(e1));
+    float t = 0.f;
+    FFTT_HIP(c, hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t / reps;
+    return st;
+}
+
+fftt_status fftt_autotune(fftt_ctx* c, fftt_precision prec, double max_seconds) {
+    if (!c) return FFTT_E_INVALID;
+    if (prec < FFTT_FP64 || prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "autotune: unknown precision");
+    if (!(max_seconds > 0)) FFTT_BAD(c, "autotune: max_seconds must be > 0");
+    fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    const bool fp64 = prec == FFTT_FP64;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    DevBuf xb, yb;
+    FFTT_HIP(c, xb.alloc((size_t)c->N * es));
+    FFTT_HIP(c, yb.alloc((size_t)c->nb * c->M * es));
+    FFTT_HIP(c, launch_fill_value(c->stream, fp64, xb.p, c->N, 1.0));
+    FFTT_HIP(c, launch_fill_value(c->stream, fp64, yb.p, (int64_t)c->nb * c->M, 1e-7));
+    const bool prof = c->prof;
+    c->prof = false;
+    // the current shape is the baseline; its cost sets the repetitions
+    double tj = 0, tjt = 0;
+    st = time_operator(c, prec, false, xb.p, yb.p, 1, &tj);
+    if (st == FFTT_OK) st = time_operator(c, prec, true, xb.p, yb.p, 1, &tjt);
+    if (st != FFTT_OK) {
+        c->prof = prof;
+        return st;
+    }
+    const double per = std::max(tj + tjt, 1e-3);
+    const int reps = std::max(1, std::min(5, (int)(0.05 * 1e3 * max_seconds / per)));
+    auto t_start = std::chrono::steady_clock::now();
+    auto budget_left = [&]() {
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start)
+                              .count();
+        return el < max_seconds;
+    };
+    struct Shape { int wpb, staged, table, uj, ujt, sj, sjt; };
+    Shape best{c->waves_per_block, c->staged, c->staged_pair_table, 0, 0, c->split_j, c->split_jt};
+    best.uj = c->staged ? c->unroll_js : c->unroll_j;
+    best.ujt = c->staged ? c->unroll_jts : c->unroll_jt;
+    double best_j = 1e30, best_jt = 1e30;
+    const int wpbs[] = {16, 8, 4};
+    const int tables = fp64 || prec == FFTT_FP32_BF16TABLE ? 1 : 2;
+    for (int staged = 1; staged >= 0 && st == FFTT_OK; --staged) {
+        if (fp64 && staged) continue;
+        for (int wpb : wpbs) {
+            for (int table = 0; table < (staged ? tables : 1); ++table) {
+                c->waves_per_block = wpb;
+                c->staged = staged;
+                c->staged_pair_table = table;
+                if (staged && !staged_q(c, prec)) continue;
+                const int* us;
+                static const int us_staged[] = {2, 4, 8, 0};
+                static const int us_wave[] = {2, 4, 0};
+                us = staged ? us_staged : us_wave;
+                double bj = 1e30, bjt = 1e30;
+                int buj = us[0], bujt = us[0], bsj = c->split_j, bsjt = c->split_jt;
+                for (const int* u = us; *u && st == FFTT_OK && budget_left(); ++u) {
+                    for (int split = staged ? 1 : 0; split <= 1; ++split) {
+                        if (staged) {
+                            c->unroll_js = c->unroll_jts = *u;
+                        } else {
+                            c->unroll_j = c->unroll_jt = *u;
+                            c->split_j = c->split_jt = split;
+                        }
+                        double a = 0, b = 0;
+                        st = time_operator(c, prec, false, xb.p, yb.p, reps, &a);
+                        if (st == FFTT_OK) st = time_operator(c, prec, true, xb.p, yb.p, reps, &b);
+                        if (st != FFTT_OK) break;
+                        if (a < bj) { bj = a; buj = *u; bsj = split; }
+                        if (b < bjt) { bjt = b; bujt = *u; bsjt = split; }
+                    }
+                }
+                if (st == FFTT_OK && bj + bjt < best_j + best_jt) {
+                    best_j = bj;
+                    best_jt = bjt;
+                    best = Shape{wpb, staged, table, buj, bujt, bsj, bsjt};
+                }
+            }
+        }
+    }
+    c->prof = prof;
+    c->waves_per_block = best.wpb;
+    c->staged = best.staged;
+    c->staged_pair_table = best.table;
+    c->split_j = best.sj;
+    c->split_jt = best.sjt;
+    if (best.staged) {
+        c->unroll_js = best.uj;
+        c->unroll_jts = best.ujt;
+    } else {
+        c->unroll_j = best.uj;
+        c->unroll_jt = best.ujt;
+    }
+    return st;
+}
+
 fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
     if (!c) return FFTT_E_INVALID;
     switch (key) {

@@ -117,6 +117,7 @@ hipError_t launch_weights(hipStream_t s, bool fp64, const void* dT, const int32_
                           const int32_t* kidx, const double* C, int64_t Mk, int64_t M, int nb,
                           void* w);
 hipError_t launch_fill(hipStream_t s, bool fp64, void* p, int64_t n);
+hipError_t launch_fill_value(hipStream_t s, bool fp64, void* p, int64_t n, double v);
 hipError_t launch_apply(hipStream_t s, fftt_precision prec, bool transpose,
                         const ApplyArgs& a);
 // Table formats of the staged kernels.
@@ -215,7 +216,7 @@ struct fftt_ctx {
     int unroll_j = 4;
     int split_jt = 0, split_j = 1;
     int staged = 1;            // use the LDS-staged kernels when they fit
-    int unroll_jts = 8, unroll_js = 8;
+    int unroll_jts = 8, unroll_js = 4;
     int staged_pair_table = 0; // FP32 staged kernels: 0 node table, 1 (h, slope) pairs
     int staged_block_max = 0;  // cap on the staged block size (0: LDS decides)
     size_t lds_limit = 65536;

@@ -403,6 +403,22 @@ __global__ void k_fill0(T* __restrict__ p, int64_t n) {
     if (i < n) p[i] = (T)0;
 }
 
+template <class T>
+__global__ void k_fillv(T* __restrict__ p, int64_t n, T v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_value(hipStream_t s, bool fp64, void* p, int64_t n, double v) {
+    if (n == 0) return hipSuccess;
+    const unsigned nblk = (unsigned)((n + 255) / 256);
+    if (fp64)
+        hipLaunchKernelGGL(k_fillv<double>, dim3(nblk), dim3(256), 0, s, (double*)p, n, v);
+    else
+        hipLaunchKernelGGL(k_fillv<float>, dim3(nblk), dim3(256), 0, s, (float*)p, n, (float)v);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(hipStream_t s, bool fp64, void* p, int64_t n) {
     if (n == 0) return hipSuccess;
     const unsigned nblk = (unsigned)((n + 255) / 256);

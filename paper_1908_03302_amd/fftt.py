@@ -23,7 +23,8 @@ _STATUS = {0: "FFTT_OK", -1: "FFTT_E_INVALID", -2: "FFTT_E_NOMEM", -3: "FFTT_E_D
 EXPORTS = ["fftt_create", "fftt_destroy", "fftt_last_error", "fftt_set_stream",
            "fftt_set_geometry", "fftt_set_kernel_table", "fftt_build_table_from_pulse",
            "fftt_prepare", "fftt_work_count", "fftt_apply_J", "fftt_apply_JT", "fftt_solve",
-           "fftt_psf", "fftt_profile", "fftt_kernel_time", "fftt_set_tuning"]
+           "fftt_psf", "fftt_profile", "fftt_kernel_time", "fftt_set_tuning", "fftt_get_tuning",
+           "fftt_autotune"]
 TUNE_WAVES_PER_BLOCK, TUNE_UNROLL_JT, TUNE_UNROLL_J, TUNE_SPLIT_JT, TUNE_SPLIT_J = 0, 1, 2, 3, 4
 TUNE_STAGED, TUNE_UNROLL_JT_STAGED, TUNE_UNROLL_J_STAGED = 5, 6, 7
 TUNE_STAGED_TABLE = 8
@@ -81,6 +82,8 @@ def load():
     L.fftt_psf.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.c_int32, C.c_double, vp]
     L.fftt_profile.argtypes = [vp, C.c_int32]
     L.fftt_set_tuning.argtypes = [vp, C.c_int32, C.c_int32]
+    L.fftt_get_tuning.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
+    L.fftt_autotune.argtypes = [vp, C.c_int, C.c_double]
     L.fftt_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or C.c_int
@@ -196,6 +199,27 @@ class Context:
                        (TUNE_STAGED_BLOCK, staged_block)):
             if v is not None:
                 self._check(self.L.fftt_set_tuning(self.h, key, int(v)), "set_tuning")
+
+    TUNING_KEYS = {"waves_per_block": TUNE_WAVES_PER_BLOCK, "unroll_jt": TUNE_UNROLL_JT,
+                   "unroll_j": TUNE_UNROLL_J, "split_jt": TUNE_SPLIT_JT, "split_j": TUNE_SPLIT_J,
+                   "staged": TUNE_STAGED, "unroll_jt_staged": TUNE_UNROLL_JT_STAGED,
+                   "unroll_j_staged": TUNE_UNROLL_J_STAGED, "staged_table": TUNE_STAGED_TABLE,
+                   "reciprocity": TUNE_RECIPROCITY, "staged_block": TUNE_STAGED_BLOCK}
+
+    def get_tuning(self):
+        """All tuning keys and their current values."""
+        out = {}
+        for name, key in self.TUNING_KEYS.items():
+            v = C.c_int32()
+            self._check(self.L.fftt_get_tuning(self.h, key, C.byref(v)), "get_tuning")
+            out[name] = v.value
+        return out
+
+    def autotune(self, prec=FP32, max_seconds=5.0):
+        """Time candidate launch shapes and keep the fastest; returns them."""
+        self._bind_stream()
+        self._check(self.L.fftt_autotune(self.h, int(prec), float(max_seconds)), "autotune")
+        return self.get_tuning()
 
     def profile(self, enable=True):
         self._check(self.L.fftt_profile(self.h, 1 if enable else 0), "profile")

@@ -86,4 +86,4 @@ def test_block_sizes_agree_with_oracle(stack, block, staged, unroll):
                 say("blocks", block, "staged", staged, "prec", prec, "J", ej, "J^T", et)
                 assert ej < bar and et < bar
     finally:
-        ctx.set_tuning(staged=1, staged_block=0, unroll_jt_staged=8, unroll_j_staged=8)
+        ctx.set_tuning(staged=1, staged_block=0, unroll_jt_staged=8, unroll_j_staged=4)

@@ -323,7 +323,7 @@ def test_launch_shapes_agree(ragged, wpb, unroll, split, staged, stab):
                 assert rel(y, y_ref) < 1e-5 and rel(xg, x_ref) < 1e-5
     finally:
         ctx.set_tuning(waves_per_block=16, unroll_jt=2, unroll_j=4, split_jt=0, split_j=1,
-                       staged=1, unroll_jt_staged=8, unroll_j_staged=8, staged_table=0)
+                       staged=1, unroll_jt_staged=8, unroll_j_staged=4, staged_table=0)
 
 
 # ------------------------------------------------ slice-by-slice (full size)
@@ -358,3 +358,29 @@ def test_slices3d_sampled_rows_and_columns(slices3d):
         ej, et = rel(y[rows], y_ref), rel(xg[cols], x_ref)
         say("slices3d", prec, "sampled rows", ej, "cols", et)
         assert ej < bar and et < bar
+
+
+# ------------------------------------------------------------ autotuner
+
+@pytest.mark.parametrize("prec_name", ["FP32", "FP64"])
+def test_autotune_keeps_results(ragged, prec_name):
+    """The autotuner picks a valid launch shape; the operators still agree
+    with the oracle afterwards."""
+    w, o, ot, ctx = ragged
+    f = _fftt()
+    prec = getattr(f, prec_name)
+    before = ctx.get_tuning()
+    try:
+        chosen = ctx.autotune(prec=prec, max_seconds=3.0)
+        say("autotune", prec_name, chosen)
+        assert chosen["waves_per_block"] in (4, 8, 16)
+        x = I.random_vector(w.n, 70) * 5.0
+        yt = I.random_vector(2 * w.m, 71) * 1e-7
+        y = host(ctx.apply_J(dev(x, prec), prec=prec)).reshape(2, -1)
+        xg = host(ctx.apply_JT(dev(yt, prec), prec=prec))
+        if prec == f.FP64:
+            assert rel(y, ot.apply_J(x)) < 1e-11 and rel(xg, ot.apply_JT(yt)) < 1e-11
+        else:
+            assert rel(y, o.apply_J(x)) < 1e-5 and rel(xg, o.apply_JT(yt)) < 1e-5
+    finally:
+        ctx.set_tuning(**before)
