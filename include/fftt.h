@@ -140,8 +140,13 @@ fftt_status fftt_apply_JT(fftt_ctx *ctx, fftt_precision prec, const void *dT,
  * (if > 0), or once the normal-equation residual falls by rel_tol (if > 0).
  *   d_obs: device [B][M]; x: device [N], in: x0 (used as start when
  *   opts->use_x0 != 0, else zero), out: estimate.  Synchronises once at the
- *   end; rep receives iterations, final misfit (evaluated in the solver's
- *   arithmetic), relative normal residual and elapsed time. */
+ *   end (and once per iteration when a target or tolerance is set); rep
+ *   receives iterations, final misfit (evaluated in the solver's
+ *   arithmetic), relative normal residual and elapsed time.
+ *   use_graph != 0: the second iteration is captured into a HIP graph on the
+ *   context's stream and replayed for the remaining ones (one launch per
+ *   iteration instead of ~20); results are identical to use_graph = 0.  The
+ *   stream must not be used by other work during the solve. */
 typedef struct {
     int32_t method;
     int32_t prec;            /* fftt_precision */
@@ -151,6 +156,7 @@ typedef struct {
     int32_t use_x0;
     double target_misfit;
     double rel_tol;
+    int32_t use_graph;
 } fftt_solve_opts;
 
 typedef struct {

@@ -453,6 +453,52 @@ fftt_status ensure_ready(fftt_ctx* c) {
 
 }  // namespace
 
+// Solver iterations in a HIP graph: iteration 0 runs eagerly (it allocates
+// the operators' work buffers); with `on`, iteration 1 is captured once on
+// the context's stream and every later iteration replays the graph.  Event
+// timing of the kernels is off while it lives.
+struct IterGraph {
+    fftt_ctx* c;
+    bool on;
+    bool prof;
+    hipGraphExec_t exec = nullptr;
+    ~IterGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        c->prof = prof;
+    }
+    template <class F>
+    fftt_status step(int it, F&& body) {
+        if (!on || it == 0) return body();
+        if (!exec) {
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) {
+                c->err = std::string("solve: graph capture: ") + hipGetErrorString(e);
+                return FFTT_E_DEVICE;
+            }
+            const fftt_status sb = body();
+            e = hipStreamEndCapture(c->stream, &g);
+            if (sb != FFTT_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return sb;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                exec = nullptr;
+                c->err = std::string("solve: graph: ") + hipGetErrorString(e);
+                return FFTT_E_DEVICE;
+            }
+        }
+        const hipError_t e = hipGraphLaunch(exec, c->stream);
+        if (e != hipSuccess) {
+            c->err = std::string("solve: graph launch: ") + hipGetErrorString(e);
+            return FFTT_E_DEVICE;
+        }
+        return FFTT_OK;
+    }
+};
+
 extern "C" {
 
 fftt_status fftt_create(fftt_ctx** out, int device, void* hip_stream) {
@@ -870,9 +916,39 @@ fftt_status fftt_kernel_time(fftt_ctx* c, int32_t which, double* ms, int64_t* la
     return FFTT_OK;
 }
 
+static fftt_status solve_impl(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs, void* x,
+                              fftt_solve_report* rep);
+
 fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs, void* x,
                        fftt_solve_report* rep) {
     if (!c) return FFTT_E_INVALID;
+    if (!o || !o->use_graph || c->stream != nullptr) return solve_impl(c, o, d_obs, x, rep);
+    // the null stream cannot be captured: run on the context's private
+    // stream, ordered after the caller's earlier work and before its later
+    fftt_status st = set_device(c);
+    if (st != FFTT_OK) return st;
+    if (!c->graph_stream)
+        FFTT_HIP(c, hipStreamCreateWithFlags(&c->graph_stream, hipStreamNonBlocking));
+    hipEvent_t ev;
+    FFTT_HIP(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, nullptr);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->graph_stream, ev, 0);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        FFTT_HIP(c, e);
+    }
+    c->stream = c->graph_stream;
+    st = solve_impl(c, o, d_obs, x, rep);
+    c->stream = nullptr;
+    e = hipEventRecord(ev, c->graph_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(nullptr, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) FFTT_HIP(c, e);
+    return st;
+}
+
+static fftt_status solve_impl(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs, void* x,
+                              fftt_solve_report* rep) {
     if (!o || !d_obs || !x) FFTT_BAD(c, "solve: null argument");
     if (o->method != 0 && o->method != 1) FFTT_BAD(c, "solve: method must be 0 (CGLS) or 1 (LSQR)");
     if (o->prec < FFTT_FP64 || o->prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "solve: unknown precision");
@@ -911,6 +987,8 @@ fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs,
         fftt_status st_ = (expr);            \
         if (st_ != FFTT_OK) return st_;      \
     } while (0)
+    IterGraph graph{c, o->use_graph != 0, c->prof};
+    if (graph.on) c->prof = false;
     const auto t0 = std::chrono::steady_clock::now();
     int it = 0;
     double misfit = 0.0, relres = 0.0;
@@ -930,7 +1008,7 @@ fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs,
         FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, GAMMA, 1.0));
         FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, G0, 1.0));
         FFTT_HIP(c, solver_dot(s, fp64, r, r, D, part, sc, MIS, 1.0));
-        for (it = 0; it < o->max_iter;) {
+        auto iteration = [&]() -> fftt_status {
             SOLVE_OK(apply_J_one(c, prec, p, q));
             FFTT_HIP(c, solver_dot(s, fp64, q, q, D, part, sc, DQ, isg * isg));
             FFTT_HIP(c, solver_dot(s, fp64, p, p, N, part, sc, DP, 1.0));
@@ -943,6 +1021,10 @@ fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs,
             FFTT_HIP(c, solver_cgls_beta(s, sc));
             FFTT_HIP(c, solver_axpby(s, fp64, p, sv, N, 1.0, BETA, 1.0, -1, sc));
             FFTT_HIP(c, solver_dot(s, fp64, r, r, D, part, sc, MIS, 1.0));
+            return FFTT_OK;
+        };
+        for (it = 0; it < o->max_iter;) {
+            SOLVE_OK(graph.step(it, iteration));
             ++it;
             if (check) {
                 SOLVE_OK(fetch());
@@ -973,7 +1055,7 @@ fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs,
         FFTT_HIP(c, solver_lsqr_alpha_rot(s, sc, damp, 1));
         FFTT_HIP(c, solver_axpby(s, fp64, p, p, N, 0.0, -1, 1.0, INV_ALPHA, sc));     // v /= alpha
         FFTT_HIP(c, solver_lin2(s, fp64, wv, p, nullptr, N, 1.0, 0.0));             // w = v
-        for (it = 0; it < o->max_iter;) {
+        auto iteration = [&]() -> fftt_status {
             SOLVE_OK(apply_J_one(c, prec, p, q));
             FFTT_HIP(c, solver_axpby(s, fp64, r, q, D, -1.0, ALPHA, isg, -1, sc));   // u = Av - a u
             FFTT_HIP(c, solver_dot(s, fp64, r, r, D, part, sc, BETA, 1.0));
@@ -986,6 +1068,10 @@ fftt_status fftt_solve(fftt_ctx* c, const fftt_solve_opts* o, const void* d_obs,
             FFTT_HIP(c, solver_axpby(s, fp64, p, p, N, 0.0, -1, 1.0, INV_ALPHA, sc));
             FFTT_HIP(c, solver_axpby(s, fp64, x, wv, N, 1.0, -1, 1.0, PHI_RHO, sc));  // x += phi/rho w
             FFTT_HIP(c, solver_axpby(s, fp64, wv, p, N, 1.0, THETA_RHO, 1.0, -1, sc)); // w = v - theta/rho w
+            return FFTT_OK;
+        };
+        for (it = 0; it < o->max_iter;) {
+            SOLVE_OK(graph.step(it, iteration));
             ++it;
             if (check) {
                 FFTT_HIP(c, solver_dot(s, fp64, x, x, N, part, sc, XX, 1.0));

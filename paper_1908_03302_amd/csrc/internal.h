@@ -229,11 +229,15 @@ struct fftt_ctx {
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[4];
     size_t prof_used[4] = {0, 0, 0, 0};
+    // private stream of graph solves when the caller's stream is the null
+    // stream (which cannot be captured); default priority
+    hipStream_t graph_stream = nullptr;
     ~fftt_ctx() {
         for (auto& v : prof_ev)
             for (auto& e : v) {
                 (void)hipEventDestroy(e.first);
                 (void)hipEventDestroy(e.second);
             }
+        if (graph_stream) (void)hipStreamDestroy(graph_stream);
     }
 };

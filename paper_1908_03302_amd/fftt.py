@@ -35,7 +35,8 @@ TUNE_STAGED_BLOCK = 10
 class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("prec", C.c_int32), ("alpha", C.c_double),
                 ("noise_sigma", C.c_double), ("max_iter", C.c_int32), ("use_x0", C.c_int32),
-                ("target_misfit", C.c_double), ("rel_tol", C.c_double)]
+                ("target_misfit", C.c_double), ("rel_tol", C.c_double),
+                ("use_graph", C.c_int32)]
 
 
 class SolveReport(C.Structure):
@@ -264,9 +265,9 @@ class Context:
         return dc
 
     def solve(self, d_obs, x, method=0, prec=FP32, alpha=1e-3, noise_sigma=1.0, max_iter=20,
-              x0=False, target_misfit=0.0, rel_tol=0.0):
+              x0=False, target_misfit=0.0, rel_tol=0.0, graph=False):
         o = SolveOpts(int(method), int(prec), float(alpha), float(noise_sigma), int(max_iter),
-                      1 if x0 else 0, float(target_misfit), float(rel_tol))
+                      1 if x0 else 0, float(target_misfit), float(rel_tol), 1 if graph else 0)
         rep = SolveReport()
         self._bind_stream()
         st = self._check(self.L.fftt_solve(

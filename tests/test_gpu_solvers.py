@@ -139,3 +139,36 @@ def test_solver_argument_errors(small):
         gpu_solve(ctx, d, f.FP64, w.n, method=0, alpha=ALPHA, noise_sigma=0.0)
     with pytest.raises(f.FFTTError):
         ctx.psf(np.array([w.n + 5]), 1.0, prec=f.FP64)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("prec_name", ["FP32", "FP64"])
+def test_solve_graph_replays_match_eager(small, method, prec_name):
+    """With use_graph, iteration 2 is captured once and replayed; solves of
+    1, 2, 3 and 6 iterations (0 to 4 replays), with eager operator work and
+    synchronisations in between, give bit-identical iterates to the eager
+    solver.  A target-misfit stop (one host check per replay) too."""
+    w, Jd, ctx, d = small
+    f = F()
+    prec = getattr(f, prec_name)
+    sig = w.noise_sigma
+    probe = dev(w.model, prec)
+    for k in (1, 2, 3, 6):
+        xe, re_ = gpu_solve(ctx, d, prec, w.n, method=method, alpha=ALPHA, noise_sigma=sig,
+                            max_iter=k)
+        ctx.apply_J(probe, prec=prec)          # unrelated eager work on the stream
+        torch.cuda.synchronize()
+        xg, rg = gpu_solve(ctx, d, prec, w.n, method=method, alpha=ALPHA, noise_sigma=sig,
+                           max_iter=k, graph=True)
+        assert re_["iters"] == rg["iters"] == k
+        assert np.array_equal(xe, xg), (k, rel(xg, xe))
+        assert re_["misfit"] == rg["misfit"]
+    # early stop at a target misfit: same iteration count and iterate
+    _, r20 = gpu_solve(ctx, d, prec, w.n, method=method, alpha=ALPHA, noise_sigma=sig,
+                       max_iter=20)
+    target = r20["misfit"] * 1.05
+    xe, re_ = gpu_solve(ctx, d, prec, w.n, method=method, alpha=ALPHA, noise_sigma=sig,
+                        max_iter=40, target_misfit=target)
+    xg, rg = gpu_solve(ctx, d, prec, w.n, method=method, alpha=ALPHA, noise_sigma=sig,
+                       max_iter=40, target_misfit=target, graph=True)
+    assert re_["iters"] == rg["iters"] and np.array_equal(xe, xg)
