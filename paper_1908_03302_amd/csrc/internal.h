@@ -216,7 +216,7 @@ struct fftt_ctx {
     int unroll_j = 4;
     int split_jt = 0, split_j = 1;
     int staged = 1;            // use the LDS-staged kernels when they fit
-    int unroll_jts = 8, unroll_js = 4;
+    int unroll_jts = 8, unroll_js = 8;
     int staged_pair_table = 0; // FP32 staged kernels: 0 node table, 1 (h, slope) pairs
     int staged_block_max = 0;  // cap on the staged block size (0: LDS decides)
     size_t lds_limit = 65536;

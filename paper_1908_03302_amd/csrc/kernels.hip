@@ -915,12 +915,18 @@ struct StepEntries {
 };
 
 // Transducer indices are returned relative to the staged block's first one.
+// The entry lists are read-only during every kernel that reads them; reading
+// through the constant address space states it, so the compiler keeps these
+// wave-uniform loads on the scalar path even in kernels that store elsewhere.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+using ConstU4 = const __attribute__((address_space(4))) u32x4;
+
 template <int U>
 __device__ __forceinline__ StepEntries<U> load_entries(const Entry* __restrict__ ents, int64_t e,
                                                        int base) {
     StepEntries<U> E;
-    const uint4* __restrict__ raw = reinterpret_cast<const uint4*>(ents + e);
-    uint4 v[U];
+    ConstU4* raw = (ConstU4*)(ents + e);
+    u32x4 v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = raw[u];
 #pragma unroll
@@ -931,6 +937,13 @@ __device__ __forceinline__ StepEntries<U> load_entries(const Entry* __restrict__
         E.R0[u] = __uint_as_float(v[u].z);
     }
     return E;
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint64_t u = (uint64_t)x;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // Transducer blocks of the staged kernels: aligned index ranges
@@ -974,7 +987,9 @@ __device__ __forceinline__ void for_each_block(const ApplyArgs& A, int64_t a, fl
         chunk = (chunk + U - 1) / U * U;
         const int64_t e0 = min(b1, b0 + (int64_t)wave * chunk);
         const int64_t e1 = min(b1, e0 + chunk);
-        body(q0, e0, e1);
+        // wave-uniform by construction; stated so that the entries are read
+        // with scalar loads and handled by scalar instructions
+        body(__builtin_amdgcn_readfirstlane(q0), uniform64(e0), uniform64(e1));
         __syncthreads();   // before the next block is staged over this one
         b0 = b1;
     }
