@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--no-psf", action="store_true", help="skip the batched PSF leg")
     ap.add_argument("--no-multiband", action="store_true", help="skip the four-band leg")
     ap.add_argument("--no-slices", action="store_true", help="skip the 16-height slice leg")
+    ap.add_argument("--no-series", action="store_true",
+                    help="skip the sine-series evaluation leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of the autotuner's")
     ap.add_argument("--cg-iters", type=int, default=20)
@@ -248,6 +250,8 @@ def main():
         del cs
     if not args.no_psf:
         out["psf"] = psf_leg(ctx, w, fftt, torch, pv)
+    if not args.no_series:
+        out["series"] = series_leg(ctx, w, fftt, torch, pv, avg_j, avg_jt)
     del dc, dT, dc2
     if not args.no_multiband:
         out["multiband"] = multiband_leg(fftt, torch)
@@ -290,6 +294,44 @@ def psf_leg(ctx, w, fftt, torch, pv, reps=3):
             % (name, wall, kms, tf))
     del out
     return res
+
+
+def series_leg(ctx, w, fftt, torch, pv, table_j, table_jt, reps=5):
+    """J and J^T of the bench workload with the detour function evaluated as
+    the paper stores it, a sine series over uniform frequency nodes, instead
+    of the table.  Algorithmic flops per pv: 23 (geometry) + 4 per term
+    (Reinsch's recurrence) + 40 (sin/cos of the half angle, scaling) + 2."""
+    p = w.pulses[0]
+    a, beta = fftt.build_series_from_pulse(w.c0, p.samples, p.dt, w.r_max[0])
+    ctx.set_kernel_series(0, a, beta, w.r_max[0])
+    shape = ctx.get_tuning()
+    ctx.set_tuning(kernel_eval=1)
+    tuning = ctx.autotune(prec=fftt.FP32, max_seconds=3.0)
+    dev = torch.device("cuda:0")
+    dc = torch.tensor(w.model, dtype=torch.float32, device=dev)
+    dT = torch.empty(w.m, dtype=torch.float32, device=dev)
+    dc2 = torch.empty(w.n, dtype=torch.float32, device=dev)
+    for _ in range(2):
+        ctx.apply_J(dc, dT)
+        ctx.apply_JT(dT, dc2)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.apply_J(dc, dT)
+        ctx.apply_JT(dT, dc2)
+    j, jt = ctx.kernel_time(0), ctx.kernel_time(1)
+    ctx.profile(False)
+    ctx.set_tuning(kernel_eval=0, **{k: v for k, v in shape.items()
+                                    if k not in ("reciprocity", "kernel_eval")})
+    ms_j, ms_jt = j[0] / j[1], jt[0] / jt[1]
+    fpv = 23 + 4 * a.size + 40 + 2
+    log("bench: sine series (%d terms): J %.3f ms, J^T %.3f ms (table %.3f / %.3f)"
+        % (a.size, ms_j, ms_jt, table_j, table_jt))
+    return {"terms": int(a.size), "beta_r_max": beta * w.r_max[0], "J_ms": ms_j,
+            "JT_ms": ms_jt, "pv_per_s": 2 * pv / ((ms_j + ms_jt) * 1e-3),
+            "time_vs_table": (ms_j + ms_jt) / (table_j + table_jt), "flops_per_pv": fpv,
+            "J_tflops": pv * fpv / (ms_j * 1e-3) / 1e12,
+            "JT_tflops": pv * fpv / (ms_jt * 1e-3) / 1e12, "launch_shape": tuning}
 
 
 def multiband_leg(fftt, torch, reps=10):

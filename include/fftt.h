@@ -104,6 +104,35 @@ fftt_status fftt_build_table_from_pulse(double c0, const double *f, int64_t nt,
                                         double dt, int64_t n, double r_max,
                                         double *h_out, double *r_max_out);
 
+/* The paper's own representation of the detour function (Sec. II-C: the
+ * coefficients and arguments of the sines of eq. Kernel_freq, evaluated on
+ * the fly):  h(R) = sum_{m=1}^{n} a_m sin(m beta R) for 0 <= R < r_max and 0
+ * beyond.  Attaches such a series to a band whose table is already set with
+ * the same r_max (re-setting the table with another r_max drops it).
+ * a: host [n_terms], 1 <= n_terms <= 64; 0 < beta * r_max <= pi.  With
+ * FFTT_TUNE_KERNEL_EVAL = 1 the FP32 operators (apply_J, apply_JT and the
+ * solves built on them) evaluate the series instead of interpolating the
+ * table; they then return FFTT_E_STATE if a band has no series and
+ * FFTT_E_UNSUPPORTED where the LDS-staged kernels do not apply.  FP64,
+ * BF16-table and PSF evaluations keep the table. */
+fftt_status fftt_set_kernel_series(fftt_ctx *ctx, int32_t band, const double *a,
+                                   int32_t n_terms, double beta, double r_max);
+
+/* Host helper: the sine series of eq. Kernel_freq for a sampled pulse
+ * (S = |DTFT(f)|^2 as above): the frequency integrals as trapezoid sums over
+ * uniform nodes w_m = m dw, m = 1..n, so a_m = w_m^3 S(w_m) / sum_k w_k^2
+ * S(w_k) and beta = dw / c0.  dw = 2 pi c0 / (2.5 r_max): the series is
+ * periodic in R with period 2.5 r_max, so its first alias lies beyond
+ * 1.5 r_max.  n is the fewest nodes reaching past the last frequency where
+ * w^3 S exceeds tol times its maximum (e.g. tol = 1e-8: h within ~1e-10 of
+ * max|h|, far below FP32 rounding); FFTT_E_INVALID if
+ * that needs more than max_terms, or for bad arguments (r_max > 0 required).
+ * a_out: host [max_terms]; *n_terms_out, *beta_out returned. */
+fftt_status fftt_build_series_from_pulse(double c0, const double *f, int64_t nt,
+                                         double dt, double r_max, double tol,
+                                         int32_t max_terms, double *a_out,
+                                         int32_t *n_terms_out, double *beta_out);
+
 /* Build the device-side culling lists now (otherwise the first apply does).
  * Synchronises the stream. */
 fftt_status fftt_prepare(fftt_ctx *ctx);
@@ -204,6 +233,8 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *     at a time, which requires every pair to lie in one block (else the
  *     per-wavefront kernels run).  0 (default) = automatic, otherwise an
  *     upper bound on Q (a power of two >= 16).
+ *   FFTT_TUNE_KERNEL_EVAL: 0 (default) = the FP32 operators interpolate
+ *     the table, 1 = they sum the bands' sine series (fftt_set_kernel_series).
  *   FFTT_TUNE_RECIPROCITY: 1 (default) = a pair (s, r) and its reverse
  *     (r, s) have the same row of J (source-receiver reciprocity, Sec. II-B;
  *     the detour and L are symmetric), so each unordered pair is evaluated
@@ -215,7 +246,7 @@ enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_
        FFTT_TUNE_SPLIT_JT = 3, FFTT_TUNE_SPLIT_J = 4, FFTT_TUNE_STAGED = 5,
        FFTT_TUNE_UNROLL_JT_STAGED = 6, FFTT_TUNE_UNROLL_J_STAGED = 7,
        FFTT_TUNE_STAGED_TABLE = 8, FFTT_TUNE_RECIPROCITY = 9,
-       FFTT_TUNE_STAGED_BLOCK = 10 };
+       FFTT_TUNE_STAGED_BLOCK = 10, FFTT_TUNE_KERNEL_EVAL = 11 };
 fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
 
 /* Current value of a tuning key (FFTT_E_INVALID for an unknown key). */

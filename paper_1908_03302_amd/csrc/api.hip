@@ -26,6 +26,12 @@ using namespace fftt;
         return FFTT_E_INVALID;      \
     } while (0)
 
+#define FFTT_FAIL(ctx, code, msg)   \
+    do {                            \
+        (ctx)->err = (msg);         \
+        return (code);              \
+    } while (0)
+
 namespace {
 
 bool finite3(const double* v) {
@@ -94,6 +100,24 @@ fftt_status upload_tables(fftt_ctx* c) {
                           hipMemcpyHostToDevice));
     FFTT_HIP(c, hipMemcpy(c->d_tabbf.p, tbf.data(), tbf.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice));
+    // sine series: [theta/2 per table-coordinate unit, n rounded up to a
+    // multiple of 4 (int bits), 0, 0, a_1 .. a_n, zeros]
+    c->series_ready = true;
+    for (int b = 0; b < nb; ++b) c->series_ready = c->series_ready && !c->ser_a[b].empty();
+    if (c->series_ready) {
+        std::vector<float> ser((size_t)nb * kSeriesStride, 0.f);
+        for (int b = 0; b < nb; ++b) {
+            float* row = ser.data() + (size_t)b * kSeriesStride;
+            const int32_t nt = (int32_t)c->ser_a[b].size();
+            const int32_t n4 = (nt + 3) / 4 * 4;
+            row[0] = (float)(0.5 * c->ser_beta[b] * c->r_max[b] / (double)(n - 1));
+            std::memcpy(&row[1], &n4, sizeof(n4));
+            for (int32_t m = 0; m < nt; ++m) row[4 + m] = (float)c->ser_a[b][m];
+        }
+        FFTT_HIP(c, c->d_series.alloc(ser.size() * sizeof(float)));
+        FFTT_HIP(c, hipMemcpy(c->d_series.p, ser.data(), ser.size() * sizeof(float),
+                              hipMemcpyHostToDevice));
+    }
     c->tab_dirty = false;
     return FFTT_OK;
 }
@@ -294,6 +318,12 @@ int staged_table(const fftt_ctx* c, fftt_precision prec) {
     return c->staged_pair_table ? STAB_PAIR32 : STAB_NODE32;
 }
 
+// Evaluation of the detour function by the J / J^T kernels: the staged
+// table, or for FP32 with FFTT_TUNE_KERNEL_EVAL the sine series.
+int op_table(const fftt_ctx* c, fftt_precision prec) {
+    return (prec == FFTT_FP32 && c->eval_series) ? STAB_SERIES : staged_table(c, prec);
+}
+
 // Transducers per staged block for an FP32 / BF16-table apply: the
 // smallest power of two covering all transducers, halved until the tables
 // plus one float2 per (transducer, lane) of the block fit in LDS; 0 when
@@ -301,7 +331,7 @@ int staged_table(const fftt_ctx* c, fftt_precision prec) {
 // per-wavefront kernels run then).
 int staged_q(fftt_ctx* c, fftt_precision prec) {
     if (!c->staged || prec == FFTT_FP64) return 0;
-    const int fmt = staged_table(c, prec);
+    const int fmt = op_table(c, prec);
     int q = 16;
     while (q < c->n_tx) q *= 2;
     while (q >= 16 && ((c->staged_block_max && q > c->staged_block_max) ||
@@ -324,6 +354,7 @@ const void* staged_table_ptr(const fftt_ctx* c, int fmt) {
     switch (fmt) {
         case STAB_NODE32: return c->d_tab32n.p;
         case STAB_PAIR32: return c->d_tab32.p;
+        case STAB_SERIES: return c->d_series.p;
         default: return c->d_tabbf.p;
     }
 }
@@ -378,15 +409,20 @@ fftt_status apply_J_one(fftt_ctx* c, fftt_precision prec, const void* x, void* y
     a.unroll = c->unroll_j;
     a.split = c->split_j;
     a.x = x;
+    if (op_table(c, prec) == STAB_SERIES && !c->series_ready)
+        FFTT_FAIL(c, FFTT_E_STATE, "series evaluation: a band has no sine series");
     hipEvent_t stop;
     FFTT_HIP(c, prof_begin(c, 0, &stop));
     if (const int q = staged_q(c, prec)) {
         a.stage_q = q;
         a.unroll = c->unroll_js;
-        const int fmt = staged_table(c, prec);
+        const int fmt = op_table(c, prec);
         a.tab = staged_table_ptr(c, fmt);
         FFTT_HIP(c, launch_apply_staged(c->stream, fmt, false, a));
     } else {
+        if (op_table(c, prec) == STAB_SERIES)
+            FFTT_FAIL(c, FFTT_E_UNSUPPORTED,
+                      "series evaluation needs the staged kernels (FFTT_TUNE_STAGED, LDS)");
         FFTT_HIP(c, launch_apply(c->stream, prec, false, a));
     }
     FFTT_HIP(c, prof_end(c, stop));
@@ -410,6 +446,8 @@ fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* 
     a.tab = fp64 ? c->d_tab64.p : (prec == FFTT_FP32 ? c->d_tab32.p : c->d_tabbf.p);
     a.w = c->d_w.p;
     a.out = x;
+    if (op_table(c, prec) == STAB_SERIES && !c->series_ready)
+        FFTT_FAIL(c, FFTT_E_STATE, "series evaluation: a band has no sine series");
     FFTT_HIP(c, launch_weights(c->stream, fp64, y, c->d_kptr.as<int32_t>(),
                                c->d_kidx.as<int32_t>(), c->d_C.as<double>(), c->Mk, c->M, c->nb,
                                c->d_w.p));
@@ -419,10 +457,13 @@ fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* 
     if (const int q = staged_q(c, prec)) {
         a.stage_q = q;
         a.unroll = c->unroll_jts;
-        const int fmt = staged_table(c, prec);
+        const int fmt = op_table(c, prec);
         a.tab = staged_table_ptr(c, fmt);
         FFTT_HIP(c, launch_apply_staged(c->stream, fmt, true, a));
     } else {
+        if (op_table(c, prec) == STAB_SERIES)
+            FFTT_FAIL(c, FFTT_E_UNSUPPORTED,
+                      "series evaluation needs the staged kernels (FFTT_TUNE_STAGED, LDS)");
         FFTT_HIP(c, launch_apply(c->stream, prec, true, a));
     }
     FFTT_HIP(c, prof_end(c, stop));
@@ -642,7 +683,10 @@ fftt_status fftt_set_kernel_table(fftt_ctx* c, int32_t band, const double* h, in
         c->h.resize(c->nb);
         c->r_max.resize(c->nb, 0.0);
         c->band_set.resize(c->nb, false);
+        c->ser_a.resize(c->nb);
+        c->ser_beta.resize(c->nb, 0.0);
     }
+    if (c->r_max[band] != r_max) c->ser_a[band].clear();   // a series belongs to its r_max
     c->ntab = (int)n;
     c->h[band].assign(h, h + n);
     c->r_max[band] = r_max;
@@ -657,6 +701,32 @@ fftt_status fftt_build_table_from_pulse(double c0, const double* f, int64_t nt, 
                                         double* r_max_out) {
     std::string err;
     const int rc = build_table_from_pulse(c0, f, nt, dt, n, r_max, h_out, r_max_out, &err);
+    return rc == 0 ? FFTT_OK : FFTT_E_INVALID;
+}
+
+fftt_status fftt_set_kernel_series(fftt_ctx* c, int32_t band, const double* a, int32_t n_terms,
+                                   double beta, double r_max) {
+    if (!c) return FFTT_E_INVALID;
+    if (band < 0 || band >= c->nb || !c->band_set[band])
+        FFTT_BAD(c, "set_kernel_series: the band's table must be set first");
+    if (r_max != c->r_max[band]) FFTT_BAD(c, "set_kernel_series: r_max differs from the table's");
+    if (!a || n_terms < 1 || n_terms > kSeriesMax) FFTT_BAD(c, "set_kernel_series: 1..64 terms");
+    if (!(beta > 0) || !std::isfinite(beta) || beta * r_max > M_PI * (1.0 + 1e-12))
+        FFTT_BAD(c, "set_kernel_series: need 0 < beta * r_max <= pi");
+    for (int32_t m = 0; m < n_terms; ++m)
+        if (!std::isfinite(a[m])) FFTT_BAD(c, "set_kernel_series: non-finite coefficient");
+    c->ser_a[band].assign(a, a + n_terms);
+    c->ser_beta[band] = beta;
+    c->tab_dirty = true;
+    return FFTT_OK;
+}
+
+fftt_status fftt_build_series_from_pulse(double c0, const double* f, int64_t nt, double dt,
+                                         double r_max, double tol, int32_t max_terms,
+                                         double* a_out, int32_t* n_terms_out, double* beta_out) {
+    std::string err;
+    const int rc = build_series_from_pulse(c0, f, nt, dt, r_max, tol, max_terms, a_out,
+                                           n_terms_out, beta_out, &err);
     return rc == 0 ? FFTT_OK : FFTT_E_INVALID;
 }
 
@@ -721,6 +791,7 @@ fftt_status fftt_get_tuning(fftt_ctx* c, int32_t key, int32_t* value) {
         case FFTT_TUNE_STAGED_TABLE: *value = c->staged_pair_table; return FFTT_OK;
         case FFTT_TUNE_RECIPROCITY: *value = c->reciprocity; return FFTT_OK;
         case FFTT_TUNE_STAGED_BLOCK: *value = c->staged_block_max; return FFTT_OK;
+        case FFTT_TUNE_KERNEL_EVAL: *value = c->eval_series; return FFTT_OK;
     }
     FFTT_BAD(c, "unknown tuning key");
 }
@@ -785,9 +856,10 @@ fftt_status fftt_autotune(fftt_ctx* c, fftt_precision prec, double max_seconds) 
     best.ujt = c->staged ? c->unroll_jts : c->unroll_jt;
     double best_j = 1e30, best_jt = 1e30;
     const int wpbs[] = {16, 8, 4};
-    const int tables = fp64 || prec == FFTT_FP32_BF16TABLE ? 1 : 2;
+    const bool series = op_table(c, prec) == STAB_SERIES;   // needs the staged kernels
+    const int tables = fp64 || series || prec == FFTT_FP32_BF16TABLE ? 1 : 2;
     for (int staged = 1; staged >= 0 && st == FFTT_OK; --staged) {
-        if (fp64 && staged) continue;
+        if ((fp64 && staged) || (series && !staged)) continue;
         for (int wpb : wpbs) {
             for (int table = 0; table < (staged ? tables : 1); ++table) {
                 c->waves_per_block = wpb;
@@ -883,6 +955,10 @@ fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
         case FFTT_TUNE_STAGED_TABLE:
             if (value != 0 && value != 1) FFTT_BAD(c, "staged table must be 0 or 1");
             c->staged_pair_table = value;
+            return FFTT_OK;
+        case FFTT_TUNE_KERNEL_EVAL:
+            if (value != 0 && value != 1) FFTT_BAD(c, "kernel evaluation must be 0 or 1");
+            c->eval_series = value;
             return FFTT_OK;
         case FFTT_TUNE_SPLIT_JT:
         case FFTT_TUNE_SPLIT_J:

@@ -17,6 +17,11 @@ constexpr int kMaxBands = 4;
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxTable = 16384;
 constexpr int kEntryPad = 4;      // zeroed entries after the last (look-ahead reads)
+// Sine series of the detour function (at most kSeriesMax terms per band);
+// device layout per band: [theta/2 per unit of the table coordinate,
+// term count (int bits, a multiple of 4), 0, 0, a_1 .. a_n, zero padding].
+constexpr int kSeriesMax = 64;
+constexpr int kSeriesStride = 4 + kSeriesMax;
 
 // Geometry of one transducer seen from one tile centre c (all exact in FP64
 // except the two FP32 roundings, which the kernels compensate):
@@ -125,6 +130,7 @@ enum StagedTable {
     STAB_NODE32 = 0,  // FP32 nodes h_k (4 bytes per node), cutoff by a select
     STAB_PAIR32 = 1,  // FP32 (h_k, h_{k+1} - h_k) (8 bytes per node), cutoff by the clamp
     STAB_BF16 = 2,    // packed BF16 (h_k, slope) (4 bytes per node)
+    STAB_SERIES = 3,  // no table: the band's sine series (scalar loads, no LDS)
 };
 hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a);
 // LDS of a staged launch: tables plus q staged transducers (q * 512 bytes).
@@ -160,6 +166,9 @@ hipError_t solver_unit(hipStream_t s, bool fp64, void* x, int64_t n, int64_t v);
 // ---- host table builder (table.cpp) ----
 int build_table_from_pulse(double c0, const double* f, int64_t nt, double dt, int64_t n,
                            double r_max, double* h_out, double* r_max_out, std::string* err);
+int build_series_from_pulse(double c0, const double* f, int64_t nt, double dt, double r_max,
+                            double tol, int32_t max_terms, double* a_out, int32_t* n_out,
+                            double* beta_out, std::string* err);
 
 }  // namespace fftt
 
@@ -200,6 +209,12 @@ struct fftt_ctx {
     std::vector<bool> band_set;
     bool tab_dirty = true;
     fftt::DevBuf d_tab32, d_tab64, d_tabbf, d_tab32n;
+    // optional sine series per band (same r_max as the band's table)
+    std::vector<std::vector<double>> ser_a;
+    std::vector<double> ser_beta;
+    bool series_ready = false;           // every band has one (uploaded)
+    int eval_series = 0;                 // FP32 operators evaluate the series
+    fftt::DevBuf d_series;
 
     // culling lists
     bool lists_ok = false;

@@ -490,6 +490,106 @@ __device__ __forceinline__ float lookup_x(const float* tab, float x, float nm1) 
     return x < nm1 ? v : 0.0f;
 }
 
+// Sine series instead of a table (the paper's own stored form of eq.
+// Kernel_freq, Sec. II-C):  h = sum_{m=1}^{n} a_m sin(m theta), theta = beta R,
+// h = 0 for R >= r_max.  Per band, kSeriesStride floats in global memory:
+// [theta/2 per unit of the table coordinate, n (int bits, a multiple of 4),
+// 0, 0, a_1 .. a_n].  They are read through the constant address space, so
+// the wave-uniform coefficients arrive by scalar loads as SGPR operands.
+// Clenshaw's recurrence in Reinsch's form: with
+// lam = 2 cos(theta) - 2 = -4 sin^2(theta/2),
+//   d_m = a_m + lam b_{m+1} + d_{m+1},  b_m = d_m + b_{m+1},  h = b_1 sin(theta),
+// which, unlike the three-term form b_m = a_m + 2 cos(theta) b_{m+1} - b_{m+2},
+// does not amplify rounding as theta -> 0 (3 VALU per term).  sin and cos of
+// theta/2 <= pi/2 come from their Taylor polynomials to degree 13 / 14
+// (truncation < 1e-9).
+struct SinCoef {
+    float v;
+};
+
+template <class TabT>
+constexpr bool table_in_lds() { return true; }
+template <>
+constexpr bool table_in_lds<SinCoef>() { return false; }
+
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+using ConstF = const __attribute__((address_space(4))) float;
+using ConstF4 = const __attribute__((address_space(4))) f32x4v;
+
+// Half-angle sine and cosine for 0 <= t <= pi/2 (Taylor polynomials).
+__device__ __forceinline__ void half_angle(float t, float& sh, float& ch) {
+    // 1/k! for the Taylor polynomials
+    constexpr float f3 = 1.0 / 6, f5 = 1.0 / 120, f7 = 1.0 / 5040, f9 = 1.0 / 362880,
+                    f11 = 1.0 / 39916800, f13 = 1.0 / 6227020800.0;
+    constexpr float f2 = 1.0 / 2, f4 = 1.0 / 24, f6 = 1.0 / 720, f8 = 1.0 / 40320,
+                    f10 = 1.0 / 3628800, f12 = 1.0 / 479001600, f14 = 1.0 / 87178291200.0;
+    const float u = t * t;
+    float sp = fmaf(u, -f13, f11);
+    sp = fmaf(u, sp, -f9);
+    sp = fmaf(u, sp, f7);
+    sp = fmaf(u, sp, -f5);
+    sp = fmaf(u, sp, f3);
+    sp = fmaf(u, -sp, 1.0f);
+    float cp = fmaf(u, f14, -f12);
+    cp = fmaf(u, cp, f10);
+    cp = fmaf(u, cp, -f8);
+    cp = fmaf(u, cp, f6);
+    cp = fmaf(u, cp, -f4);
+    cp = fmaf(u, cp, f2);
+    ch = fmaf(u, -cp, 1.0f);
+    sh = t * sp;
+}
+
+// U lookups at once (table coordinates x[u], unclamped).  For the tables
+// these are independent interpolations; the series evaluates the U
+// recurrences together, so every scalar load of four coefficients serves
+// all of them.
+template <int U, class TabT>
+__device__ __forceinline__ void lookup_n(const TabT* tab, const float (&x)[U], float nm1,
+                                         float (&h)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) h[u] = lookup_x(tab, table_x(x[u], nm1), nm1);
+}
+
+template <int U>
+__device__ __forceinline__ void lookup_n(const SinCoef* tab, const float (&x)[U], float nm1,
+                                         float (&h)[U]) {
+    ConstF* c = (ConstF*)tab;
+    float xc[U], lam[U], sn[U], b[U], d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        xc[u] = table_x(x[u], nm1);
+        float sh, ch;
+        half_angle(c[0] * xc[u], sh, ch);  // theta / 2
+        lam[u] = -4.0f * sh * sh;
+        sn[u] = 2.0f * sh * ch;            // sin(theta)
+        b[u] = d[u] = 0.0f;
+    }
+    const int n = __float_as_int(c[1]);
+    for (int k = n; k > 0; k -= 4) {
+        const f32x4v a = *(ConstF4*)(c + k);   // a_{k-3} .. a_k
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            d[u] = fmaf(lam[u], b[u], a.w + d[u]);
+            b[u] += d[u];
+            d[u] = fmaf(lam[u], b[u], a.z + d[u]);
+            b[u] += d[u];
+            d[u] = fmaf(lam[u], b[u], a.y + d[u]);
+            b[u] += d[u];
+            d[u] = fmaf(lam[u], b[u], a.x + d[u]);
+            b[u] += d[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) h[u] = xc[u] < nm1 ? b[u] * sn[u] : 0.0f;
+}
+
+// Band b's table (or series) within a staged kernel's table pointer.
+template <class TabT>
+__device__ __forceinline__ const TabT* band_tab(const TabT* st, int b, int ntab) {
+    return st + (size_t)b * (table_in_lds<TabT>() ? ntab : kSeriesStride);
+}
+
 template <class TabT>
 __device__ __forceinline__ float lookup(const TabT* tab, float R, float inv_dr, float nm1) {
     return lookup_x(tab, table_x(R * inv_dr, nm1), nm1);
@@ -520,11 +620,18 @@ __device__ __forceinline__ LaneVox lane_vox(const ApplyArgs& A, int64_t a, int l
     return L;
 }
 
+// LDS bytes in front of a staged kernel's other LDS data.
+template <class TabT>
+__device__ __forceinline__ size_t lds_table_bytes(const ApplyArgs& A, int nb) {
+    return table_in_lds<TabT>() ? (((size_t)nb * A.ntab * sizeof(TabT) + 15) & ~(size_t)15) : 0;
+}
+
 template <class TabT>
 __device__ __forceinline__ const TabT* stage_table(const ApplyArgs& A, int nb) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    TabT* st = reinterpret_cast<TabT*>(smem);
     const TabT* gt = static_cast<const TabT*>(A.tab);
+    if constexpr (!table_in_lds<TabT>()) return gt;
+    TabT* st = reinterpret_cast<TabT*>(smem);
     const int n = nb * A.ntab;
     for (int i = threadIdx.x; i < n; i += blockDim.x) st[i] = gt[i];
     __syncthreads();
@@ -578,7 +685,7 @@ __device__ __forceinline__ void store_voxel(const ApplyArgs& A, const LaneVox& V
 template <class TabT>
 __device__ __forceinline__ unsigned char* lds_after(const ApplyArgs& A, int nb) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    return smem + (((size_t)nb * A.ntab * sizeof(TabT) + 15) & ~(size_t)15);
+    return smem + lds_table_bytes<TabT>(A, nb);
 }
 
 // Wave-uniform tile index of this wavefront (blocks hold blockDim.x/64 tiles).
@@ -875,7 +982,7 @@ hipError_t launch_apply(hipStream_t s, fftt_precision prec, bool transpose, cons
 template <class TabT>
 __device__ __forceinline__ float2* staged_tx(const ApplyArgs& A, int nb) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    return reinterpret_cast<float2*>(smem + (((size_t)nb * A.ntab * sizeof(TabT) + 15) & ~(size_t)15));
+    return reinterpret_cast<float2*>(smem + lds_table_bytes<TabT>(A, nb));
 }
 
 // Stages transducers q0 .. q0 + n - 1 into sx[q - q0][lane].
@@ -1073,17 +1180,21 @@ __device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, c
     }
     with_sources<U, false>(E, sx, lane, prev, cd, cg, 1.0f,
                            [&](const float (&sd)[U], const float (&sg)[U]) {
+        float x0[U], hw[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            // R / dR_0 = (delta_s + delta_r) / dR_0 + R0 / dR_0
-            const float x0 = fmaf(E.R0[u], A.inv_dr[0], sd[u] + rd[u]);
-            float hw = lookup_x(st, table_x(x0, nm1), nm1) * W.w[u][0];
+        for (int u = 0; u < U; ++u)   // R / dR_0 = (delta_s + delta_r) / dR_0 + R0 / dR_0
+            x0[u] = fmaf(E.R0[u], A.inv_dr[0], sd[u] + rd[u]);
 #pragma unroll
-            for (int b = 1; b < NB; ++b)
-                hw = fmaf(lookup_x(st + b * A.ntab, table_x(x0 * A.xr[b], nm1), nm1), W.w[u][b],
-                          hw);
-            acc = fmaf(hw, sg[u] * rg[u], acc);
+        for (int b = 0; b < NB; ++b) {
+            float xb[U], h[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xb[u] = b == 0 ? x0[u] : x0[u] * A.xr[b];
+            lookup_n<U>(band_tab(st, b, A.ntab), xb, nm1, h);
+#pragma unroll
+            for (int u = 0; u < U; ++u) hw[u] = b == 0 ? h[u] * W.w[u][0] : fmaf(h[u], W.w[u][b], hw[u]);
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = fmaf(hw[u], sg[u] * rg[u], acc);
     });
 }
 
@@ -1151,12 +1262,12 @@ __device__ __forceinline__ void j32s_body(const ApplyArgs& A, const TabT* st, co
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            float v[U];
+            float xb[U], v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const float xb = b == 0 ? x0[u] : x0[u] * A.xr[b];
-                v[u] = lookup_x(st + b * A.ntab, table_x(xb, nm1), nm1) * t[u];
-            }
+            for (int u = 0; u < U; ++u) xb[u] = b == 0 ? x0[u] : x0[u] * A.xr[b];
+            lookup_n<U>(band_tab(st, b, A.ntab), xb, nm1, v);
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] *= t[u];
             const float sum = multi_sum<U>(v, lane);
             if (lane < U) part[b * A.nnz + e + lane] = sum;
         }
@@ -1209,7 +1320,7 @@ static hipError_t launch_staged(K kern, hipStream_t s, const ApplyArgs& a, size_
 }
 
 static size_t staged_entry_bytes(int tabfmt) {
-    return tabfmt == STAB_PAIR32 ? sizeof(float2) : sizeof(float);
+    return tabfmt == STAB_PAIR32 ? sizeof(float2) : tabfmt == STAB_SERIES ? 0 : sizeof(float);
 }
 
 size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t q, int wpb) {
@@ -1220,7 +1331,7 @@ size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t q, int wpb) {
 
 template <class TabT, int NB, int U>
 static hipError_t launch_staged_t(hipStream_t s, bool transpose, const ApplyArgs& a) {
-    const size_t bytes = (size_t)NB * a.ntab * sizeof(TabT);
+    const size_t bytes = table_in_lds<TabT>() ? (size_t)NB * a.ntab * sizeof(TabT) : 0;
     return transpose ? launch_staged(k_jt32s<NB, TabT, U>, s, a, bytes)
                      : launch_staged(k_j32s<NB, TabT, U>, s, a, bytes);
 }
@@ -1232,6 +1343,8 @@ static hipError_t launch_staged_nbu(hipStream_t s, int tabfmt, bool transpose,
         case STAB_NODE32: return launch_staged_t<float, NB, U>(s, transpose, a);
         case STAB_PAIR32: return launch_staged_t<float2, NB, U>(s, transpose, a);
         case STAB_BF16: return launch_staged_t<uint32_t, NB, U>(s, transpose, a);
+        // the series' own loop is long: at most four entries per step (no spills)
+        case STAB_SERIES: return launch_staged_t<SinCoef, NB, (U > 4 ? 4 : U)>(s, transpose, a);
     }
     return hipErrorInvalidValue;
 }

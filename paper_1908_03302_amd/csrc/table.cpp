@@ -112,4 +112,64 @@ int build_table_from_pulse(double c0, const double* f, int64_t nt, double dt, in
     return 0;
 }
 
+// Sine series of the same function (the paper's stored representation of
+// eq. Kernel_freq, Sec. II-C): the two frequency integrals as trapezoid sums
+// over uniform nodes w_m = m dw, m = 1..n (the node w = 0 contributes
+// nothing), so h(R) = sum_m a_m sin(m beta R) with beta = dw / c0 and
+// a_m = w_m^3 S(w_m) / sum_k w_k^2 S(w_k).  Both integrands are even in w,
+// so the sums converge spectrally once their top node is past the band and
+// the spacing is fine enough: the sum is periodic in R with period
+// 2 pi c0 / dw, chosen as 2.5 r_max, which keeps the first alias of h at
+// R >= 1.5 r_max, where h is negligible.  The band ends at the last
+// frequency where w^3 S exceeds tol times its maximum.
+int build_series_from_pulse(double c0, const double* f, int64_t nt, double dt, double r_max,
+                            double tol, int32_t max_terms, double* a_out, int32_t* n_out,
+                            double* beta_out, std::string* err) {
+    if (!(c0 > 0) || !std::isfinite(c0) || nt < 2 || !(dt > 0) || !std::isfinite(dt) ||
+        !(r_max > 0) || !std::isfinite(r_max) || !(tol > 0 && tol < 1) || max_terms < 1 || !f ||
+        !a_out || !n_out || !beta_out) {
+        *err = "build_series_from_pulse: bad argument";
+        return -1;
+    }
+    for (int64_t k = 0; k < nt; ++k)
+        if (!std::isfinite(f[k])) {
+            *err = "build_series_from_pulse: non-finite pulse sample";
+            return -1;
+        }
+    const int scan = 8192;
+    const double w_nyq = M_PI / dt;
+    std::vector<double> g(scan + 1);
+    double gmax = 0.0;
+    for (int i = 0; i <= scan; ++i) {
+        const double w = w_nyq * i / scan;
+        g[i] = w * w * w * energy_spectrum(f, nt, dt, w);
+        gmax = std::fmax(gmax, g[i]);
+    }
+    if (!(gmax > 0)) {
+        *err = "build_series_from_pulse: pulse has no energy";
+        return -1;
+    }
+    int last = 0;
+    for (int i = 0; i <= scan; ++i)
+        if (g[i] > tol * gmax) last = i;
+    const double w_top = w_nyq * std::fmin(1.0, (double)(last + 1) / scan);
+    const double dw = 2.0 * M_PI * c0 / (2.5 * r_max);
+    const int64_t n = (int64_t)std::ceil(w_top / dw);
+    if (n > max_terms) {
+        *err = "build_series_from_pulse: the band needs " + std::to_string(n) + " terms";
+        return -1;
+    }
+    double den = 0.0;
+    for (int64_t m = 1; m <= n; ++m) {
+        const double w = dw * (double)m;
+        const double S = energy_spectrum(f, nt, dt, w);
+        a_out[m - 1] = w * w * w * S;
+        den += w * w * S;
+    }
+    for (int64_t m = 0; m < n; ++m) a_out[m] /= den;
+    *n_out = (int32_t)n;
+    *beta_out = dw / c0;
+    return 0;
+}
+
 }  // namespace fftt

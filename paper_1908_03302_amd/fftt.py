@@ -24,12 +24,13 @@ EXPORTS = ["fftt_create", "fftt_destroy", "fftt_last_error", "fftt_set_stream",
            "fftt_set_geometry", "fftt_set_kernel_table", "fftt_build_table_from_pulse",
            "fftt_prepare", "fftt_work_count", "fftt_apply_J", "fftt_apply_JT", "fftt_solve",
            "fftt_psf", "fftt_profile", "fftt_kernel_time", "fftt_set_tuning", "fftt_get_tuning",
-           "fftt_autotune"]
+           "fftt_autotune", "fftt_set_kernel_series", "fftt_build_series_from_pulse"]
 TUNE_WAVES_PER_BLOCK, TUNE_UNROLL_JT, TUNE_UNROLL_J, TUNE_SPLIT_JT, TUNE_SPLIT_J = 0, 1, 2, 3, 4
 TUNE_STAGED, TUNE_UNROLL_JT_STAGED, TUNE_UNROLL_J_STAGED = 5, 6, 7
 TUNE_STAGED_TABLE = 8
 TUNE_RECIPROCITY = 9
 TUNE_STAGED_BLOCK = 10
+TUNE_KERNEL_EVAL = 11
 
 
 class SolveOpts(C.Structure):
@@ -74,6 +75,10 @@ def load():
     L.fftt_set_kernel_table.argtypes = [vp, C.c_int32, dp, i64, C.c_double]
     L.fftt_build_table_from_pulse.argtypes = [C.c_double, dp, i64, C.c_double, i64, C.c_double,
                                               dp, dp]
+    L.fftt_set_kernel_series.argtypes = [vp, C.c_int32, dp, C.c_int32, C.c_double, C.c_double]
+    L.fftt_build_series_from_pulse.argtypes = [C.c_double, dp, i64, C.c_double, C.c_double,
+                                               C.c_double, C.c_int32, dp, C.POINTER(C.c_int32),
+                                               dp]
     L.fftt_prepare.argtypes = [vp]
     L.fftt_work_count.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                   C.POINTER(C.c_int64)]
@@ -109,6 +114,21 @@ def build_table_from_pulse(c0, f, dt, n, r_max=0.0):
     if st != FFTT_OK:
         raise FFTTError(st, "fftt_build_table_from_pulse failed")
     return h, rm.value
+
+
+def build_series_from_pulse(c0, f, dt, r_max, tol=1e-8, max_terms=64):
+    """Sine-series coefficients a_1..a_n and beta of h(R) = sum a_m sin(m beta R)."""
+    L = load()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    a = np.empty(int(max_terms))
+    n = C.c_int32(0)
+    beta = C.c_double(0.0)
+    st = L.fftt_build_series_from_pulse(float(c0), _dp(f), f.size, float(dt), float(r_max),
+                                        float(tol), int(max_terms), _dp(a), C.byref(n),
+                                        C.byref(beta))
+    if st != FFTT_OK:
+        raise FFTTError(st, "fftt_build_series_from_pulse failed")
+    return a[:n.value].copy(), beta.value
 
 
 def _dtype_for(prec):
@@ -175,6 +195,11 @@ class Context:
                                                  float(r_max)), "set_kernel_table")
         self.n_bands = max(self.n_bands, int(band) + 1)
 
+    def set_kernel_series(self, band, a, beta, r_max):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        self._check(self.L.fftt_set_kernel_series(self.h, int(band), _dp(a), a.size, float(beta),
+                                                  float(r_max)), "set_kernel_series")
+
     def prepare(self):
         self._bind_stream()
         self._check(self.L.fftt_prepare(self.h), "prepare")
@@ -189,7 +214,7 @@ class Context:
 
     def set_tuning(self, waves_per_block=None, unroll_jt=None, unroll_j=None, split_jt=None,
                    split_j=None, staged=None, unroll_jt_staged=None, unroll_j_staged=None,
-                   staged_table=None, reciprocity=None, staged_block=None):
+                   staged_table=None, reciprocity=None, staged_block=None, kernel_eval=None):
         for key, v in ((TUNE_WAVES_PER_BLOCK, waves_per_block), (TUNE_UNROLL_JT, unroll_jt),
                        (TUNE_UNROLL_J, unroll_j), (TUNE_SPLIT_JT, split_jt),
                        (TUNE_SPLIT_J, split_j), (TUNE_STAGED, staged),
@@ -197,7 +222,7 @@ class Context:
                        (TUNE_UNROLL_J_STAGED, unroll_j_staged),
                        (TUNE_STAGED_TABLE, staged_table),
                        (TUNE_RECIPROCITY, reciprocity),
-                       (TUNE_STAGED_BLOCK, staged_block)):
+                       (TUNE_STAGED_BLOCK, staged_block), (TUNE_KERNEL_EVAL, kernel_eval)):
             if v is not None:
                 self._check(self.L.fftt_set_tuning(self.h, key, int(v)), "set_tuning")
 
@@ -205,7 +230,8 @@ class Context:
                    "unroll_j": TUNE_UNROLL_J, "split_jt": TUNE_SPLIT_JT, "split_j": TUNE_SPLIT_J,
                    "staged": TUNE_STAGED, "unroll_jt_staged": TUNE_UNROLL_JT_STAGED,
                    "unroll_j_staged": TUNE_UNROLL_J_STAGED, "staged_table": TUNE_STAGED_TABLE,
-                   "reciprocity": TUNE_RECIPROCITY, "staged_block": TUNE_STAGED_BLOCK}
+                   "reciprocity": TUNE_RECIPROCITY, "staged_block": TUNE_STAGED_BLOCK,
+                   "kernel_eval": TUNE_KERNEL_EVAL}
 
     def get_tuning(self):
         """All tuning keys and their current values."""
@@ -289,13 +315,17 @@ class Context:
         return out
 
 
-def context_for_workload(w, device=0, n_table=None):
+def context_for_workload(w, device=0, n_table=None, series=False):
     """Context with the workload's geometry and one table per band built by
-    the library's own table builder."""
+    the library's own table builder (and with series=True also each band's
+    sine series from the library's series builder)."""
     ctx = Context(device)
     ctx.set_geometry(w.c0, w.tx, w.pairs, w.grid.origin, w.grid.spacing, w.grid.dims, w.mask)
     n = n_table or w.n_table
     for b, (p, r) in enumerate(zip(w.pulses, w.r_max)):
         h, rm = build_table_from_pulse(w.c0, p.samples, p.dt, n, r)
         ctx.set_kernel_table(b, h, rm)
+        if series:
+            a, beta = build_series_from_pulse(w.c0, p.samples, p.dt, rm)
+            ctx.set_kernel_series(b, a, beta, rm)
     return ctx

@@ -58,3 +58,33 @@ def test_table_builder_rejects_bad_input():
         fftt.build_table_from_pulse(-1.0, np.ones(100), 1e-8, 512, 0.0)
     with pytest.raises(fftt.FFTTError):
         fftt.build_table_from_pulse(1500.0, np.ones(100), 1e-8, 1, 0.0)
+
+
+@pytest.mark.parametrize("fc,bw,r_max", [(0.5e6, 0.5, I.R_MAX_HALF_MHZ_BW50),
+                                         (0.5e6, 1.0, I.R_MAX[0.5e6]),
+                                         (1e6, 1.0, I.R_MAX[1e6]), (2e6, 1.0, I.R_MAX[2e6])])
+def test_series_builder_matches_oracle(fc, bw, r_max):
+    """The library's sine series (few uniform nodes) reproduces the oracle's
+    quadrature of eq. Kernel_freq on [0, r_max] to 1e-8 of max|h|; its
+    argument spacing keeps beta r_max = 0.8 pi (period 2.5 r_max)."""
+    p = I.sampled_pulse(fc, bw)
+    a, beta = fftt.build_series_from_pulse(1500.0, p.samples, p.dt, r_max)
+    assert 8 <= a.size <= 40
+    assert abs(beta * r_max - 0.8 * np.pi) < 1e-12
+    qa, qb = oracle.quad_coeffs(p.samples, p.dt, 1500.0, r_max=r_max)
+    R = np.linspace(0.0, r_max, 20001)
+    ho = oracle.h_eval(qa, qb, R)
+    hs = np.sin(np.outer(R, beta * np.arange(1, a.size + 1))) @ a
+    assert np.abs(hs - ho).max() <= 1e-8 * np.abs(ho).max()
+
+
+def test_series_builder_rejects_bad_input():
+    p = I.sampled_pulse(1e6, 1.0)
+    with pytest.raises(fftt.FFTTError):   # needs ~24 terms
+        fftt.build_series_from_pulse(1500.0, p.samples, p.dt, I.R_MAX[1e6], max_terms=8)
+    with pytest.raises(fftt.FFTTError):
+        fftt.build_series_from_pulse(1500.0, p.samples, p.dt, 0.0)
+    with pytest.raises(fftt.FFTTError):
+        fftt.build_series_from_pulse(1500.0, np.zeros(100), 1e-8, 1e-3)
+    with pytest.raises(fftt.FFTTError):
+        fftt.build_series_from_pulse(1500.0, p.samples, p.dt, I.R_MAX[1e6], tol=0.0)
