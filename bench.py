@@ -250,6 +250,7 @@ def main():
         del cs
     if not args.no_psf:
         out["psf"] = psf_leg(ctx, w, fftt, torch, pv)
+    out["coverage"] = coverage_leg(ctx, w, torch)
     if not args.no_series:
         out["series"] = series_leg(ctx, w, fftt, torch, pv, avg_j, avg_jt)
     del dc, dT, dc2
@@ -293,6 +294,25 @@ def psf_leg(ctx, w, fftt, torch, pv, reps=3):
         log("bench: 512 PSFs %s: %.1f ms (kernels %.1f ms), %.1f TFLOP/s"
             % (name, wall, kms, tf))
     del out
+    return res
+
+
+def coverage_leg(ctx, w, torch, reps=5):
+    """Sensitivity coverage sum_i |J_ij| and diag(J^T J): one J^T-like pass each."""
+    out = torch.empty(w.n, dtype=torch.float32, device="cuda:0")
+    res = {}
+    for kind, name in ((0, "coverage_ms"), (1, "diag_JTJ_ms")):
+        ctx.coverage(kind, out=out)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.coverage(kind, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / reps
+    log("bench: coverage %.3f ms, diag(J^T J) %.3f ms" % (res["coverage_ms"], res["diag_JTJ_ms"]))
     return res
 
 
@@ -439,6 +459,13 @@ def cg_time_to_misfit(ctx, w, fftt, torch, iters, eager_too=False):
                     max_iter=4 * iters, target_misfit=target, graph=True)
     r32 = ctx.solve(d32, x32, method=0, prec=fftt.FP32, alpha=alpha, noise_sigma=sig,
                     max_iter=4 * iters, target_misfit=target, graph=True)
+    # Jacobi-preconditioned CG to the same misfit (the diagonal pass included)
+    xp64 = torch.zeros_like(x64)
+    xp32 = torch.zeros_like(x32)
+    p64 = ctx.solve(d64, xp64, method=0, prec=fftt.FP64, alpha=alpha, noise_sigma=sig,
+                    max_iter=4 * iters, target_misfit=target, graph=True, precond=True)
+    p32 = ctx.solve(d32, xp32, method=0, prec=fftt.FP32, alpha=alpha, noise_sigma=sig,
+                    max_iter=4 * iters, target_misfit=target, graph=True, precond=True)
     eager = {}
     if eager_too:
         xe = torch.zeros_like(x64)
@@ -456,13 +483,19 @@ def cg_time_to_misfit(ctx, w, fftt, torch, iters, eager_too=False):
            "target_misfit": target,
            "fp64": {"ms": r64["time_ms"], "iters": r64["iters"], "misfit": true_misfit(x64)},
            "mixed_fp32": {"ms": r32["time_ms"], "iters": r32["iters"], "misfit": true_misfit(x32)},
+           "fp64_jacobi": {"ms": p64["time_ms"], "iters": p64["iters"],
+                           "misfit": true_misfit(xp64)},
+           "mixed_fp32_jacobi": {"ms": p32["time_ms"], "iters": p32["iters"],
+                                 "misfit": true_misfit(xp32)},
            }
     out["speedup_mixed_vs_fp64"] = r64["time_ms"] / r32["time_ms"]
     out["timing"] = "wall time of the solve call, iterations replayed from a HIP graph, one " \
                     "misfit check per iteration on the host"
     out.update(eager)
-    log("bench: CG to misfit %.6g: FP64 %.1f ms (%d it), mixed %.1f ms (%d it)"
-        % (target, r64["time_ms"], r64["iters"], r32["time_ms"], r32["iters"]))
+    log("bench: CG to misfit %.6g: FP64 %.1f ms (%d it), mixed %.1f ms (%d it); Jacobi: "
+        "FP64 %.1f ms (%d it), mixed %.1f ms (%d it)"
+        % (target, r64["time_ms"], r64["iters"], r32["time_ms"], r32["iters"],
+           p64["time_ms"], p64["iters"], p32["time_ms"], p32["iters"]))
     return out
 
 

@@ -175,7 +175,12 @@ fftt_status fftt_apply_JT(fftt_ctx *ctx, fftt_precision prec, const void *dT,
  *   use_graph != 0: the second iteration is captured into a HIP graph on the
  *   context's stream and replayed for the remaining ones (one launch per
  *   iteration instead of ~20); results are identical to use_graph = 0.  The
- *   stream must not be used by other work during the solve. */
+ *   stream must not be used by other work during the solve.
+ *   precond = 1 (CGLS only): Jacobi-preconditioned CG on the same normal
+ *   equations, M = diag(J^T J) / sigma^2 + alpha I, the diagonal computed
+ *   once per solve by fftt_coverage (FP32, staged kernels; FFTT_E_UNSUPPORTED
+ *   where those do not apply).  The fixed point is unchanged; rel_tol still
+ *   measures |J^T (d - J x)/sigma^2 - alpha x| relative to its start. */
 typedef struct {
     int32_t method;
     int32_t prec;            /* fftt_precision */
@@ -186,6 +191,7 @@ typedef struct {
     double target_misfit;
     double rel_tol;
     int32_t use_graph;
+    int32_t precond;         /* 0 none, 1 Jacobi (method 0) */
 } fftt_solve_opts;
 
 typedef struct {
@@ -197,6 +203,16 @@ typedef struct {
 
 fftt_status fftt_solve(fftt_ctx *ctx, const fftt_solve_opts *opts,
                        const void *d_obs, void *x, fftt_solve_report *rep);
+
+/* Sensitivity coverage (Sec. IV: the absolute values of the operator
+ * summed over its rows) and the diagonal of the Gauss-Newton Hessian:
+ *   kind 0: out_j = sum_b sum_i |J^b_ij|;   kind 1: out_j = sum_b sum_i (J^b_ij)^2
+ * over every caller pair i (pairs sharing a row of J each count) and band b.
+ * One J^T-like pass in FP32 with the current kernel evaluation (table or
+ * series; prec FFTT_FP32 or FFTT_FP32_BF16TABLE selects the table), on the
+ * LDS-staged kernels (FFTT_E_UNSUPPORTED where they do not apply, and for
+ * FFTT_FP64).  out: device [N] FP32, inactive voxels 0.  Asynchronous. */
+fftt_status fftt_coverage(fftt_ctx *ctx, fftt_precision prec, int32_t kind, void *out);
 
 /* Hessian point-spread functions (eq. resolution_2):
  * out[k] = J^T J e_{voxels[k]} / sigma^2, e_i = 1 m/s at voxel i, summed

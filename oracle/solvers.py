@@ -47,6 +47,38 @@ def cgls(J, JT, d, sigma, alpha, n_iter, x0=None, tol=0.0):
     return x, hist
 
 
+def pcgls(J, JT, d, sigma, alpha, minv, n_iter, x0=None):
+    """Preconditioned conjugate gradients on the same damped normal
+    equations, preconditioner M^-1 = diag(minv): the textbook PCG recurrences
+    (residual s, preconditioned residual z = M^-1 s, gamma = s.z) with the
+    residual kept in data space as in cgls.  minv = 1 gives cgls.
+    Returns (x, history of |J x - d|^2/sigma^2)."""
+    b = np.asarray(d, dtype=np.float64) / sigma
+    minv = np.asarray(minv, dtype=np.float64)
+    x = np.zeros_like(JT(b)) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - J(x) / sigma
+    s = JT(r) / sigma - alpha * x
+    z = minv * s
+    p = z.copy()
+    gamma = float(s @ z)
+    hist = [float(r @ r)]
+    for _ in range(n_iter):
+        q = J(p) / sigma
+        delta = float(q @ q) + alpha * float(p @ p)
+        if delta == 0.0:
+            break
+        a = gamma / delta
+        x += a * p
+        r -= a * q
+        s = JT(r) / sigma - alpha * x
+        z = minv * s
+        gamma_new = float(s @ z)
+        hist.append(float(r @ r))
+        p = z + (gamma_new / gamma) * p
+        gamma = gamma_new
+    return x, hist
+
+
 def lsqr(J, JT, b, damp, n_iter, n_cols):
     """LSQR of Paige and Saunders (1982) for min |A x - b|^2 + damp^2 |x|^2,
     written from the published bidiagonalisation recurrences; x0 = 0."""

@@ -470,6 +470,35 @@ fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* 
     return FFTT_OK;
 }
 
+// out [N] FP32 = coverage (kind 0) or diag(J^T J) (kind 1); ensure_ready done.
+fftt_status coverage_one(fftt_ctx* c, fftt_precision prec, int32_t kind, float* out) {
+    const int q = staged_q(c, prec);
+    if (!q)
+        FFTT_FAIL(c, FFTT_E_UNSUPPORTED, "coverage needs the staged kernels (FFTT_TUNE_STAGED, LDS)");
+    const int fmt = op_table(c, prec);
+    if (fmt == STAB_SERIES && !c->series_ready)
+        FFTT_FAIL(c, FFTT_E_STATE, "series evaluation: a band has no sine series");
+    FFTT_HIP(c, c->d_w.alloc((size_t)c->nb * c->Mk * sizeof(double)));
+    ApplyArgs a = base_args(c);
+    a.stage_q = q;
+    a.tab = staged_table_ptr(c, fmt);
+    a.out = out;
+    // the largest weight (|C_p| m_p or C_p^2 m_p) is scaled into [1, 2) by a
+    // power of two, undone on the output (both exact)
+    double wmax = 0.0;
+    for (int64_t k = 0; k < c->Mk; ++k) {
+        const double m = (double)(c->kptr[k + 1] - c->kptr[k]);
+        wmax = std::max(wmax, kind == 0 ? std::fabs(c->C[k]) * m : c->C[k] * c->C[k] * m);
+    }
+    const int e = wmax > 0.0 ? std::ilogb(wmax) : 0;
+    FFTT_HIP(c, launch_fill(c->stream, false, out, c->N));
+    FFTT_HIP(c, launch_coverage(c->stream, fmt, kind + 1, a, c->d_C.as<double>(),
+                                c->d_kptr.as<int32_t>(), std::ldexp(1.0, -e),
+                                c->d_w.as<float>()));
+    FFTT_HIP(c, solver_lin2(c->stream, false, out, out, nullptr, c->N, std::ldexp(1.0, e), 0.0));
+    return FFTT_OK;
+}
+
 fftt_status ensure_ready(fftt_ctx* c) {
     if (!c->has_geom) {
         c->err = "geometry not set";
@@ -728,6 +757,19 @@ fftt_status fftt_build_series_from_pulse(double c0, const double* f, int64_t nt,
     const int rc = build_series_from_pulse(c0, f, nt, dt, r_max, tol, max_terms, a_out,
                                            n_terms_out, beta_out, &err);
     return rc == 0 ? FFTT_OK : FFTT_E_INVALID;
+}
+
+fftt_status fftt_coverage(fftt_ctx* c, fftt_precision prec, int32_t kind, void* out) {
+    if (!c) return FFTT_E_INVALID;
+    if (kind != 0 && kind != 1) FFTT_BAD(c, "coverage: kind must be 0 (sum |J|) or 1 (sum J^2)");
+    if (!out) FFTT_BAD(c, "coverage: null output");
+    if (prec != FFTT_FP32 && prec != FFTT_FP32_BF16TABLE) {
+        if (prec == FFTT_FP64) FFTT_FAIL(c, FFTT_E_UNSUPPORTED, "coverage is computed in FP32");
+        FFTT_BAD(c, "coverage: unknown precision");
+    }
+    fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    return coverage_one(c, prec, kind, static_cast<float*>(out));
 }
 
 fftt_status fftt_prepare(fftt_ctx* c) {
@@ -1031,6 +1073,8 @@ static fftt_status solve_impl(fftt_ctx* c, const fftt_solve_opts* o, const void*
     if (!(o->noise_sigma > 0) || !std::isfinite(o->noise_sigma)) FFTT_BAD(c, "solve: noise_sigma must be > 0");
     if (!(o->alpha >= 0) || !std::isfinite(o->alpha)) FFTT_BAD(c, "solve: alpha must be >= 0");
     if (o->max_iter < 0) FFTT_BAD(c, "solve: max_iter < 0");
+    if (o->precond != 0 && o->precond != 1) FFTT_BAD(c, "solve: precond must be 0 or 1");
+    if (o->precond && o->method != 0) FFTT_BAD(c, "solve: the Jacobi preconditioner is for CGLS");
     fftt_status st = ensure_ready(c);
     if (st != FFTT_OK) return st;
     const fftt_precision prec = (fftt_precision)o->prec;
@@ -1039,14 +1083,26 @@ static fftt_status solve_impl(fftt_ctx* c, const fftt_solve_opts* o, const void*
     const int64_t N = c->N, D = (int64_t)c->nb * c->M;
     const double isg = 1.0 / o->noise_sigma, alpha = o->alpha;
     hipStream_t s = c->stream;
-    // vectors: data-space r (or u), q; model-space sv, p (or v), w
-    FFTT_HIP(c, c->d_solve.alloc((size_t)(2 * D + 3 * N) * es));
+    // vectors: data-space r (or u), q; model-space sv, p (or v), w (or the
+    // preconditioned residual z), minv
+    FFTT_HIP(c, c->d_solve.alloc((size_t)(2 * D + 4 * N) * es));
     char* base = c->d_solve.as<char>();
     void* r = base;
     void* q = base + D * es;
     void* sv = base + 2 * D * es;
     void* p = base + (2 * D + N) * es;
     void* wv = base + (2 * D + 2 * N) * es;
+    void* minv = base + (2 * D + 3 * N) * es;
+    const bool pc = o->precond == 1;
+    if (pc) {
+        // Jacobi: M^-1 = 1 / (diag(J^T J) / sigma^2 + alpha), diagonal in FP32
+        FFTT_HIP(c, c->d_diag.alloc((size_t)N * sizeof(float)));
+        const fftt_precision dprec = prec == FFTT_FP32_BF16TABLE ? prec : FFTT_FP32;
+        st = coverage_one(c, dprec, 1, c->d_diag.as<float>());
+        if (st != FFTT_OK) return st;
+        FFTT_HIP(c, solver_jacobi(c->stream, fp64, minv, c->d_diag.as<float>(), N, isg * isg,
+                                  alpha));
+    }
     FFTT_HIP(c, c->d_scal.alloc((32 + 512) * sizeof(double)));
     double* sc = c->d_scal.as<double>();
     double* part = sc + 32;
@@ -1069,8 +1125,12 @@ static fftt_status solve_impl(fftt_ctx* c, const fftt_solve_opts* o, const void*
     int it = 0;
     double misfit = 0.0, relres = 0.0;
     if (o->method == 0) {
-        // CGLS on (J^T J / sigma^2 + alpha I) x = J^T d / sigma^2
-        enum { GAMMA = 0, DQ = 1, DP = 2, STEP = 3, BETA = 4, MIS = 5, G0 = 6, GNEW = 7 };
+        // CGLS on (J^T J / sigma^2 + alpha I) x = J^T d / sigma^2; with the
+        // Jacobi preconditioner the search directions follow z = M^-1 s and
+        // gamma = s.z (PCG in CGLS form); SS, SS0 = |s|^2 for rel_tol
+        enum { GAMMA = 0, DQ = 1, DP = 2, STEP = 3, BETA = 4, MIS = 5, G0 = 6, GNEW = 7,
+               SS = 21, SS0 = 22 };
+        void* zv = wv;
         if (o->use_x0) {
             SOLVE_OK(apply_J_one(c, prec, x, q));
             FFTT_HIP(c, solver_lin2(s, fp64, r, d_obs, q, D, isg, -isg));
@@ -1080,9 +1140,16 @@ static fftt_status solve_impl(fftt_ctx* c, const fftt_solve_opts* o, const void*
         }
         SOLVE_OK(apply_JT_one(c, prec, r, sv));
         FFTT_HIP(c, solver_axpby(s, fp64, sv, x, N, isg, -1, -alpha, -1, sc));
-        FFTT_HIP(c, solver_lin2(s, fp64, p, sv, nullptr, N, 1.0, 0.0));
-        FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, GAMMA, 1.0));
-        FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, G0, 1.0));
+        if (pc) {
+            FFTT_HIP(c, solver_mul(s, fp64, zv, minv, sv, N));
+            FFTT_HIP(c, solver_lin2(s, fp64, p, zv, nullptr, N, 1.0, 0.0));
+            FFTT_HIP(c, solver_dot(s, fp64, sv, zv, N, part, sc, GAMMA, 1.0));
+        } else {
+            FFTT_HIP(c, solver_lin2(s, fp64, p, sv, nullptr, N, 1.0, 0.0));
+            FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, GAMMA, 1.0));
+        }
+        FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, SS, 1.0));
+        FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, SS0, 1.0));
         FFTT_HIP(c, solver_dot(s, fp64, r, r, D, part, sc, MIS, 1.0));
         auto iteration = [&]() -> fftt_status {
             SOLVE_OK(apply_J_one(c, prec, p, q));
@@ -1093,26 +1160,34 @@ static fftt_status solve_impl(fftt_ctx* c, const fftt_solve_opts* o, const void*
             FFTT_HIP(c, solver_axpby(s, fp64, r, q, D, 1.0, -1, -isg, STEP, sc));
             SOLVE_OK(apply_JT_one(c, prec, r, sv));
             FFTT_HIP(c, solver_axpby(s, fp64, sv, x, N, isg, -1, -alpha, -1, sc));
-            FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, GNEW, 1.0));
+            if (pc) {
+                FFTT_HIP(c, solver_mul(s, fp64, zv, minv, sv, N));
+                FFTT_HIP(c, solver_dot(s, fp64, sv, zv, N, part, sc, GNEW, 1.0));
+                FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, SS, 1.0));
+            } else {
+                FFTT_HIP(c, solver_dot(s, fp64, sv, sv, N, part, sc, GNEW, 1.0));
+            }
             FFTT_HIP(c, solver_cgls_beta(s, sc));
-            FFTT_HIP(c, solver_axpby(s, fp64, p, sv, N, 1.0, BETA, 1.0, -1, sc));
+            FFTT_HIP(c, solver_axpby(s, fp64, p, pc ? zv : sv, N, 1.0, BETA, 1.0, -1, sc));
             FFTT_HIP(c, solver_dot(s, fp64, r, r, D, part, sc, MIS, 1.0));
             return FFTT_OK;
         };
+        // |s|^2 of the current residual (gamma itself without preconditioner)
+        const int ss = pc ? SS : GAMMA;
         for (it = 0; it < o->max_iter;) {
             SOLVE_OK(graph.step(it, iteration));
             ++it;
             if (check) {
                 SOLVE_OK(fetch());
                 misfit = hs[MIS];
-                relres = hs[G0] > 0 ? std::sqrt(hs[GAMMA] / hs[G0]) : 0.0;
+                relres = hs[SS0] > 0 ? std::sqrt(hs[ss] / hs[SS0]) : 0.0;
                 if (o->target_misfit > 0 && misfit <= o->target_misfit) break;
                 if (o->rel_tol > 0 && relres <= o->rel_tol) break;
             }
         }
         SOLVE_OK(fetch());
         misfit = hs[MIS];
-        relres = hs[G0] > 0 ? std::sqrt(hs[GAMMA] / hs[G0]) : 0.0;
+        relres = hs[SS0] > 0 ? std::sqrt(hs[ss] / hs[SS0]) : 0.0;
     } else {
         // LSQR (Paige & Saunders) on A = J / sigma, b = d / sigma, damp = sqrt(alpha)
         enum { BETA = 8, ALPHA = 9, PHIBAR = 11, PHI_RHO = 12, THETA_RHO = 13, XX = 14,

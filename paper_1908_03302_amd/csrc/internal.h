@@ -133,6 +133,12 @@ enum StagedTable {
     STAB_SERIES = 3,  // no table: the band's sine series (scalar loads, no LDS)
 };
 hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a);
+// mode 1: out = sum_i |J_ij| (sensitivity coverage), mode 2: out = diag(J^T J),
+// summed over bands and multiplied by wscale (a power of two), for the
+// active voxels of a.out (others untouched); w: scratch [nb][M] (a.M =
+// kernel pairs).
+hipError_t launch_coverage(hipStream_t s, int tabfmt, int mode, const ApplyArgs& a,
+                           const double* C, const int32_t* kptr, double wscale, float* w);
 // LDS of a staged launch: tables plus q staged transducers (q * 512 bytes).
 size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t q, int wpb);
 // Batched point-spread functions: W ([nb][M][ldw], zeroed) and out ([n][N],
@@ -162,6 +168,10 @@ hipError_t solver_cgls_beta(hipStream_t s, double* sc);
 hipError_t solver_lsqr_beta(hipStream_t s, double* sc);
 hipError_t solver_lsqr_alpha_rot(hipStream_t s, double* sc, double damp, int first);
 hipError_t solver_unit(hipStream_t s, bool fp64, void* x, int64_t n, int64_t v);
+hipError_t solver_jacobi(hipStream_t s, bool fp64, void* minv, const float* diag, int64_t n,
+                         double scale, double alpha);
+hipError_t solver_mul(hipStream_t s, bool fp64, void* z, const void* a, const void* b,
+                      int64_t n);
 
 // ---- host table builder (table.cpp) ----
 int build_table_from_pulse(double c0, const double* f, int64_t nt, double dt, int64_t n,
@@ -237,7 +247,7 @@ struct fftt_ctx {
     size_t lds_limit = 65536;
 
     // work buffers
-    fftt::DevBuf d_w, d_part, d_red, d_solve, d_scal;
+    fftt::DevBuf d_w, d_part, d_red, d_solve, d_scal, d_diag;
     fftt::DevBuf d_psfw, d_psfd;   // batched PSF weights, (tile, lane) of each voxel
 
     // optional event timing of the main kernels (index: 0 J, 1 J^T, 2 reduction)

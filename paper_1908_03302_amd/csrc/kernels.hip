@@ -1166,7 +1166,11 @@ __device__ __forceinline__ StepWeights<NB, U> load_weights(const ApplyArgs& A,
     return W;
 }
 
-template <int NB, class TabT, int U>
+// MODE of the J^T kernel: 0 = J^T dT (weights C_p sum dT); 1 = sensitivity
+// coverage sum_i |J_ij| (weights |C_p| m_p, |h|); 2 = diag(J^T J) =
+// sum_i J_ij^2 (weights C_p^2 m_p, h^2, (1/(R_xs R_xr))^2); m_p = caller
+// pairs sharing kernel pair p.
+template <int NB, class TabT, int U, int MODE = 0>
 __device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, const float2* sx,
                                            const StepEntries<U>& E, const StepWeights<NB, U>& W,
                                            float nm1, int lane, int& prev, float& cd, float& cg,
@@ -1191,14 +1195,21 @@ __device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, c
             for (int u = 0; u < U; ++u) xb[u] = b == 0 ? x0[u] : x0[u] * A.xr[b];
             lookup_n<U>(band_tab(st, b, A.ntab), xb, nm1, h);
 #pragma unroll
-            for (int u = 0; u < U; ++u) hw[u] = b == 0 ? h[u] * W.w[u][0] : fmaf(h[u], W.w[u][b], hw[u]);
+            for (int u = 0; u < U; ++u) {
+                if constexpr (MODE == 1) h[u] = fabsf(h[u]);
+                if constexpr (MODE == 2) h[u] *= h[u];
+                hw[u] = b == 0 ? h[u] * W.w[u][0] : fmaf(h[u], W.w[u][b], hw[u]);
+            }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc = fmaf(hw[u], sg[u] * rg[u], acc);
+        for (int u = 0; u < U; ++u) {
+            const float g = sg[u] * rg[u];
+            acc = fmaf(hw[u], MODE == 2 ? g * g : g, acc);
+        }
     });
 }
 
-template <int NB, class TabT, int U>
+template <int NB, class TabT, int U, int MODE = 0>
 __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_jt32s(ApplyArgs A) {
     const TabT* st = stage_table<TabT>(A, NB);
     float2* sx = staged_tx<TabT>(A, NB);
@@ -1214,13 +1225,13 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_jt32s(ApplyArgs A) {
         int64_t e = e0;
         for (; e + U <= e1; e += U) {
             const StepEntries<U> E = load_entries<U>(A.ents, e, q0);
-            jt32s_body<NB, TabT, U>(A, st, sx, E, load_weights<NB, U>(A, w, E), nm1, lane, prev,
-                                    cd, cg, acc);
+            jt32s_body<NB, TabT, U, MODE>(A, st, sx, E, load_weights<NB, U>(A, w, E), nm1, lane,
+                                          prev, cd, cg, acc);
         }
         for (; e < e1; ++e) {
             const StepEntries<1> E = load_entries<1>(A.ents, e, q0);
-            jt32s_body<NB, TabT, 1>(A, st, sx, E, load_weights<NB, 1>(A, w, E), nm1, lane, prev,
-                                    cd, cg, acc);
+            jt32s_body<NB, TabT, 1, MODE>(A, st, sx, E, load_weights<NB, 1>(A, w, E), nm1, lane,
+                                          prev, cd, cg, acc);
         }
     });
     // combine the wavefronts in order (the staged distances are no longer
@@ -1368,6 +1379,58 @@ hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const 
         case 4: return launch_staged_nb<4>(s, tabfmt, transpose, a);
     }
     return hipErrorInvalidValue;
+}
+
+// Sensitivity coverage / diag(J^T J): the staged J^T kernel in MODE 1 / 2
+// (four entries per step) with per-pair weights from k_coverage_weights.
+template <int NB, int MODE>
+static hipError_t launch_coverage_nb(hipStream_t s, int tabfmt, const ApplyArgs& a) {
+    switch (tabfmt) {
+        case STAB_NODE32:
+            return launch_staged(k_jt32s<NB, float, 4, MODE>, s, a, (size_t)NB * a.ntab * 4);
+        case STAB_PAIR32:
+            return launch_staged(k_jt32s<NB, float2, 4, MODE>, s, a, (size_t)NB * a.ntab * 8);
+        case STAB_BF16:
+            return launch_staged(k_jt32s<NB, uint32_t, 4, MODE>, s, a, (size_t)NB * a.ntab * 4);
+        case STAB_SERIES: return launch_staged(k_jt32s<NB, SinCoef, 4, MODE>, s, a, 0);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int MODE>
+static hipError_t launch_coverage_m(hipStream_t s, int tabfmt, const ApplyArgs& a) {
+    switch (a.nb) {
+        case 1: return launch_coverage_nb<1, MODE>(s, tabfmt, a);
+        case 2: return launch_coverage_nb<2, MODE>(s, tabfmt, a);
+        case 3: return launch_coverage_nb<3, MODE>(s, tabfmt, a);
+        case 4: return launch_coverage_nb<4, MODE>(s, tabfmt, a);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Weights of the coverage passes times wscale, a power of two that keeps them
+// in the normal FP32 range (C_p^2 is ~1e-42 for millimetre voxels).
+__global__ void k_coverage_weights(const double* __restrict__ C, const int32_t* __restrict__ kptr,
+                                   int64_t Mk, int nb, int mode, double wscale,
+                                   float* __restrict__ w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Mk * (int64_t)nb) return;
+    const int64_t k = i % Mk;
+    const double m = (double)(kptr[k + 1] - kptr[k]);
+    w[i] = (float)((mode == 1 ? fabs(C[k]) * m : C[k] * C[k] * m) * wscale);
+}
+
+hipError_t launch_coverage(hipStream_t s, int tabfmt, int mode, const ApplyArgs& a,
+                           const double* C, const int32_t* kptr, double wscale, float* w) {
+    const int64_t n = a.M * (int64_t)a.nb;
+    if (n > 0)
+        hipLaunchKernelGGL(k_coverage_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           C, kptr, a.M, a.nb, mode, wscale, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ApplyArgs b = a;
+    b.w = w;
+    return mode == 1 ? launch_coverage_m<1>(s, tabfmt, b) : launch_coverage_m<2>(s, tabfmt, b);
 }
 
 // ------------------------------------------------------------ J reduction

@@ -199,6 +199,48 @@ hipError_t solver_lsqr_alpha_rot(hipStream_t s, double* sc, double damp, int fir
     return hipGetLastError();
 }
 
+// ---- Jacobi preconditioner ----
+
+// minv = 1 / (scale * diag + alpha) (0 where that is not positive)
+template <class T>
+__global__ void k_jacobi(T* __restrict__ minv, const float* __restrict__ diag, int64_t n,
+                         double scale, double alpha) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double d = scale * (double)diag[i] + alpha;
+    minv[i] = (T)(d > 0.0 ? 1.0 / d : 0.0);
+}
+
+// z = a * b elementwise
+template <class T>
+__global__ void k_mul(T* __restrict__ z, const T* __restrict__ a, const T* __restrict__ b,
+                      int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = a[i] * b[i];
+}
+
+hipError_t solver_jacobi(hipStream_t s, bool fp64, void* minv, const float* diag, int64_t n,
+                         double scale, double alpha) {
+    if (fp64)
+        hipLaunchKernelGGL(k_jacobi<double>, dim3(nblk(n)), dim3(256), 0, s, (double*)minv, diag,
+                           n, scale, alpha);
+    else
+        hipLaunchKernelGGL(k_jacobi<float>, dim3(nblk(n)), dim3(256), 0, s, (float*)minv, diag,
+                           n, scale, alpha);
+    return hipGetLastError();
+}
+
+hipError_t solver_mul(hipStream_t s, bool fp64, void* z, const void* a, const void* b,
+                      int64_t n) {
+    if (fp64)
+        hipLaunchKernelGGL(k_mul<double>, dim3(nblk(n)), dim3(256), 0, s, (double*)z,
+                           (const double*)a, (const double*)b, n);
+    else
+        hipLaunchKernelGGL(k_mul<float>, dim3(nblk(n)), dim3(256), 0, s, (float*)z,
+                           (const float*)a, (const float*)b, n);
+    return hipGetLastError();
+}
+
 // ---- point-spread functions ----
 
 // dc = e_v (1 m/s at voxel v): zero fill then one element.

@@ -24,7 +24,8 @@ EXPORTS = ["fftt_create", "fftt_destroy", "fftt_last_error", "fftt_set_stream",
            "fftt_set_geometry", "fftt_set_kernel_table", "fftt_build_table_from_pulse",
            "fftt_prepare", "fftt_work_count", "fftt_apply_J", "fftt_apply_JT", "fftt_solve",
            "fftt_psf", "fftt_profile", "fftt_kernel_time", "fftt_set_tuning", "fftt_get_tuning",
-           "fftt_autotune", "fftt_set_kernel_series", "fftt_build_series_from_pulse"]
+           "fftt_autotune", "fftt_set_kernel_series", "fftt_build_series_from_pulse",
+           "fftt_coverage"]
 TUNE_WAVES_PER_BLOCK, TUNE_UNROLL_JT, TUNE_UNROLL_J, TUNE_SPLIT_JT, TUNE_SPLIT_J = 0, 1, 2, 3, 4
 TUNE_STAGED, TUNE_UNROLL_JT_STAGED, TUNE_UNROLL_J_STAGED = 5, 6, 7
 TUNE_STAGED_TABLE = 8
@@ -37,7 +38,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("prec", C.c_int32), ("alpha", C.c_double),
                 ("noise_sigma", C.c_double), ("max_iter", C.c_int32), ("use_x0", C.c_int32),
                 ("target_misfit", C.c_double), ("rel_tol", C.c_double),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("precond", C.c_int32)]
 
 
 class SolveReport(C.Structure):
@@ -86,6 +87,7 @@ def load():
     L.fftt_apply_JT.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
     L.fftt_solve.argtypes = [vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveReport)]
     L.fftt_psf.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.c_int32, C.c_double, vp]
+    L.fftt_coverage.argtypes = [vp, C.c_int, C.c_int32, vp]
     L.fftt_profile.argtypes = [vp, C.c_int32]
     L.fftt_set_tuning.argtypes = [vp, C.c_int32, C.c_int32]
     L.fftt_get_tuning.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
@@ -291,9 +293,10 @@ class Context:
         return dc
 
     def solve(self, d_obs, x, method=0, prec=FP32, alpha=1e-3, noise_sigma=1.0, max_iter=20,
-              x0=False, target_misfit=0.0, rel_tol=0.0, graph=False):
+              x0=False, target_misfit=0.0, rel_tol=0.0, graph=False, precond=False):
         o = SolveOpts(int(method), int(prec), float(alpha), float(noise_sigma), int(max_iter),
-                      1 if x0 else 0, float(target_misfit), float(rel_tol), 1 if graph else 0)
+                      1 if x0 else 0, float(target_misfit), float(rel_tol), 1 if graph else 0,
+                      1 if precond else 0)
         rep = SolveReport()
         self._bind_stream()
         st = self._check(self.L.fftt_solve(
@@ -301,6 +304,16 @@ class Context:
             self._tensor(x, prec, self.N, "x"), C.byref(rep)), "solve")
         return dict(iters=rep.iters, misfit=rep.misfit, rel_resid=rep.rel_resid,
                     time_ms=rep.time_ms, converged=(st == FFTT_OK))
+
+    def coverage(self, kind=0, out=None, prec=FP32):
+        """kind 0: sum_i |J_ij| (sensitivity coverage); 1: diag(J^T J); FP32 [N]."""
+        torch = self._torch
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float32, device="cuda:%d" % self.device)
+        self._bind_stream()
+        self._check(self.L.fftt_coverage(self.h, int(prec), int(kind),
+                                         self._tensor(out, FP32, self.N, "out")), "coverage")
+        return out
 
     def psf(self, voxels, noise_sigma, out=None, prec=FP32):
         torch = self._torch

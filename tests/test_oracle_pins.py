@@ -338,6 +338,59 @@ def test_cgls_reaches_damped_normal_equation_solution(small, dense_small):
     assert all(hist[i + 1] <= hist[i] * (1 + 1e-12) for i in range(5))
 
 
+def _jacobi(Jd, sig, alpha):
+    return 1.0 / ((Jd ** 2).sum(axis=0) / sig ** 2 + alpha)
+
+
+def test_pcgls_identity_preconditioner_is_cgls(small, dense_small):
+    w, o = small
+    Jd = dense_small
+    sig = w.noise_sigma
+    d = Jd @ w.model + I.noise(w.m, sig, w.noise_seed)
+    ops = (lambda v: Jd @ v, lambda v: Jd.T @ v)
+    x1, h1 = solvers.cgls(*ops, d, sig, ALPHA_SMALL, 20)
+    x2, h2 = solvers.pcgls(*ops, d, sig, ALPHA_SMALL, np.ones(w.n), 20)
+    assert np.linalg.norm(x2 - x1) <= 1e-12 * np.linalg.norm(x1)
+    assert np.allclose(h1, h2, rtol=1e-12)
+
+
+def test_pcgls_is_cg_on_the_symmetrically_scaled_system(small, dense_small):
+    """PCG with M = D equals plain CG (textbook Hestenes-Stiefel, written out
+    here on the explicit matrix) on D^-1/2 A D^-1/2 y = D^-1/2 b with
+    x = D^-1/2 y, iterate by iterate; and it reaches numpy's direct solve."""
+    w, o = small
+    Jd = dense_small
+    sig = w.noise_sigma
+    d = Jd @ w.model + I.noise(w.m, sig, w.noise_seed)
+    minv = _jacobi(Jd, sig, ALPHA_SMALL)
+    A = Jd.T @ Jd / sig ** 2 + ALPHA_SMALL * np.eye(w.n)
+    rhs = Jd.T @ d / sig ** 2
+    sc = np.sqrt(minv)
+    As = sc[:, None] * A * sc[None, :]
+    bs = sc * rhs
+    y = np.zeros(w.n)
+    r = bs.copy()
+    p = r.copy()
+    rr = r @ r
+    for k in range(1, 7):
+        Ap = As @ p
+        a = rr / (p @ Ap)
+        y += a * p
+        r -= a * Ap
+        rr_new = r @ r
+        p = r + rr_new / rr * p
+        rr = rr_new
+        if k in (3, 6):
+            # the two forms round differently and CG amplifies that from
+            # iteration to iteration (~4x each here): compare early iterates
+            x, _ = solvers.pcgls(lambda v: Jd @ v, lambda v: Jd.T @ v, d, sig, ALPHA_SMALL,
+                                 minv, k)
+            assert np.linalg.norm(x - sc * y) <= 1e-11 * np.linalg.norm(sc * y)
+    x, _ = solvers.pcgls(lambda v: Jd @ v, lambda v: Jd.T @ v, d, sig, ALPHA_SMALL, minv, 300)
+    xd = np.linalg.solve(A, rhs)
+    assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
 def test_lsqr_matches_scipy(small, dense_small):
     """Same iterates as scipy's LSQR on the dense matrix."""
     from scipy.sparse.linalg import lsqr as sp_lsqr
