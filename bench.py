@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--no-psf", action="store_true", help="skip the batched PSF leg")
     ap.add_argument("--no-multiband", action="store_true", help="skip the four-band leg")
     ap.add_argument("--no-slices", action="store_true", help="skip the 16-height slice leg")
+    ap.add_argument("--no-lowrank", action="store_true",
+                    help="skip the low-rank Hessian eigen-decomposition leg")
     ap.add_argument("--no-series", action="store_true",
                     help="skip the sine-series evaluation leg")
     ap.add_argument("--no-autotune", action="store_true",
@@ -251,6 +253,8 @@ def main():
     if not args.no_psf:
         out["psf"] = psf_leg(ctx, w, fftt, torch, pv)
     out["coverage"] = coverage_leg(ctx, w, torch)
+    if not args.no_lowrank:
+        out["lowrank"] = lowrank_leg(ctx, w, fftt, torch)
     if not args.no_series:
         out["series"] = series_leg(ctx, w, fftt, torch, pv, avg_j, avg_jt)
     del dc, dT, dc2
@@ -295,6 +299,34 @@ def psf_leg(ctx, w, fftt, torch, pv, reps=3):
             % (name, wall, kms, tf))
     del out
     return res
+
+
+def lowrank_leg(ctx, w, fftt, torch, k=32, l=40, q=2):
+    """k leading eigenpairs of J^T J / sigma^2 (randomized range finder, q
+    subspace iterations, Rayleigh-Ritz) from a seeded Gaussian start block,
+    FP32 operators, then the low-rank posterior variance / resolution
+    diagonals (alpha of the workload)."""
+    import numpy as np
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(7)
+    om = torch.randn(l * w.n, dtype=torch.float32, device="cuda:0", generator=gen)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vals, vecs, r = ctx.hessian_lowrank(om, k, q=q, noise_sigma=w.noise_sigma, prec=fftt.FP32)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    var, res = ctx.lowrank_diag(vals, vecs, w.extra["alpha"], prec=fftt.FP32)
+    torch.cuda.synchronize()
+    t_diag = time.perf_counter() - t0
+    applies = l + (q + 1) * r
+    log("bench: low-rank Hessian: %d Ritz pairs from %d samples, %d subspace iterations: "
+        "%.1f ms (%d J + J^T applications), diagonals %.2f ms; leading eigenvalues %s"
+        % (k, l, q, 1e3 * t_eig, applies, 1e3 * t_diag, np.array2string(vals[:4], precision=4)))
+    return {"k": k, "samples": l, "subspace_iterations": q, "rank": r, "ms": 1e3 * t_eig,
+            "operator_applications": applies, "diag_ms": 1e3 * t_diag,
+            "leading_eigenvalues": [float(v) for v in vals[:8]],
+            "resolution_diag_max": float(res.max())}
 
 
 def coverage_leg(ctx, w, torch, reps=5):

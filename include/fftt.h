@@ -214,6 +214,35 @@ fftt_status fftt_solve(fftt_ctx *ctx, const fftt_solve_opts *opts,
  * FFTT_FP64).  out: device [N] FP32, inactive voxels 0.  Asynchronous. */
 fftt_status fftt_coverage(fftt_ctx *ctx, fftt_precision prec, int32_t kind, void *out);
 
+/* Low-rank eigen-decomposition of the Gauss-Newton Hessian of the misfit,
+ * H = J^T J / sigma^2 summed over bands (eq. low_rank with Gamma_pr = I),
+ * by a randomized range finder with q subspace iterations and a
+ * Rayleigh-Ritz step (Halko, Martinsson & Tropp, SIAM Review 2011):
+ * Q = orth(H omega), then q times Q = orth(H Q), then T = Q^T H Q = U Theta
+ * U^T and the Ritz pairs (Theta, Q U).  orth keeps the directions whose
+ * Gram eigenvalue exceeds 1e-24 (FP64) / 1e-12 (otherwise) of the largest,
+ * so a sampled range of lower rank r yields r Ritz pairs; *rank_out (may be
+ * NULL) returns r, and eigenvalues / vectors beyond r are 0.
+ *   omega: device [l][N] start block (the caller's random numbers), in the
+ *   operator's precision; 1 <= k <= l <= 512, 0 <= q <= 32.
+ *   eigvals: host [k], descending; eigvecs: device [k][N], orthonormal.
+ * Costs l + (q + 1) r applications of J and of J^T plus FP64 Gram matrices
+ * of the blocks; synchronises the stream. */
+fftt_status fftt_hessian_lowrank(fftt_ctx *ctx, fftt_precision prec, double noise_sigma,
+                                 const void *omega, int32_t l, int32_t q, int32_t k,
+                                 double *eigvals, void *eigvecs, int32_t *rank_out);
+
+/* Diagonals of the low-rank posterior covariance and resolution matrix
+ * (eq. posterior_app / resolution_app with Gamma_pr = I) from k eigenpairs
+ * of H:  d_i = lambda_i / (lambda_i + alpha),
+ *   var_j = (1 - sum_i d_i v_ij^2) / alpha,   res_j = sum_i d_i v_ij^2.
+ * eigvals: host [k] (>= 0); eigvecs: device [k][N]; var_out, res_out: device
+ * [N] or NULL (not both); buffers in the precision's type; alpha > 0.
+ * Synchronises the stream. */
+fftt_status fftt_lowrank_diag(fftt_ctx *ctx, fftt_precision prec, const double *eigvals,
+                              const void *eigvecs, int32_t k, double alpha, void *var_out,
+                              void *res_out);
+
 /* Hessian point-spread functions (eq. resolution_2):
  * out[k] = J^T J e_{voxels[k]} / sigma^2, e_i = 1 m/s at voxel i, summed
  * over bands.

@@ -79,6 +79,48 @@ def pcgls(J, JT, d, sigma, alpha, minv, n_iter, x0=None):
     return x, hist
 
 
+def orth(Y, rel_tol):
+    """Orthonormal basis of the range of Y's columns: left singular vectors
+    whose squared singular value exceeds rel_tol times the largest."""
+    U, s, _ = np.linalg.svd(Y, full_matrices=False)
+    keep = s ** 2 > rel_tol * s[0] ** 2 if s.size and s[0] > 0 else np.zeros(0, bool)
+    return U[:, keep]
+
+
+def randomized_eigh(H, omega, q, k, rel_tol=1e-24):
+    """k leading eigenpairs of a symmetric positive semidefinite operator by a
+    randomized range finder with q subspace iterations and Rayleigh-Ritz
+    (Halko, Martinsson & Tropp 2011): Q = orth(H omega); q times
+    Q = orth(H Q); T = Q^T H Q = U diag(theta) U^T; Ritz pairs (theta, Q U).
+    H maps an [N][c] block to [N][c].  Returns (eigenvalues [k] descending,
+    zero-padded beyond the sampled rank; vectors [N][k]; rank)."""
+    Q = orth(H(omega), rel_tol)
+    for _ in range(q):
+        Q = orth(H(Q), rel_tol)
+    r = Q.shape[1]
+    T = Q.T @ H(Q)
+    T = 0.5 * (T + T.T)
+    w, U = np.linalg.eigh(T)
+    order = np.argsort(w)[::-1]
+    w, U = w[order], U[:, order]
+    kk = min(k, r)
+    vals = np.zeros(k)
+    vecs = np.zeros((Q.shape[0], k))
+    vals[:kk] = w[:kk]
+    vecs[:, :kk] = Q @ U[:, :kk]
+    return vals, vecs, r
+
+
+def lowrank_posterior_diag(vals, vecs, alpha):
+    """Diagonals of the low-rank posterior covariance and resolution
+    (eq. posterior_app / resolution_app, Gamma_pr = I):
+    var = (1 - sum_i d_i v_i^2) / alpha, res = sum_i d_i v_i^2,
+    d_i = lambda_i / (lambda_i + alpha)."""
+    d = vals / (vals + alpha)
+    s = (vecs ** 2) @ d
+    return (1.0 - s) / alpha, s
+
+
 def lsqr(J, JT, b, damp, n_iter, n_cols):
     """LSQR of Paige and Saunders (1982) for min |A x - b|^2 + damp^2 |x|^2,
     written from the published bidiagonalisation recurrences; x0 = 0."""

@@ -521,6 +521,61 @@ fftt_status ensure_ready(fftt_ctx* c) {
     return FFTT_OK;
 }
 
+// ---- randomized eigensolver for H = J^T J / sigma^2 (Sec. II-E) ----
+
+// y = H x = J^T (J x) / sigma^2; dT: scratch [nb][M].
+fftt_status hess_apply(fftt_ctx* c, fftt_precision prec, double isg2, const void* x, void* dT,
+                       void* y) {
+    fftt_status st = apply_J_one(c, prec, x, dT);
+    if (st != FFTT_OK) return st;
+    FFTT_HIP(c, solver_lin2(c->stream, prec == FFTT_FP64, dT, dT, nullptr, (int64_t)c->nb * c->M,
+                            isg2, 0.0));
+    return apply_JT_one(c, prec, dT, y);
+}
+
+// Orthonormal basis of the columns of Y ([l][N]) by the eigen-decomposition
+// of the FP64 Gram matrix (G = U S U^T, Q = Y U_r S_r^-1/2 over the r
+// eigenvalues above rel_tol S_max), done twice; the basis overwrites Y (the
+// first pass goes through T).  Returns r.
+fftt_status orth_block(fftt_ctx* c, bool fp64, void* Y, void* T, int l, double rel_tol,
+                       int* r_out) {
+    const int64_t N = c->N;
+    int cols = l;
+    for (int pass = 0; pass < 2; ++pass) {
+        void* src = pass == 0 ? Y : T;
+        void* dst = pass == 0 ? T : Y;
+        FFTT_HIP(c, c->d_lr_part.alloc(gram_part_doubles(cols, cols, N) * sizeof(double)));
+        FFTT_HIP(c, c->d_lr_small.alloc((size_t)cols * cols * sizeof(double)));
+        FFTT_HIP(c, launch_gram(c->stream, fp64, src, cols, src, cols, N,
+                                c->d_lr_part.as<double>(), c->d_lr_small.as<double>()));
+        std::vector<double> G((size_t)cols * cols), w, U;
+        FFTT_HIP(c, hipMemcpyAsync(G.data(), c->d_lr_small.p, G.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, c->stream));
+        FFTT_HIP(c, hipStreamSynchronize(c->stream));
+        for (int a = 0; a < cols; ++a)   // exact symmetry before the eigensolver
+            for (int b = a + 1; b < cols; ++b)
+                G[(size_t)a * cols + b] = G[(size_t)b * cols + a] =
+                    0.5 * (G[(size_t)a * cols + b] + G[(size_t)b * cols + a]);
+        jacobi_eigh(G, cols, w, U);
+        int r = 0;
+        while (r < cols && w[r] > rel_tol * w[0] && w[r] > 0.0) ++r;
+        if (r == 0) {
+            *r_out = 0;
+            return FFTT_OK;
+        }
+        std::vector<double> W((size_t)cols * r);
+        for (int a = 0; a < cols; ++a)
+            for (int b = 0; b < r; ++b) W[(size_t)a * r + b] = U[(size_t)a * cols + b] / std::sqrt(w[b]);
+        FFTT_HIP(c, hipMemcpy(c->d_lr_small.p, W.data(), W.size() * sizeof(double),
+                              hipMemcpyHostToDevice));
+        FFTT_HIP(c, launch_combine(c->stream, fp64, src, cols, N, c->d_lr_small.as<double>(), r,
+                                   dst));
+        cols = r;
+    }
+    *r_out = cols;
+    return FFTT_OK;
+}
+
 }  // namespace
 
 // Solver iterations in a HIP graph: iteration 0 runs eagerly (it allocates
@@ -770,6 +825,112 @@ fftt_status fftt_coverage(fftt_ctx* c, fftt_precision prec, int32_t kind, void* 
     fftt_status st = ensure_ready(c);
     if (st != FFTT_OK) return st;
     return coverage_one(c, prec, kind, static_cast<float*>(out));
+}
+
+fftt_status fftt_hessian_lowrank(fftt_ctx* c, fftt_precision prec, double noise_sigma,
+                                 const void* omega, int32_t l, int32_t q, int32_t k,
+                                 double* eigvals, void* eigvecs, int32_t* rank_out) {
+    if (!c) return FFTT_E_INVALID;
+    if (prec < FFTT_FP64 || prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "lowrank: unknown precision");
+    if (!omega || !eigvals || !eigvecs) FFTT_BAD(c, "lowrank: null argument");
+    if (l < 1 || l > 512 || k < 1 || k > l || q < 0 || q > 32)
+        FFTT_BAD(c, "lowrank: need 1 <= k <= l <= 512 and 0 <= q <= 32");
+    if (!(noise_sigma > 0) || !std::isfinite(noise_sigma)) FFTT_BAD(c, "lowrank: noise_sigma must be > 0");
+    fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    const bool fp64 = prec == FFTT_FP64;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    const int64_t N = c->N, D = (int64_t)c->nb * c->M;
+    const double isg2 = 1.0 / (noise_sigma * noise_sigma);
+    // rank threshold on the Gram eigenvalues (squared singular values)
+    const double tol = fp64 ? 1e-24 : 1e-12;
+    FFTT_HIP(c, c->d_lr.alloc((size_t)2 * l * N * es));
+    FFTT_HIP(c, c->d_solve.alloc((size_t)D * es));
+    char* A = c->d_lr.as<char>();
+    char* B = A + (size_t)l * N * es;
+    void* dT = c->d_solve.p;
+    auto col = [&](const void* base, int i) {
+        return static_cast<const char*>(base) + (size_t)i * N * es;
+    };
+    // A = H Omega, orthonormalised
+    for (int i = 0; i < l; ++i) {
+        st = hess_apply(c, prec, isg2, col(omega, i), dT, A + (size_t)i * N * es);
+        if (st != FFTT_OK) return st;
+    }
+    int r = 0;
+    st = orth_block(c, fp64, A, B, l, tol, &r);
+    if (st != FFTT_OK) return st;
+    // subspace iterations: A = orth(H A)
+    for (int it = 0; it < q && r > 0; ++it) {
+        for (int i = 0; i < r; ++i) {
+            st = hess_apply(c, prec, isg2, col(A, i), dT, B + (size_t)i * N * es);
+            if (st != FFTT_OK) return st;
+        }
+        std::swap(A, B);
+        st = orth_block(c, fp64, A, B, r, tol, &r);
+        if (st != FFTT_OK) return st;
+    }
+    if (rank_out) *rank_out = r;
+    std::vector<double> evals(k, 0.0);
+    FFTT_HIP(c, launch_fill(c->stream, fp64, eigvecs, (int64_t)k * N));
+    if (r > 0) {
+        // Rayleigh-Ritz: T = Q^T H Q, T = U Theta U^T, Ritz vectors Q U
+        for (int i = 0; i < r; ++i) {
+            st = hess_apply(c, prec, isg2, col(A, i), dT, B + (size_t)i * N * es);
+            if (st != FFTT_OK) return st;
+        }
+        FFTT_HIP(c, c->d_lr_part.alloc(gram_part_doubles(r, r, N) * sizeof(double)));
+        FFTT_HIP(c, c->d_lr_small.alloc((size_t)r * r * sizeof(double)));
+        FFTT_HIP(c, launch_gram(c->stream, fp64, A, r, B, r, N, c->d_lr_part.as<double>(),
+                                c->d_lr_small.as<double>()));
+        std::vector<double> T((size_t)r * r), w, U;
+        FFTT_HIP(c, hipMemcpyAsync(T.data(), c->d_lr_small.p, T.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, c->stream));
+        FFTT_HIP(c, hipStreamSynchronize(c->stream));
+        for (int a = 0; a < r; ++a)
+            for (int b = a + 1; b < r; ++b)
+                T[(size_t)a * r + b] = T[(size_t)b * r + a] =
+                    0.5 * (T[(size_t)a * r + b] + T[(size_t)b * r + a]);
+        jacobi_eigh(T, r, w, U);
+        const int kk = std::min<int>(k, r);
+        std::vector<double> Uk((size_t)r * kk);
+        for (int a = 0; a < r; ++a)
+            for (int b = 0; b < kk; ++b) Uk[(size_t)a * kk + b] = U[(size_t)a * r + b];
+        for (int b = 0; b < kk; ++b) evals[b] = w[b];
+        FFTT_HIP(c, hipMemcpy(c->d_lr_small.p, Uk.data(), Uk.size() * sizeof(double),
+                              hipMemcpyHostToDevice));
+        FFTT_HIP(c, launch_combine(c->stream, fp64, A, r, N, c->d_lr_small.as<double>(), kk,
+                                   eigvecs));
+    }
+    FFTT_HIP(c, hipStreamSynchronize(c->stream));
+    std::copy(evals.begin(), evals.end(), eigvals);
+    return FFTT_OK;
+}
+
+fftt_status fftt_lowrank_diag(fftt_ctx* c, fftt_precision prec, const double* eigvals,
+                              const void* eigvecs, int32_t k, double alpha, void* var_out,
+                              void* res_out) {
+    if (!c) return FFTT_E_INVALID;
+    if (prec < FFTT_FP64 || prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "lowrank_diag: unknown precision");
+    if (!eigvals || !eigvecs || k < 1 || (!var_out && !res_out))
+        FFTT_BAD(c, "lowrank_diag: null argument or k < 1");
+    if (!(alpha > 0) || !std::isfinite(alpha)) FFTT_BAD(c, "lowrank_diag: alpha must be > 0");
+    if (!c->has_geom) FFTT_FAIL(c, FFTT_E_STATE, "lowrank_diag: geometry not set");
+    for (int32_t i = 0; i < k; ++i)
+        if (!(eigvals[i] >= 0) || !std::isfinite(eigvals[i]))
+            FFTT_BAD(c, "lowrank_diag: eigenvalues must be finite and >= 0");
+    fftt_status st = set_device(c);
+    if (st != FFTT_OK) return st;
+    std::vector<double> d(k);
+    for (int32_t i = 0; i < k; ++i) d[i] = eigvals[i] / (eigvals[i] + alpha);
+    DevBuf dd;
+    FFTT_HIP(c, dd.alloc((size_t)k * sizeof(double)));
+    FFTT_HIP(c, hipMemcpy(dd.p, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
+    FFTT_HIP(c, launch_lowrank_diag(c->stream, prec == FFTT_FP64, eigvecs, k, c->N,
+                                    dd.as<double>(), 1.0 / alpha, var_out, res_out));
+    // dd is freed on return: the kernel must have read it
+    FFTT_HIP(c, hipStreamSynchronize(c->stream));
+    return FFTT_OK;
 }
 
 fftt_status fftt_prepare(fftt_ctx* c) {

@@ -173,6 +173,19 @@ hipError_t solver_jacobi(hipStream_t s, bool fp64, void* minv, const float* diag
 hipError_t solver_mul(hipStream_t s, bool fp64, void* z, const void* a, const void* b,
                       int64_t n);
 
+// ---- low-rank Hessian analysis (lowrank.hip) ----
+// out [la][lb] (FP64) = A B^T over n rows (A: [la][n], B: [lb][n]);
+// part: scratch of gram_part_doubles(la, lb, n) doubles.
+hipError_t launch_gram(hipStream_t s, bool fp64, const void* A, int la, const void* B, int lb,
+                       int64_t n, double* part, double* out);
+size_t gram_part_doubles(int la, int lb, int64_t n);
+// out [m][n] = sum_a Y[a][.] X[a][b] (X: device [l][m] FP64)
+hipError_t launch_combine(hipStream_t s, bool fp64, const void* Y, int l, int64_t n,
+                          const double* X, int m, void* out);
+hipError_t launch_lowrank_diag(hipStream_t s, bool fp64, const void* V, int k, int64_t n,
+                               const double* d, double inv_alpha, void* var, void* res);
+void jacobi_eigh(std::vector<double>& A, int n, std::vector<double>& w, std::vector<double>& U);
+
 // ---- host table builder (table.cpp) ----
 int build_table_from_pulse(double c0, const double* f, int64_t nt, double dt, int64_t n,
                            double r_max, double* h_out, double* r_max_out, std::string* err);
@@ -248,6 +261,7 @@ struct fftt_ctx {
 
     // work buffers
     fftt::DevBuf d_w, d_part, d_red, d_solve, d_scal, d_diag;
+    fftt::DevBuf d_lr, d_lr_part, d_lr_small;   // low-rank analysis: blocks, Gram scratch
     fftt::DevBuf d_psfw, d_psfd;   // batched PSF weights, (tile, lane) of each voxel
 
     // optional event timing of the main kernels (index: 0 J, 1 J^T, 2 reduction)

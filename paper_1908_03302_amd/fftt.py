@@ -25,7 +25,7 @@ EXPORTS = ["fftt_create", "fftt_destroy", "fftt_last_error", "fftt_set_stream",
            "fftt_prepare", "fftt_work_count", "fftt_apply_J", "fftt_apply_JT", "fftt_solve",
            "fftt_psf", "fftt_profile", "fftt_kernel_time", "fftt_set_tuning", "fftt_get_tuning",
            "fftt_autotune", "fftt_set_kernel_series", "fftt_build_series_from_pulse",
-           "fftt_coverage"]
+           "fftt_coverage", "fftt_hessian_lowrank", "fftt_lowrank_diag"]
 TUNE_WAVES_PER_BLOCK, TUNE_UNROLL_JT, TUNE_UNROLL_J, TUNE_SPLIT_JT, TUNE_SPLIT_J = 0, 1, 2, 3, 4
 TUNE_STAGED, TUNE_UNROLL_JT_STAGED, TUNE_UNROLL_J_STAGED = 5, 6, 7
 TUNE_STAGED_TABLE = 8
@@ -88,6 +88,9 @@ def load():
     L.fftt_solve.argtypes = [vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveReport)]
     L.fftt_psf.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.c_int32, C.c_double, vp]
     L.fftt_coverage.argtypes = [vp, C.c_int, C.c_int32, vp]
+    L.fftt_hessian_lowrank.argtypes = [vp, C.c_int, C.c_double, vp, C.c_int32, C.c_int32,
+                                       C.c_int32, dp, vp, C.POINTER(C.c_int32)]
+    L.fftt_lowrank_diag.argtypes = [vp, C.c_int, dp, vp, C.c_int32, C.c_double, vp, vp]
     L.fftt_profile.argtypes = [vp, C.c_int32]
     L.fftt_set_tuning.argtypes = [vp, C.c_int32, C.c_int32]
     L.fftt_get_tuning.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
@@ -314,6 +317,37 @@ class Context:
         self._check(self.L.fftt_coverage(self.h, int(prec), int(kind),
                                          self._tensor(out, FP32, self.N, "out")), "coverage")
         return out
+
+    def hessian_lowrank(self, omega, k, q=1, noise_sigma=1.0, prec=FP32, eigvecs=None):
+        """k leading Ritz pairs of J^T J / sigma^2 from the start block omega
+        ([l][N] device tensor).  Returns (eigenvalues [k] numpy, eigenvectors
+        [k][N] tensor, rank of the sampled range)."""
+        torch = self._torch
+        l = omega.numel() // max(self.N, 1)
+        if eigvecs is None:
+            eigvecs = torch.empty(k * self.N, dtype=_dtype_for(prec), device=omega.device)
+        ev = np.zeros(int(k))
+        r = C.c_int32(0)
+        self._bind_stream()
+        self._check(self.L.fftt_hessian_lowrank(
+            self.h, int(prec), float(noise_sigma), self._tensor(omega, prec, l * self.N, "omega"),
+            int(l), int(q), int(k), _dp(ev), self._tensor(eigvecs, prec, k * self.N, "eigvecs"),
+            C.byref(r)), "hessian_lowrank")
+        return ev, eigvecs, r.value
+
+    def lowrank_diag(self, eigvals, eigvecs, alpha, prec=FP32):
+        """(posterior variance, resolution) diagonals [N] from k eigenpairs."""
+        torch = self._torch
+        ev = np.ascontiguousarray(eigvals, dtype=np.float64)
+        k = ev.size
+        var = torch.empty(self.N, dtype=_dtype_for(prec), device=eigvecs.device)
+        res = torch.empty_like(var)
+        self._bind_stream()
+        self._check(self.L.fftt_lowrank_diag(
+            self.h, int(prec), _dp(ev), self._tensor(eigvecs, prec, k * self.N, "eigvecs"),
+            int(k), float(alpha), self._tensor(var, prec, self.N, "var"),
+            self._tensor(res, prec, self.N, "res")), "lowrank_diag")
+        return var, res
 
     def psf(self, voxels, noise_sigma, out=None, prec=FP32):
         torch = self._torch

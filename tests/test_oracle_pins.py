@@ -432,3 +432,55 @@ def test_tv_gradient_by_finite_differences():
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k]))
     # constant field: TV = N * beta
     assert abs(solvers.tv(np.full(60, 3.0), dims, sp, 0.1)[0] - 6.0) < 1e-12
+
+
+# ------------------------------------------------------------- low rank (Sec. II-E)
+def _low_rank_psd(n, r, seed):
+    B = np.random.default_rng(seed).standard_normal((n, r))
+    return B @ B.T
+
+
+def test_randomized_eigh_exact_on_low_rank():
+    """A positive semidefinite matrix of rank r below the sample size: the
+    range is captured exactly, so the Ritz pairs are its nonzero eigenpairs
+    (numpy eigh) and the reported rank is r."""
+    A = _low_rank_psd(300, 7, 1)
+    om = np.random.default_rng(2).standard_normal((300, 12))
+    vals, vecs, r = solvers.randomized_eigh(lambda X: A @ X, om, 1, 10)
+    assert r == 7
+    w, U = np.linalg.eigh(A)
+    w, U = w[::-1], U[:, ::-1]
+    assert np.allclose(vals[:7], w[:7], rtol=1e-10)
+    assert np.all(vals[7:] == 0.0)
+    assert np.allclose(np.abs(np.sum(vecs[:, :7] * U[:, :7], axis=0)), 1.0, atol=1e-9)
+
+
+def test_low_rank_posterior_is_exact_when_rank_is_captured():
+    """eq. posterior_app / resolution_app with every nonzero eigenpair of a
+    rank-r H: alpha^-1 (I - V D V^T) = (H + alpha I)^-1 and V D V^T =
+    (H + alpha I)^-1 H exactly (diagonals compared)."""
+    A = _low_rank_psd(200, 9, 3)
+    alpha = 0.7
+    w, U = np.linalg.eigh(A)
+    vals, vecs = w[::-1][:9], U[:, ::-1][:, :9]
+    var, res = solvers.lowrank_posterior_diag(vals, vecs, alpha)
+    P = np.linalg.inv(A + alpha * np.eye(200))
+    assert np.allclose(var, np.diag(P), rtol=1e-10, atol=0)
+    assert np.allclose(res, np.diag(P @ A), rtol=1e-9, atol=1e-12)
+
+
+def test_randomized_eigh_converges_on_the_small_ring(small, dense_small):
+    """Leading eigenvalues of the small ring's J^T J / sigma^2 (Lanczos,
+    scipy eigsh) from 40 samples and three subspace iterations: the largest
+    to 1e-9, the first eight to 2e-5 (the ring's symmetry makes pairs of
+    equal eigenvalues, which slows the others)."""
+    from scipy.sparse.linalg import eigsh
+    w, o = small
+    Jd = dense_small
+    sig = w.noise_sigma
+    ev = eigsh(Jd.T @ Jd / sig ** 2, k=10, which="LA")[0][::-1]
+    om = np.random.default_rng(5).standard_normal((w.n, 40))
+    vals, vecs, r = solvers.randomized_eigh(lambda X: Jd.T @ (Jd @ X) / sig ** 2, om, 3, 8)
+    err = np.abs(vals - ev[:8]) / ev[:8]
+    assert err[0] < 1e-9 and err.max() < 2e-5
+    assert np.allclose(vecs.T @ vecs, np.eye(8), atol=1e-12)
