@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--no-psf", action="store_true", help="skip the batched PSF leg")
     ap.add_argument("--no-multiband", action="store_true", help="skip the four-band leg")
     ap.add_argument("--no-slices", action="store_true", help="skip the 16-height slice leg")
+    ap.add_argument("--no-plane", action="store_true", help="skip the 2D-approximation leg")
     ap.add_argument("--no-lowrank", action="store_true",
                     help="skip the low-rank Hessian eigen-decomposition leg")
     ap.add_argument("--no-series", action="store_true",
@@ -260,6 +261,8 @@ def main():
     del dc, dT, dc2
     if not args.no_multiband:
         out["multiband"] = multiband_leg(fftt, torch)
+    if not args.no_plane:
+        out["plane2d"] = plane_leg(fftt, torch)
     if not args.no_slices:
         out["slices"] = slices_leg(fftt, torch)
     if not args.no_cpu:
@@ -384,6 +387,42 @@ def series_leg(ctx, w, fftt, torch, pv, table_j, table_jt, reps=5):
             "time_vs_table": (ms_j + ms_jt) / (table_j + table_jt), "flops_per_pv": fpv,
             "J_tflops": pv * fpv / (ms_j * 1e-3) / 1e12,
             "JT_tflops": pv * fpv / (ms_jt * 1e-3) / 1e12, "launch_shape": tuning}
+
+
+def plane_leg(fftt, torch, reps=10, iters=20):
+    """The 2D approximation of the lab-like ring (256x256 pixels, z over
+    +-24 mm on 60 layers): J and J^T, and 20 mixed-precision CGLS iterations
+    replayed from a HIP graph."""
+    from paper_1908_03302_amd import inputs as I
+    w = I.plane128()
+    ctx = fftt.context_for_workload(w, device=0)
+    t0 = time.perf_counter()
+    ctx.prepare()
+    t_prep = time.perf_counter() - t0
+    _, pv, _ = ctx.work_count()
+    dev = torch.device("cuda:0")
+    dc = torch.tensor(w.model, dtype=torch.float32, device=dev)
+    dT = torch.empty(w.m, dtype=torch.float32, device=dev)
+    dc2 = torch.empty(w.n, dtype=torch.float32, device=dev)
+    for _ in range(2):
+        ctx.apply_J(dc, dT)
+        ctx.apply_JT(dT, dc2)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.apply_J(dc, dT)
+        ctx.apply_JT(dT, dc2)
+    j, jt = ctx.kernel_time(0), ctx.kernel_time(1)
+    ctx.profile(False)
+    ms_j, ms_jt = j[0] / j[1], jt[0] / jt[1]
+    x = torch.zeros(w.n, dtype=torch.float32, device=dev)
+    rep = ctx.solve(dT, x, method=0, prec=fftt.FP32, alpha=w.extra["alpha"],
+                    noise_sigma=w.noise_sigma, max_iter=iters, graph=True)
+    log("bench: 2D plane (%d layers): prepare %.2f s, J %.3f ms, J^T %.3f ms, CGLS %d its %.1f ms"
+        % (w.nz, t_prep, ms_j, ms_jt, rep["iters"], rep["time_ms"]))
+    return {"workload": w.name, "pixels": w.n, "layers": w.nz, "pv_evaluated_per_apply": pv,
+            "J_ms": ms_j, "JT_ms": ms_jt, "pv_per_s": 2 * pv / ((ms_j + ms_jt) * 1e-3),
+            "cgls_iters": rep["iters"], "cgls_ms": rep["time_ms"]}
 
 
 def multiband_leg(fftt, torch, reps=10):

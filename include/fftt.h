@@ -85,6 +85,26 @@ fftt_status fftt_set_geometry(fftt_ctx *ctx, double c0,
                               const double origin[3], const double spacing[3],
                               const int64_t dims[3], const uint8_t *active_mask);
 
+/* The 2D approximation (Sec. II-B, eq. forward_2D): transducers and the
+ * model in (or near) one plane, the model constant along z over [z0, z1],
+ * so dT = sum over pixels of (int_{z0}^{z1} K0 dz) dc(x, y) dA.  The z
+ * integral is the midpoint rule on nz layers of thickness dz = (z1 - z0)/nz:
+ * the operators work on the prism of nx * ny * nz voxels (layer k at z0 +
+ * (k + 1/2) dz, voxel volume dA dz) with J reading dc(x, y) in every layer
+ * and J^T summing the layers.  Model vectors (apply_J input, apply_JT
+ * output, solves, point-spread functions, low-rank analysis) then have N =
+ * nx * ny values; fftt_coverage and the Jacobi preconditioner return
+ * FFTT_E_UNSUPPORTED (their absolute values and squares do not commute with
+ * the layer sum); fftt_work_count counts prism evaluations.
+ *   origin, spacing, dims: in-plane grid (pixel (0,0) centre, x fastest);
+ *   active_mask: host [ny][nx] or NULL; 1 <= nz <= 4096.  Otherwise as
+ *   fftt_set_geometry, which switches back to 3D. */
+fftt_status fftt_set_geometry_2d(fftt_ctx *ctx, double c0, const double *tx_xyz,
+                                 int64_t n_tx, const int32_t *pairs, int64_t n_pairs,
+                                 const double origin[2], const double spacing[2],
+                                 const int64_t dims[2], double z0, double z1, int64_t nz,
+                                 const uint8_t *active_mask);
+
 /* Kernel table of frequency band `band` (0 <= band < 4): host h[n] holds
  * h(k * r_max / (n-1)), k = 0..n-1, the function of the detour defined by
  * eq. Kernel_freq (without A).  Between nodes h is interpolated linearly;

@@ -260,3 +260,70 @@ class Oracle:
 
     def count_pv(self):
         return int(lib().orc_count_pv(C.byref(self.g)))
+
+
+# ---------------------------------------------------------------- 2D approximation
+def prism(w2):
+    """The prism of eq. forward_2D's z integral by the midpoint rule: nz
+    layers of thickness dz = (z1 - z0) / nz centred at z0 + (k + 1/2) dz over
+    the in-plane grid; returns (origin, spacing, dims, mask) of that 3D grid."""
+    g = w2.grid
+    nz = int(w2.nz)
+    dz = (w2.z1 - w2.z0) / nz
+    origin = (g.origin[0], g.origin[1], w2.z0 + 0.5 * dz)
+    spacing = (g.spacing[0], g.spacing[1], dz)
+    dims = (g.dims[0], g.dims[1], nz)
+    mask = np.tile(np.asarray(w2.mask, dtype=np.uint8), nz)
+    return origin, spacing, dims, mask
+
+
+class Oracle2D:
+    """Eq. forward_2D: J2D_ij = sum over the layers of the 3D operator's
+    entries (midpoint rule in z, voxel volume dA dz), i.e. the prism operator
+    applied to dc(x, y) repeated in every layer; its transpose sums the
+    layers."""
+
+    def __init__(self, w2, table_mode=False, n_table=None):
+        origin, spacing, dims, mask = prism(w2)
+        kw = dict(nw=max(auto_nodes(p.samples, p.dt, w2.c0, r)[1]
+                         for p, r in zip(w2.pulses, w2.r_max)))
+        quads = [quad_coeffs(p.samples, p.dt, w2.c0, r_max=r, **kw)
+                 for p, r in zip(w2.pulses, w2.r_max)]
+        tables = None
+        if table_mode:
+            n = n_table or w2.n_table
+            tables = [table(a, b, r, n) for (a, b), r in zip(quads, w2.r_max)]
+        self.o3 = Oracle(w2.c0, w2.tx, w2.pairs, origin, spacing, dims, mask, w2.r_max,
+                         quads=quads, tables=tables)
+        self.quads = quads
+        self.nxy = int(w2.grid.dims[0] * w2.grid.dims[1])
+        self.nz = int(w2.nz)
+        self.M, self.N, self.B = self.o3.M, self.nxy, self.o3.B
+
+    def apply_J(self, x):
+        return self.o3.apply_J(np.tile(np.asarray(x, dtype=np.float64), self.nz))
+
+    def apply_JT(self, y):
+        return self.o3.apply_JT(y).reshape(self.nz, self.nxy).sum(axis=0)
+
+    def block(self, rows=None, cols=None, band=0):
+        cols = np.arange(self.nxy) if cols is None else np.asarray(cols)
+        out = 0.0
+        for k in range(self.nz):
+            out = out + self.o3.block(rows=rows, cols=cols + k * self.nxy, band=band)
+        return out
+
+
+def kernel_z_integral(xs, xr, c0, a, b, r_max, pts2, z0, z1, n_nodes):
+    """int_{z0}^{z1} K0(x, y, z) dz at in-plane points (x, y) by the composite
+    Simpson rule on n_nodes (odd) nodes, K0 from kernel_points."""
+    pts2 = _f64(pts2).reshape(-1, 2)
+    z = np.linspace(z0, z1, n_nodes)
+    wgt = np.ones(n_nodes)
+    wgt[1:-1:2] = 4.0
+    wgt[2:-1:2] = 2.0
+    wgt *= (z[1] - z[0]) / 3.0
+    P = np.concatenate([np.repeat(pts2, n_nodes, axis=0),
+                        np.tile(z, pts2.shape[0])[:, None]], axis=1)
+    K = kernel_points(xs, xr, c0, a, b, r_max, P).reshape(pts2.shape[0], n_nodes)
+    return K @ wgt

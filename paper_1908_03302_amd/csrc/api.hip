@@ -199,6 +199,7 @@ ApplyArgs base_args(const fftt_ctx* c) {
     a.waves_per_block = c->waves_per_block;
     a.n_cu = c->n_cu;
     a.unroll = c->unroll_jt;
+    a.nxy = c->nxy2;
     for (int b = 0; b < c->nb; ++b) {
         a.inv_dr64[b] = (double)(c->ntab - 1) / c->r_max[b];
         a.inv_dr[b] = (float)a.inv_dr64[b];
@@ -445,13 +446,19 @@ fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* 
     ApplyArgs a = base_args(c);
     a.tab = fp64 ? c->d_tab64.p : (prec == FFTT_FP32 ? c->d_tab32.p : c->d_tabbf.p);
     a.w = c->d_w.p;
-    a.out = x;
+    // 2D approximation: the prism's J^T first, then the sum over its layers
+    void* out = x;
+    if (c->nxy2) {
+        FFTT_HIP(c, c->d_z3.alloc((size_t)c->N * es));
+        out = c->d_z3.p;
+    }
+    a.out = out;
     if (op_table(c, prec) == STAB_SERIES && !c->series_ready)
         FFTT_FAIL(c, FFTT_E_STATE, "series evaluation: a band has no sine series");
     FFTT_HIP(c, launch_weights(c->stream, fp64, y, c->d_kptr.as<int32_t>(),
                                c->d_kidx.as<int32_t>(), c->d_C.as<double>(), c->Mk, c->M, c->nb,
                                c->d_w.p));
-    FFTT_HIP(c, launch_fill(c->stream, fp64, x, c->N));
+    FFTT_HIP(c, launch_fill(c->stream, fp64, out, c->N));
     hipEvent_t stop;
     FFTT_HIP(c, prof_begin(c, 1, &stop));
     if (const int q = staged_q(c, prec)) {
@@ -467,11 +474,14 @@ fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* 
         FFTT_HIP(c, launch_apply(c->stream, prec, true, a));
     }
     FFTT_HIP(c, prof_end(c, stop));
+    if (c->nxy2) FFTT_HIP(c, launch_sum_z(c->stream, fp64, out, c->nxy2, c->nz2, x));
     return FFTT_OK;
 }
 
 // out [N] FP32 = coverage (kind 0) or diag(J^T J) (kind 1); ensure_ready done.
 fftt_status coverage_one(fftt_ctx* c, fftt_precision prec, int32_t kind, float* out) {
+    if (c->nxy2)   // abs() and squares do not commute with the sum over the layers
+        FFTT_FAIL(c, FFTT_E_UNSUPPORTED, "coverage / diag(J^T J) of the 2D approximation");
     const int q = staged_q(c, prec);
     if (!q)
         FFTT_FAIL(c, FFTT_E_UNSUPPORTED, "coverage needs the staged kernels (FFTT_TUNE_STAGED, LDS)");
@@ -539,7 +549,7 @@ fftt_status hess_apply(fftt_ctx* c, fftt_precision prec, double isg2, const void
 // first pass goes through T).  Returns r.
 fftt_status orth_block(fftt_ctx* c, bool fp64, void* Y, void* T, int l, double rel_tol,
                        int* r_out) {
-    const int64_t N = c->N;
+    const int64_t N = c->Nm;
     int cols = l;
     for (int pass = 0; pass < 2; ++pass) {
         void* src = pass == 0 ? Y : T;
@@ -713,6 +723,9 @@ fftt_status fftt_set_geometry(fftt_ctx* c, double c0, const double* tx_xyz, int6
     c->n_tx = n_tx;
     c->M = n_pairs;
     c->N = N;
+    c->Nm = N;
+    c->nxy2 = c->nz2 = 0;
+    c->mask2.clear();
     c->tx.assign(tx_xyz, tx_xyz + 3 * n_tx);
     c->pairs_in.assign(pairs, pairs + 2 * n_pairs);
     c->dV = spacing[0] * spacing[1] * spacing[2];
@@ -746,6 +759,38 @@ fftt_status fftt_set_geometry(fftt_ctx* c, double c0, const double* tx_xyz, int6
     st = build_pairs(c);
     if (st != FFTT_OK) return st;
     c->has_geom = true;
+    return FFTT_OK;
+}
+
+fftt_status fftt_set_geometry_2d(fftt_ctx* c, double c0, const double* tx_xyz, int64_t n_tx,
+                                 const int32_t* pairs, int64_t n_pairs, const double origin[2],
+                                 const double spacing[2], const int64_t dims[2], double z0,
+                                 double z1, int64_t nz, const uint8_t* active_mask) {
+    if (!c) return FFTT_E_INVALID;
+    if (!origin || !spacing || !dims) FFTT_BAD(c, "grid origin/spacing/dims missing");
+    if (!std::isfinite(z0) || !std::isfinite(z1) || !(z1 > z0)) FFTT_BAD(c, "need z0 < z1");
+    if (nz < 1 || nz > 4096) FFTT_BAD(c, "need 1 <= nz <= 4096 layers");
+    if (dims[0] < 1 || dims[1] < 1 || dims[0] > (1 << 20) || dims[1] > (1 << 20))
+        FFTT_BAD(c, "grid dims out of range");
+    const int64_t nxy = dims[0] * dims[1];
+    if (nxy * nz > INT32_MAX) FFTT_BAD(c, "prism has more than 2^31 voxels");
+    // midpoint rule over [z0, z1]: layer k at z0 + (k + 1/2) dz
+    const double dz = (z1 - z0) / (double)nz;
+    const double o3[3] = {origin[0], origin[1], z0 + 0.5 * dz};
+    const double s3[3] = {spacing[0], spacing[1], dz};
+    const int64_t d3[3] = {dims[0], dims[1], nz};
+    std::vector<uint8_t> m3;
+    if (active_mask) {
+        m3.resize((size_t)(nxy * nz));
+        for (int64_t k = 0; k < nz; ++k) std::memcpy(m3.data() + k * nxy, active_mask, (size_t)nxy);
+    }
+    fftt_status st = fftt_set_geometry(c, c0, tx_xyz, n_tx, pairs, n_pairs, o3, s3, d3,
+                                       active_mask ? m3.data() : nullptr);
+    if (st != FFTT_OK) return st;
+    c->Nm = c->nxy2 = nxy;
+    c->nz2 = nz;
+    c->mask2.assign((size_t)nxy, 1);
+    if (active_mask) std::memcpy(c->mask2.data(), active_mask, (size_t)nxy);
     return FFTT_OK;
 }
 
@@ -840,7 +885,7 @@ fftt_status fftt_hessian_lowrank(fftt_ctx* c, fftt_precision prec, double noise_
     if (st != FFTT_OK) return st;
     const bool fp64 = prec == FFTT_FP64;
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
-    const int64_t N = c->N, D = (int64_t)c->nb * c->M;
+    const int64_t N = c->Nm, D = (int64_t)c->nb * c->M;
     const double isg2 = 1.0 / (noise_sigma * noise_sigma);
     // rank threshold on the Gram eigenvalues (squared singular values)
     const double tol = fp64 ? 1e-24 : 1e-12;
@@ -926,7 +971,7 @@ fftt_status fftt_lowrank_diag(fftt_ctx* c, fftt_precision prec, const double* ei
     DevBuf dd;
     FFTT_HIP(c, dd.alloc((size_t)k * sizeof(double)));
     FFTT_HIP(c, hipMemcpy(dd.p, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
-    FFTT_HIP(c, launch_lowrank_diag(c->stream, prec == FFTT_FP64, eigvecs, k, c->N,
+    FFTT_HIP(c, launch_lowrank_diag(c->stream, prec == FFTT_FP64, eigvecs, k, c->Nm,
                                     dd.as<double>(), 1.0 / alpha, var_out, res_out));
     // dd is freed on return: the kernel must have read it
     FFTT_HIP(c, hipStreamSynchronize(c->stream));
@@ -957,7 +1002,7 @@ fftt_status fftt_apply_J(fftt_ctx* c, fftt_precision prec, const void* dc, void*
     if (st != FFTT_OK) return st;
     const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
     for (int32_t r = 0; r < n_rhs; ++r) {
-        st = apply_J_one(c, prec, static_cast<const char*>(dc) + (size_t)r * c->N * es,
+        st = apply_J_one(c, prec, static_cast<const char*>(dc) + (size_t)r * c->Nm * es,
                          static_cast<char*>(dT) + (size_t)r * c->nb * c->M * es);
         if (st != FFTT_OK) return st;
     }
@@ -974,7 +1019,7 @@ fftt_status fftt_apply_JT(fftt_ctx* c, fftt_precision prec, const void* dT, void
     const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
     for (int32_t r = 0; r < n_rhs; ++r) {
         st = apply_JT_one(c, prec, static_cast<const char*>(dT) + (size_t)r * c->nb * c->M * es,
-                          static_cast<char*>(dc) + (size_t)r * c->N * es);
+                          static_cast<char*>(dc) + (size_t)r * c->Nm * es);
         if (st != FFTT_OK) return st;
     }
     return FFTT_OK;
@@ -1031,9 +1076,9 @@ fftt_status fftt_autotune(fftt_ctx* c, fftt_precision prec, double max_seconds) 
     const bool fp64 = prec == FFTT_FP64;
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
     DevBuf xb, yb;
-    FFTT_HIP(c, xb.alloc((size_t)c->N * es));
+    FFTT_HIP(c, xb.alloc((size_t)c->Nm * es));
     FFTT_HIP(c, yb.alloc((size_t)c->nb * c->M * es));
-    FFTT_HIP(c, launch_fill_value(c->stream, fp64, xb.p, c->N, 1.0));
+    FFTT_HIP(c, launch_fill_value(c->stream, fp64, xb.p, c->Nm, 1.0));
     FFTT_HIP(c, launch_fill_value(c->stream, fp64, yb.p, (int64_t)c->nb * c->M, 1e-7));
     const bool prof = c->prof;
     c->prof = false;
@@ -1241,7 +1286,7 @@ static fftt_status solve_impl(fftt_ctx* c, const fftt_solve_opts* o, const void*
     const fftt_precision prec = (fftt_precision)o->prec;
     const bool fp64 = prec == FFTT_FP64;
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
-    const int64_t N = c->N, D = (int64_t)c->nb * c->M;
+    const int64_t N = c->Nm, D = (int64_t)c->nb * c->M;
     const double isg = 1.0 / o->noise_sigma, alpha = o->alpha;
     hipStream_t s = c->stream;
     // vectors: data-space r (or u), q; model-space sv, p (or v), w (or the
@@ -1421,25 +1466,26 @@ fftt_status fftt_psf(fftt_ctx* c, fftt_precision prec, const int64_t* voxels, in
     if (!(noise_sigma > 0) || !std::isfinite(noise_sigma)) FFTT_BAD(c, "psf: noise_sigma must be > 0");
     fftt_status st = ensure_ready(c);
     if (st != FFTT_OK) return st;
+    const std::vector<uint8_t>& mk = c->nxy2 ? c->mask2 : c->mask;
     for (int32_t k = 0; k < n; ++k)
-        if (voxels[k] < 0 || voxels[k] >= c->N || !c->mask[voxels[k]])
+        if (voxels[k] < 0 || voxels[k] >= c->Nm || !mk[voxels[k]])
             FFTT_BAD(c, "psf: voxel index out of range or not active");
     const bool fp64 = prec == FFTT_FP64;
     const double s2 = 1.0 / (noise_sigma * noise_sigma);
-    if (!fp64 && c->staged &&
+    if (!fp64 && c->staged && !c->nxy2 &&
         psf_lds_bytes(c->nb, c->ntab, staged_table(c, prec), c->n_tx) <= c->lds_limit)
         return psf_batched(c, prec, voxels, n, s2, static_cast<float*>(out));
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
     const int64_t D = (int64_t)c->nb * c->M;
-    FFTT_HIP(c, c->d_solve.alloc((size_t)(D + c->N) * es));
+    FFTT_HIP(c, c->d_solve.alloc((size_t)(D + c->Nm) * es));
     void* dT = c->d_solve.p;
     void* e = c->d_solve.as<char>() + D * es;
     for (int32_t k = 0; k < n; ++k) {
-        FFTT_HIP(c, solver_unit(c->stream, fp64, e, c->N, voxels[k]));
+        FFTT_HIP(c, solver_unit(c->stream, fp64, e, c->Nm, voxels[k]));
         st = apply_J_one(c, prec, e, dT);
         if (st != FFTT_OK) return st;
         FFTT_HIP(c, solver_lin2(c->stream, fp64, dT, dT, nullptr, D, s2, 0.0));
-        st = apply_JT_one(c, prec, dT, static_cast<char*>(out) + (size_t)k * c->N * es);
+        st = apply_JT_one(c, prec, dT, static_cast<char*>(out) + (size_t)k * c->Nm * es);
         if (st != FFTT_OK) return st;
     }
     return FFTT_OK;

@@ -76,6 +76,7 @@ struct ApplyArgs {
     int unroll;               // entries per inner-loop step (1, 2, 4)
     int split;                // 1: a workgroup shares one tile, its waves split the entries
     int stage_q;              // staged kernels: transducers per staged block (power of 2)
+    int64_t nxy;              // 2D approximation: J reads dc[voxel mod nxy] (0: 3D)
 };
 
 struct DevBuf {
@@ -123,6 +124,9 @@ hipError_t launch_weights(hipStream_t s, bool fp64, const void* dT, const int32_
                           void* w);
 hipError_t launch_fill(hipStream_t s, bool fp64, void* p, int64_t n);
 hipError_t launch_fill_value(hipStream_t s, bool fp64, void* p, int64_t n, double v);
+// out[p] = sum_k in[p + k nxy], k < nz (FP64 sums in layer order)
+hipError_t launch_sum_z(hipStream_t s, bool fp64, const void* in, int64_t nxy, int64_t nz,
+                        void* out);
 hipError_t launch_apply(hipStream_t s, fftt_precision prec, bool transpose,
                         const ApplyArgs& a);
 // Table formats of the staged kernels.
@@ -204,6 +208,10 @@ struct fftt_ctx {
     bool has_geom = false;
     double c0 = 0;
     int64_t n_tx = 0, M = 0, N = 0;
+    // model vectors: N values (3D), or nxy2 in-plane pixels for the 2D
+    // approximation, whose prism of N = nxy2 * nz voxels is the z-quadrature
+    int64_t Nm = 0, nxy2 = 0, nz2 = 0;
+    std::vector<uint8_t> mask2;
     std::vector<double> tx;
     std::vector<int32_t> pairs_in;        // the caller's pairs [M][2]
     // Kernel pairs: caller pairs with identical rows of J form one group
@@ -262,6 +270,7 @@ struct fftt_ctx {
     // work buffers
     fftt::DevBuf d_w, d_part, d_red, d_solve, d_scal, d_diag;
     fftt::DevBuf d_lr, d_lr_part, d_lr_small;   // low-rank analysis: blocks, Gram scratch
+    fftt::DevBuf d_z3;                          // 2D: the prism's J^T before the z sum
     fftt::DevBuf d_psfw, d_psfd;   // batched PSF weights, (tile, lane) of each voxel
 
     // optional event timing of the main kernels (index: 0 J, 1 J^T, 2 reduction)

@@ -419,6 +419,28 @@ hipError_t launch_fill_value(hipStream_t s, bool fp64, void* p, int64_t n, doubl
     return hipGetLastError();
 }
 
+template <class T>
+__global__ void k_sum_z(const T* __restrict__ in, int64_t nxy, int64_t nz, T* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nxy) return;
+    double s = 0.0;
+    for (int64_t k = 0; k < nz; ++k) s += (double)in[p + k * nxy];
+    out[p] = (T)s;
+}
+
+hipError_t launch_sum_z(hipStream_t s, bool fp64, const void* in, int64_t nxy, int64_t nz,
+                        void* out) {
+    if (nxy == 0) return hipSuccess;
+    const unsigned nblk = (unsigned)((nxy + 255) / 256);
+    if (fp64)
+        hipLaunchKernelGGL(k_sum_z<double>, dim3(nblk), dim3(256), 0, s, (const double*)in, nxy,
+                           nz, (double*)out);
+    else
+        hipLaunchKernelGGL(k_sum_z<float>, dim3(nblk), dim3(256), 0, s, (const float*)in, nxy, nz,
+                           (float*)out);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(hipStream_t s, bool fp64, void* p, int64_t n) {
     if (n == 0) return hipSuccess;
     const unsigned nblk = (unsigned)((n + 255) / 256);
@@ -802,7 +824,7 @@ __global__ __launch_bounds__(1024) void k_j32(ApplyArgs A) {
     const LaneVox V = lane_vox(A, a, lane);
     const TxConst* __restrict__ row = A.txc + a * A.n_tx;
     float* __restrict__ part = static_cast<float*>(A.out);
-    const float xv = V.act ? static_cast<const float*>(A.x)[V.vidx] : 0.f;
+    const float xv = V.act ? static_cast<const float*>(A.x)[A.nxy ? V.vidx % A.nxy : V.vidx] : 0.f;
     const float nm1 = (float)(A.ntab - 1);
     float ds = 0.f, rss = 0.f;
     int prev = -1;
@@ -897,7 +919,7 @@ __global__ __launch_bounds__(1024) void k_j64(ApplyArgs A) {
     const LaneVox V = lane_vox(A, a, lane);
     const TxConst* __restrict__ row = A.txc + a * A.n_tx;
     double* __restrict__ part = static_cast<double*>(A.out);
-    const double xv = V.act ? static_cast<const double*>(A.x)[V.vidx] : 0.0;
+    const double xv = V.act ? static_cast<const double*>(A.x)[A.nxy ? V.vidx % A.nxy : V.vidx] : 0.0;
     const double nm1 = (double)(A.ntab - 1);
     double ds = 0.0, Rs = 1.0;
     int prev = -1;
@@ -1298,7 +1320,7 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_j32s(ApplyArgs A) {
         bool inside, act;
         int64_t vidx, v[3];
         voxel_of_lane(A, A.tiles[a], lane, inside, act, vidx, v);
-        xv = act ? static_cast<const float*>(A.x)[vidx] : 0.f;
+        xv = act ? static_cast<const float*>(A.x)[A.nxy ? v[0] + A.g.dims[0] * v[1] : vidx] : 0.f;
     }
     const float nm1 = (float)(A.ntab - 1);
     for_each_block<U>(A, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {

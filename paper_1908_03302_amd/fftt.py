@@ -25,7 +25,8 @@ EXPORTS = ["fftt_create", "fftt_destroy", "fftt_last_error", "fftt_set_stream",
            "fftt_prepare", "fftt_work_count", "fftt_apply_J", "fftt_apply_JT", "fftt_solve",
            "fftt_psf", "fftt_profile", "fftt_kernel_time", "fftt_set_tuning", "fftt_get_tuning",
            "fftt_autotune", "fftt_set_kernel_series", "fftt_build_series_from_pulse",
-           "fftt_coverage", "fftt_hessian_lowrank", "fftt_lowrank_diag"]
+           "fftt_coverage", "fftt_hessian_lowrank", "fftt_lowrank_diag",
+           "fftt_set_geometry_2d"]
 TUNE_WAVES_PER_BLOCK, TUNE_UNROLL_JT, TUNE_UNROLL_J, TUNE_SPLIT_JT, TUNE_SPLIT_J = 0, 1, 2, 3, 4
 TUNE_STAGED, TUNE_UNROLL_JT_STAGED, TUNE_UNROLL_J_STAGED = 5, 6, 7
 TUNE_STAGED_TABLE = 8
@@ -74,6 +75,9 @@ def load():
     L.fftt_set_geometry.argtypes = [vp, C.c_double, dp, i64, C.POINTER(C.c_int32), i64, dp, dp,
                                     C.POINTER(C.c_int64), C.POINTER(C.c_uint8)]
     L.fftt_set_kernel_table.argtypes = [vp, C.c_int32, dp, i64, C.c_double]
+    L.fftt_set_geometry_2d.argtypes = [vp, C.c_double, dp, i64, C.POINTER(C.c_int32), i64, dp,
+                                       dp, C.POINTER(C.c_int64), C.c_double, C.c_double, i64,
+                                       C.POINTER(C.c_uint8)]
     L.fftt_build_table_from_pulse.argtypes = [C.c_double, dp, i64, C.c_double, i64, C.c_double,
                                               dp, dp]
     L.fftt_set_kernel_series.argtypes = [vp, C.c_int32, dp, C.c_int32, C.c_double, C.c_double]
@@ -191,6 +195,26 @@ class Context:
             self.h, float(c0), _dp(tx), tx.shape[0],
             pairs.ctypes.data_as(C.POINTER(C.c_int32)), pairs.shape[0], _dp(o), _dp(s),
             d.ctypes.data_as(C.POINTER(C.c_int64)), mp), "set_geometry")
+        self.M = pairs.shape[0]
+        self.N = int(np.prod(d))
+
+    def set_geometry_2d(self, c0, tx, pairs, origin, spacing, dims, z0, z1, nz, mask=None):
+        """2D approximation: in-plane grid (origin, spacing, dims of length 2),
+        the model constant over [z0, z1], midpoint rule on nz layers."""
+        tx = np.ascontiguousarray(tx, dtype=np.float64).reshape(-1, 3)
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        o = np.ascontiguousarray(origin, dtype=np.float64)
+        s = np.ascontiguousarray(spacing, dtype=np.float64)
+        d = np.ascontiguousarray(dims, dtype=np.int64)
+        mp = C.POINTER(C.c_uint8)()
+        if mask is not None:
+            self._mask = np.ascontiguousarray(mask, dtype=np.uint8)
+            mp = self._mask.ctypes.data_as(C.POINTER(C.c_uint8))
+        self._check(self.L.fftt_set_geometry_2d(
+            self.h, float(c0), _dp(tx), tx.shape[0],
+            pairs.ctypes.data_as(C.POINTER(C.c_int32)), pairs.shape[0], _dp(o), _dp(s),
+            d.ctypes.data_as(C.POINTER(C.c_int64)), float(z0), float(z1), int(nz), mp),
+            "set_geometry_2d")
         self.M = pairs.shape[0]
         self.N = int(np.prod(d))
 
@@ -367,7 +391,12 @@ def context_for_workload(w, device=0, n_table=None, series=False):
     the library's own table builder (and with series=True also each band's
     sine series from the library's series builder)."""
     ctx = Context(device)
-    ctx.set_geometry(w.c0, w.tx, w.pairs, w.grid.origin, w.grid.spacing, w.grid.dims, w.mask)
+    if hasattr(w, "nz"):    # 2D approximation: in-plane grid, z range, layers
+        ctx.set_geometry_2d(w.c0, w.tx, w.pairs, w.grid.origin[:2], w.grid.spacing[:2],
+                            w.grid.dims[:2], w.z0, w.z1, w.nz, w.mask)
+    else:
+        ctx.set_geometry(w.c0, w.tx, w.pairs, w.grid.origin, w.grid.spacing, w.grid.dims,
+                         w.mask)
     n = n_table or w.n_table
     for b, (p, r) in enumerate(zip(w.pulses, w.r_max)):
         h, rm = build_table_from_pulse(w.c0, p.samples, p.dt, n, r)

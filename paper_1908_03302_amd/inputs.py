@@ -270,10 +270,75 @@ def psf512(dims=(256, 256, 64), n_psf=512) -> Workload:
     return w
 
 
+@dataclass
+class Workload2D:
+    """The 2D approximation: an in-plane grid (``grid`` with one layer at
+    z = 0 describes the pixels), the model constant along z over [z0, z1],
+    and nz layers for the z integral."""
+    name: str
+    c0: float
+    tx: np.ndarray
+    pairs: np.ndarray
+    grid: Grid               # in-plane pixels (dims (nx, ny, 1))
+    z0: float
+    z1: float
+    nz: int
+    mask: np.ndarray         # [nx * ny] uint8
+    pulses: list
+    r_max: list
+    n_table: int = 4096
+    model: np.ndarray | None = None   # [nx * ny] m/s
+    noise_sigma: float = 0.0
+    noise_seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return int(self.pairs.shape[0])
+
+    @property
+    def n(self) -> int:
+        return self.grid.n
+
+    @property
+    def n_bands(self) -> int:
+        return len(self.pulses)
+
+
+def small_plane(nz=44) -> Workload2D:
+    """2D approximation of the small ring: 24x24 pixels at 2 mm, z over
+    +-44 mm (the detour of the longest pair stays below R_max = 18.2 mm
+    within |z| < 43.6 mm), 0.5 MHz / 50 % pulse, cylinder phantom."""
+    g = centred_grid((24, 24, 1), 2e-3)
+    return Workload2D(
+        name="ring32_plane24x24_z%d_0.5MHz" % nz, c0=1500.0, tx=ring(32, 0.10),
+        pairs=all_ordered_pairs(32), grid=g, z0=-0.044, z1=0.044, nz=nz,
+        mask=cylinder_mask(g, None), pulses=[sampled_pulse(0.5e6, 0.5)],
+        r_max=[R_MAX_HALF_MHZ_BW50], n_table=4096, model=cylinder_phantom(g, 0.02, 30.0),
+        noise_sigma=5e-9, noise_seed=0, extra=dict(alpha=ALPHA_SMALL))
+
+
+def plane128(nz=60) -> Workload2D:
+    """2D approximation of the lab-like ring: 256x256 pixels at 0.8 mm, z
+    over +-24 mm (the longest chord's detour reaches R_max = 4.77 mm at
+    |z| = 23 mm), 0.8 mm layers, 1 MHz pulse, nested cylinders."""
+    g = centred_grid((256, 256, 1), 0.8e-3)
+    R = 0.11
+    return Workload2D(
+        name="ring128_plane256x256_z%d_1MHz" % nz, c0=1500.0, tx=ring(128, R),
+        pairs=all_ordered_pairs(128), grid=g, z0=-0.024, z1=0.024, nz=nz,
+        mask=cylinder_mask(g, 0.75 * R), pulses=[sampled_pulse(1.0e6, 1.0)],
+        r_max=[R_MAX[1.0e6]], n_table=4096,
+        model=nested_cylinders(g, (0.02, 0.045, 0.07), (15.0, -25.0, 40.0)),
+        noise_sigma=5e-9, noise_seed=3, extra=dict(alpha=ALPHA_RING2D))
+
+
 WORKLOADS = {
     "small_fp64": small_fp64,
     "ring2d": ring2d,
     "slices3d": slices3d,
     "multiband": multiband,
     "psf512": psf512,
+    "small_plane": small_plane,
+    "plane128": plane128,
 }
