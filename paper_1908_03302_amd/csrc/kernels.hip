@@ -1165,10 +1165,17 @@ struct StepWeights {
     float w[U][NB];
 };
 
-// The weights of a step go through the vector memory path: the pair index is
-// copied into a VGPR (identity DPP move), so the loads are counted by vmcnt
-// and their latency overlaps the step's LDS reads instead of adding a second
-// dependent scalar-memory round trip after the entries.
+// The weights of a step go through the vector memory path: the pair's byte
+// offset is copied into a VGPR by one v_mov (written as asm, so the compiler
+// cannot see that the value is wave-uniform and fold the loads back into
+// scalar loads), so the loads are counted by vmcnt and their latency overlaps
+// the step's LDS reads instead of adding a second dependent scalar-memory
+// round trip after the entries.
+__device__ __forceinline__ uint32_t to_vgpr(uint32_t x) {
+    uint32_t v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+    return v;
+}
 template <int NB, int U>
 __device__ __forceinline__ StepWeights<NB, U> load_weights(const ApplyArgs& A,
                                                           const float* __restrict__ w,
@@ -1178,8 +1185,7 @@ __device__ __forceinline__ StepWeights<NB, U> load_weights(const ApplyArgs& A,
     for (int u = 0; u < U; ++u) {
         // 32-bit byte offset, scaled on the scalar side; the band's base stays
         // in scalar registers
-        const uint32_t off =
-            __builtin_amdgcn_update_dpp(0u, (uint32_t)E.p[u] << 2, 0xe4, 0xf, 0xf, false);
+        const uint32_t off = to_vgpr((uint32_t)E.p[u] << 2);
 #pragma unroll
         for (int b = 0; b < NB; ++b)
             W.w[u][b] = *reinterpret_cast<const float*>(
