@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (and FP32 matrix) peak
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 KERNEL_SRC = os.path.join(ROOT, "paper_1908_03302_amd", "csrc", "kernels.hip")
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "ring128_J_JT_hbm_counters.md")
 
@@ -273,14 +274,20 @@ def main():
 
 def psf_leg(ctx, w, fftt, torch, pv, reps=3):
     """512 point-spread functions J^T J e_k / sigma^2 at random active voxels
-    (seed 2) in one batch; FP32 and BF16 table.  Roofline of the batched
-    kernel against the FP32 matrix peak: pv x (23 + 7 + 2 x 512) flops."""
+    (seed 2) in one batch; FP32 and BF16 table.  Algorithmic work pv x (23 +
+    7 + 2 x 512) flops.  The default contraction runs on the BF16 matrix
+    cores with each FP32 product taken as three BF16 products, so its peak
+    for this FP32 work is the dense BF16 peak / 3; the FP32 matrix-core
+    variant is timed beside it against the FP32 peak."""
     from paper_1908_03302_amd import inputs as I
     vox = I.pick_voxels(w.mask, 512, seed=2)
     out = torch.empty(len(vox) * w.n, dtype=torch.float32, device="cuda:0")
     res = {"n_psf": len(vox), "voxels_seed": 2, "noise_sigma": w.noise_sigma}
     fpv = flops_per_pv(1, len(vox))
-    for name, prec in (("fp32", fftt.FP32), ("bf16_table", fftt.FP32_BF16TABLE)):
+    for name, prec, math in (("fp32", fftt.FP32, 0), ("bf16_table", fftt.FP32_BF16TABLE, 0),
+                             ("fp32_fp32_matrix_cores", fftt.FP32, 1)):
+        ctx.set_tuning(psf_math=math)
+        peak = PEAK_BF16_TFLOPS / 3 if math == 0 else PEAK_FP32_TFLOPS
         ctx.psf(vox, w.noise_sigma, out=out, prec=prec)
         torch.cuda.synchronize()
         ctx.profile(True)
@@ -295,11 +302,12 @@ def psf_leg(ctx, w, fftt, torch, pv, reps=3):
         tf = pv * fpv / (kms * 1e-3) / 1e12
         res[name] = {"ms": wall, "kernel_ms": kms, "psf_per_s": len(vox) / (wall * 1e-3),
                      "pv_rhs_per_s": pv * len(vox) / (wall * 1e-3),
-                     "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_FP32_TFLOPS,
-                                  "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS,
-                                  "flops_per_pv": fpv}}
+                     "roofline": {"bound": "mfma", "achieved": tf, "peak": peak,
+                                  "unit": "TFLOP/s", "frac": tf / peak, "flops_per_pv": fpv,
+                                  "matrix_math": "bf16 x3 split" if math == 0 else "fp32"}}
         log("bench: 512 PSFs %s: %.1f ms (kernels %.1f ms), %.1f TFLOP/s"
             % (name, wall, kms, tf))
+    ctx.set_tuning(psf_math=0)
     del out
     return res
 

@@ -300,6 +300,10 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *     upper bound on Q (a power of two >= 16).
  *   FFTT_TUNE_KERNEL_EVAL: 0 (default) = the FP32 operators interpolate
  *     the table, 1 = they sum the bands' sine series (fftt_set_kernel_series).
+ *   FFTT_TUNE_PSF_MATH: contraction of the batched FP32 / BF16-table PSFs:
+ *     0 (default) = BF16 matrix cores with every FP32 operand split in two
+ *     BF16 parts and three products (hi hi + hi lo + lo hi, FP32
+ *     accumulation; 1 to 3 bands, 4 bands use FP32), 1 = FP32 matrix cores.
  *   FFTT_TUNE_RECIPROCITY: 1 (default) = a pair (s, r) and its reverse
  *     (r, s) have the same row of J (source-receiver reciprocity, Sec. II-B;
  *     the detour and L are symmetric), so each unordered pair is evaluated
@@ -311,7 +315,7 @@ enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_
        FFTT_TUNE_SPLIT_JT = 3, FFTT_TUNE_SPLIT_J = 4, FFTT_TUNE_STAGED = 5,
        FFTT_TUNE_UNROLL_JT_STAGED = 6, FFTT_TUNE_UNROLL_J_STAGED = 7,
        FFTT_TUNE_STAGED_TABLE = 8, FFTT_TUNE_RECIPROCITY = 9,
-       FFTT_TUNE_STAGED_BLOCK = 10, FFTT_TUNE_KERNEL_EVAL = 11 };
+       FFTT_TUNE_STAGED_BLOCK = 10, FFTT_TUNE_KERNEL_EVAL = 11, FFTT_TUNE_PSF_MATH = 12 };
 fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
 
 /* Current value of a tuning key (FFTT_E_INVALID for an unknown key). */

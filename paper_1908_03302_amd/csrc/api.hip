@@ -392,7 +392,7 @@ fftt_status psf_batched(fftt_ctx* c, fftt_precision prec, const int64_t* voxels,
     FFTT_HIP(c, launch_psf(c->stream, fmt, a, c->d_psfd.as<int32_t>(),
                            c->d_psfd.as<int32_t>() + n, c->d_C.as<double>(),
                            c->d_kptr.as<int32_t>(), s2,
-                           c->d_psfw.as<float>(), ldw, n, out, col_tab));
+                           c->d_psfw.as<float>(), ldw, n, out, col_tab, c->psf_fp32_math == 0));
     FFTT_HIP(c, prof_end(c, stop));
     // the host descriptor buffer must outlive the asynchronous copy
     FFTT_HIP(c, hipStreamSynchronize(c->stream));
@@ -1040,6 +1040,7 @@ fftt_status fftt_get_tuning(fftt_ctx* c, int32_t key, int32_t* value) {
         case FFTT_TUNE_RECIPROCITY: *value = c->reciprocity; return FFTT_OK;
         case FFTT_TUNE_STAGED_BLOCK: *value = c->staged_block_max; return FFTT_OK;
         case FFTT_TUNE_KERNEL_EVAL: *value = c->eval_series; return FFTT_OK;
+        case FFTT_TUNE_PSF_MATH: *value = c->psf_fp32_math; return FFTT_OK;
     }
     FFTT_BAD(c, "unknown tuning key");
 }
@@ -1207,6 +1208,10 @@ fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
         case FFTT_TUNE_KERNEL_EVAL:
             if (value != 0 && value != 1) FFTT_BAD(c, "kernel evaluation must be 0 or 1");
             c->eval_series = value;
+            return FFTT_OK;
+        case FFTT_TUNE_PSF_MATH:
+            if (value != 0 && value != 1) FFTT_BAD(c, "PSF math must be 0 or 1");
+            c->psf_fp32_math = value;
             return FFTT_OK;
         case FFTT_TUNE_SPLIT_JT:
         case FFTT_TUNE_SPLIT_J:
@@ -1473,7 +1478,8 @@ fftt_status fftt_psf(fftt_ctx* c, fftt_precision prec, const int64_t* voxels, in
     const bool fp64 = prec == FFTT_FP64;
     const double s2 = 1.0 / (noise_sigma * noise_sigma);
     if (!fp64 && c->staged && !c->nxy2 &&
-        psf_lds_bytes(c->nb, c->ntab, staged_table(c, prec), c->n_tx) <= c->lds_limit)
+        psf_lds_bytes(c->nb, c->ntab, staged_table(c, prec), c->n_tx, c->psf_fp32_math == 0) <=
+            c->lds_limit)
         return psf_batched(c, prec, voxels, n, s2, static_cast<float*>(out));
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
     const int64_t D = (int64_t)c->nb * c->M;

@@ -148,10 +148,12 @@ size_t staged_lds_bytes(int nb, int ntab, int tabfmt, int64_t q, int wpb);
 // Batched point-spread functions: W ([nb][M][ldw], zeroed) and out ([n][N],
 // zeroed) are filled for the n voxels given by (active tile, lane) pairs;
 // col_tab is the FP32 (h, slope) table used for the weights.
+// b3: contraction on BF16 matrix cores with three-way split operands (1 to
+// 3 bands), else FP32 matrix cores.
 hipError_t launch_psf(hipStream_t s, int tabfmt, const ApplyArgs& a, const int32_t* ptile,
                       const int32_t* plane, const double* C, const int32_t* kptr, double s2,
-                      float* W, int64_t ldw, int n, float* out, const void* col_tab);
-size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx);
+                      float* W, int64_t ldw, int n, float* out, const void* col_tab, bool b3);
+size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, bool b3);
 // J per-pair sum: S slices per 64-pair group (reduce_slices), FP64 scratch
 // red [nb][S][Mk], then the rows of every caller pair of a group.
 int reduce_slices(int64_t Mk, int n_cu);
@@ -265,6 +267,7 @@ struct fftt_ctx {
     int unroll_jts = 8, unroll_js = 8;
     int staged_pair_table = 0; // FP32 staged kernels: 0 node table, 1 (h, slope) pairs
     int staged_block_max = 0;  // cap on the staged block size (0: LDS decides)
+    int psf_fp32_math = 0;     // batched PSFs: 0 split-BF16 matrix cores (1-3 bands), 1 FP32
     size_t lds_limit = 65536;
 
     // work buffers

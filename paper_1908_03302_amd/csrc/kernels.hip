@@ -1857,7 +1857,168 @@ __global__ __launch_bounds__(1024) void k_psf32(ApplyArgs A, const float* __rest
     }
 }
 
-size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
+// ---- the same contraction with BF16 matrix-core steps, split three ways
+//
+// Every FP32 operand x is split as x ~ hi + lo, hi = bf16(x), lo = bf16(x -
+// hi) (relative error ~2^-17), and each product is taken as hi*hi + hi*lo +
+// lo*hi (the dropped lo*lo is ~2^-16 relative) on v_mfma_f32_32x32x16_bf16
+// with FP32 accumulation: three BF16 steps per K = 16 block instead of eight
+// FP32 K = 2 steps.  Norm-wise error ~3e-6 on PSF operands.  H is split once,
+// when it is produced (all wavefronts reuse it), and kept voxel-major in LDS
+// as [voxel][entry] BF16 rows of CH + 8 (16-byte aligned, conflict-free
+// 16-byte reads of a lane's 8 K-values); W is split in registers.  Operand
+// layout (32x32x16): A[m][k] in lane m + 32 (k / 8), element k % 8; B[k][n]
+// in lane n + 32 (k / 8), element k % 8.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+
+constexpr int psfb3_chunk(int nb) { return nb == 1 ? 64 : (nb == 2 ? 32 : 16); }
+
+__device__ __forceinline__ uint32_t bf16_bits(__bf16 h) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+
+// H of entries c0 .. c0 + CH - 1 split into hi / lo BF16 rows; waves take
+// pairs of entries, each lane (voxel) writes one packed dword per pair.
+template <int NB, int CH, class TabT>
+__device__ __forceinline__ void psfb3_chunk_h(const ApplyArgs& A, const TabT* st, const float2* sx,
+                                              uint32_t* hh, uint32_t* hl, int* pb, int64_t c0,
+                                              int64_t t0, int64_t t1, float nm1, int wave,
+                                              int W_, int lane) {
+    constexpr int RS = (CH + 8) / 2;   // row stride in dwords
+    for (int i2 = wave; i2 < CH / 2; i2 += W_) {
+        const int64_t e0 = c0 + 2 * i2, e1 = e0 + 1;
+        const bool ok0 = e0 < t1, ok1 = e1 < t1;
+        const Entry E0 = A.ents[ok0 ? e0 : t0], E1 = A.ents[ok1 ? e1 : t0];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float h0 = ok0 ? psf_h(A, st, sx, E0, b, nm1, lane) : 0.0f;
+            const float h1 = ok1 ? psf_h(A, st, sx, E1, b, nm1, lane) : 0.0f;
+            const __bf16 a0 = (__bf16)h0, a1 = (__bf16)h1;
+            const __bf16 l0 = (__bf16)(h0 - (float)a0), l1 = (__bf16)(h1 - (float)a1);
+            const int o = (b * 64 + lane) * RS + i2;
+            hh[o] = bf16_bits(a0) | (bf16_bits(a1) << 16);
+            hl[o] = bf16_bits(l0) | (bf16_bits(l1) << 16);
+        }
+        if (lane == 0) {
+            pb[2 * i2] = ok0 ? E0.p : -1;
+            pb[2 * i2 + 1] = ok1 ? E1.p : -1;
+        }
+    }
+}
+
+template <int NB, class TabT>
+__global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __restrict__ W,
+                                                int64_t ldw, int n, float* __restrict__ out) {
+    constexpr int CH = psfb3_chunk(NB);
+    constexpr int RS = (CH + 8) / 2;          // dwords per voxel row
+    constexpr int HB = NB * 64 * RS;          // dwords of one hi (or lo) buffer
+    const TabT* st = stage_table<TabT>(A, NB);
+    float2* sx = staged_tx<TabT>(A, NB);
+    // after the staged distances: two buffer sets {hi, lo, index}
+    uint32_t* hbuf = reinterpret_cast<uint32_t*>(sx + A.n_tx * 64);
+    int* pbuf = reinterpret_cast<int*>(hbuf + 4 * HB);
+    const int64_t a = xcd_tile(blockIdx.x);
+    if (a >= A.n_act) return;
+    const int lane = threadIdx.x & 63;
+    const LaneVox V = lane_vox(A, a, lane);
+    stage_distances(A, a, V, sx, lane, 0, (int)A.n_tx);   // one block: all transducers
+    const int W_ = (int)(blockDim.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int k0 = ((int)blockIdx.y * W_ + wave) * 32;
+    const bool active = k0 < n;   // wave-uniform; idle waves still help with H
+    const float nm1 = (float)(A.ntab - 1);
+    const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
+    const int col = lane & 31;
+    const int up = lane >> 5;
+    f32x16v c_lo = {}, c_hi = {};
+    if (t0 < t1)
+        psfb3_chunk_h<NB, CH>(A, st, sx, hbuf, hbuf + HB, pbuf, t0, t0, t1, nm1, wave, W_, lane);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t c0 = t0; c0 < t1; c0 += CH, buf ^= 1) {
+        const uint32_t* hh = hbuf + buf * 2 * HB;
+        const uint32_t* hl = hh + HB;
+        const int* pb = pbuf + buf * CH;
+        // this chunk's weights, split (requested first), the next chunk's H,
+        // then the matrix-core steps
+        bf16x8 wh[NB][CH / 16], wl[NB][CH / 16];
+        if (active) {
+            float wv[NB][CH / 16][8];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int s = 0; s < CH / 16; ++s)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        // unconditional load (row 0 for padding), selected after
+                        const int p = pb[16 * s + 8 * up + i];
+                        const float v = W[((int64_t)b * A.M + max(p, 0)) * ldw + k0 + col];
+                        wv[b][s][i] = p >= 0 ? v : 0.0f;
+                    }
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int s = 0; s < CH / 16; ++s)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const __bf16 x = (__bf16)wv[b][s][i];
+                        wh[b][s][i] = x;
+                        wl[b][s][i] = (__bf16)(wv[b][s][i] - (float)x);
+                    }
+        }
+        if (c0 + CH < t1)
+            psfb3_chunk_h<NB, CH>(A, st, sx, hbuf + (buf ^ 1) * 2 * HB,
+                                  hbuf + (buf ^ 1) * 2 * HB + HB, pbuf + (buf ^ 1) * CH, c0 + CH,
+                                  t0, t1, nm1, wave, W_, lane);
+        if (active) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int s = 0; s < CH / 16; ++s) {
+                    // lane: voxel col (+ 32 for the upper block), K-values
+                    // 16 s + 8 up .. + 7 (4 dwords)
+                    const int o = (b * 64 + col) * RS + 8 * s + 4 * up;
+                    const bf16x8 al = *reinterpret_cast<const bf16x8*>(hh + o);
+                    const bf16x8 ah = *reinterpret_cast<const bf16x8*>(hh + o + 32 * RS);
+                    const bf16x8 bl = *reinterpret_cast<const bf16x8*>(hl + o);
+                    const bf16x8 bh = *reinterpret_cast<const bf16x8*>(hl + o + 32 * RS);
+                    c_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, wh[b][s], c_lo, 0, 0, 0);
+                    c_hi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, wh[b][s], c_hi, 0, 0, 0);
+                    c_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, wl[b][s], c_lo, 0, 0, 0);
+                    c_hi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, wl[b][s], c_hi, 0, 0, 0);
+                    c_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl, wh[b][s], c_lo, 0, 0, 0);
+                    c_hi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh, wh[b][s], c_hi, 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    if (!active || k0 + col >= n) return;
+    float* __restrict__ o = out + (int64_t)(k0 + col) * A.g.dims[0] * A.g.dims[1] * A.g.dims[2];
+    const int64_t t = A.tiles[a];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = 8 * (q / 4) + 4 * up + (q & 3);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bool inside, act;
+            int64_t vidx, v[3];
+            voxel_of_lane(A, t, i + 32 * h, inside, act, vidx, v);
+            if (inside) o[vidx] = act ? (h ? c_hi[q] : c_lo[q]) : 0.0f;
+        }
+    }
+}
+
+size_t psfb3_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
+    const size_t tbytes = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
+    const int ch = psfb3_chunk(nb);
+    return ((tbytes + 15) & ~(size_t)15) + (size_t)n_tx * 64 * sizeof(float2) +
+           2 * (2 * (size_t)nb * 64 * ((ch + 8) / 2) * sizeof(uint32_t) + (size_t)ch * sizeof(int));
+}
+
+size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, bool b3) {
+    if (b3 && nb <= 3) return psfb3_lds_bytes(nb, ntab, tabfmt, n_tx);
     const size_t tbytes = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
     const int ch = nb == 1 ? psf_chunk<1>()
                  : (nb == 2 ? psf_chunk<2>() : (nb == 3 ? psf_chunk<3>() : psf_chunk<4>()));
@@ -1869,7 +2030,7 @@ template <int NB>
 static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
                                 const int32_t* ptile, const int32_t* plane, const double* C,
                                 const int32_t* kptr, double s2, float* W, int64_t ldw, int n,
-                                float* out, const void* col_tab) {
+                                float* out, const void* col_tab, bool b3) {
     // the weights (J e_k, cheap) always use the FP32 (h, slope) table, so a
     // BF16 table only enters through the contraction
     ApplyArgs ac = a;
@@ -1880,7 +2041,7 @@ static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
     if (err != hipSuccess || a.n_act == 0) return err;
     const int wpb = a.waves_per_block;
     const unsigned nbat = (unsigned)((n + 32 * wpb - 1) / (32 * wpb));
-    const size_t lds = psf_lds_bytes(NB, a.ntab, tabfmt, a.n_tx);
+    const size_t lds = psf_lds_bytes(NB, a.ntab, tabfmt, a.n_tx, b3);
     auto run = [&](auto kern) -> hipError_t {
         if (lds > 65536) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -1892,6 +2053,16 @@ static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
         hipLaunchKernelGGL(kern, dim3(grid, nbat), dim3(64 * wpb), lds, s, a, W, ldw, n, out);
         return hipGetLastError();
     };
+    if constexpr (NB <= 3) {
+        if (b3) {
+            switch (tabfmt) {
+                case STAB_NODE32: return run(k_psfb3<NB, float>);
+                case STAB_PAIR32: return run(k_psfb3<NB, float2>);
+                case STAB_BF16: return run(k_psfb3<NB, uint32_t>);
+            }
+            return hipErrorInvalidValue;
+        }
+    }
     switch (tabfmt) {
         case STAB_NODE32: return run(k_psf32<NB, float>);
         case STAB_PAIR32: return run(k_psf32<NB, float2>);
@@ -1902,16 +2073,16 @@ static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
 
 hipError_t launch_psf(hipStream_t s, int tabfmt, const ApplyArgs& a, const int32_t* ptile,
                       const int32_t* plane, const double* C, const int32_t* kptr, double s2,
-                      float* W, int64_t ldw, int n, float* out, const void* col_tab) {
+                      float* W, int64_t ldw, int n, float* out, const void* col_tab, bool b3) {
     switch (a.nb) {
         case 1: return launch_psf_nb<1>(s, tabfmt, a, ptile, plane, C, kptr, s2, W, ldw, n, out,
-                                        col_tab);
+                                        col_tab, b3);
         case 2: return launch_psf_nb<2>(s, tabfmt, a, ptile, plane, C, kptr, s2, W, ldw, n, out,
-                                        col_tab);
+                                        col_tab, b3);
         case 3: return launch_psf_nb<3>(s, tabfmt, a, ptile, plane, C, kptr, s2, W, ldw, n, out,
-                                        col_tab);
+                                        col_tab, b3);
         case 4: return launch_psf_nb<4>(s, tabfmt, a, ptile, plane, C, kptr, s2, W, ldw, n, out,
-                                        col_tab);
+                                        col_tab, b3);
     }
     return hipErrorInvalidValue;
 }

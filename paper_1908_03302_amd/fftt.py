@@ -33,6 +33,7 @@ TUNE_STAGED_TABLE = 8
 TUNE_RECIPROCITY = 9
 TUNE_STAGED_BLOCK = 10
 TUNE_KERNEL_EVAL = 11
+TUNE_PSF_MATH = 12
 
 
 class SolveOpts(C.Structure):
@@ -243,7 +244,8 @@ class Context:
 
     def set_tuning(self, waves_per_block=None, unroll_jt=None, unroll_j=None, split_jt=None,
                    split_j=None, staged=None, unroll_jt_staged=None, unroll_j_staged=None,
-                   staged_table=None, reciprocity=None, staged_block=None, kernel_eval=None):
+                   staged_table=None, reciprocity=None, staged_block=None, kernel_eval=None,
+                   psf_math=None):
         for key, v in ((TUNE_WAVES_PER_BLOCK, waves_per_block), (TUNE_UNROLL_JT, unroll_jt),
                        (TUNE_UNROLL_J, unroll_j), (TUNE_SPLIT_JT, split_jt),
                        (TUNE_SPLIT_J, split_j), (TUNE_STAGED, staged),
@@ -251,7 +253,8 @@ class Context:
                        (TUNE_UNROLL_J_STAGED, unroll_j_staged),
                        (TUNE_STAGED_TABLE, staged_table),
                        (TUNE_RECIPROCITY, reciprocity),
-                       (TUNE_STAGED_BLOCK, staged_block), (TUNE_KERNEL_EVAL, kernel_eval)):
+                       (TUNE_STAGED_BLOCK, staged_block), (TUNE_KERNEL_EVAL, kernel_eval),
+                       (TUNE_PSF_MATH, psf_math)):
             if v is not None:
                 self._check(self.L.fftt_set_tuning(self.h, key, int(v)), "set_tuning")
 
@@ -260,7 +263,7 @@ class Context:
                    "staged": TUNE_STAGED, "unroll_jt_staged": TUNE_UNROLL_JT_STAGED,
                    "unroll_j_staged": TUNE_UNROLL_J_STAGED, "staged_table": TUNE_STAGED_TABLE,
                    "reciprocity": TUNE_RECIPROCITY, "staged_block": TUNE_STAGED_BLOCK,
-                   "kernel_eval": TUNE_KERNEL_EVAL}
+                   "kernel_eval": TUNE_KERNEL_EVAL, "psf_math": TUNE_PSF_MATH}
 
     def get_tuning(self):
         """All tuning keys and their current values."""

@@ -173,3 +173,23 @@ def test_psf_batch_512_ring2d_sampled(ring2d, prec_name):
                       np.arange(1, sel.size), TOL[prec_name])
         say("ring2d PSF", k, "voxel", v, prec_name,
             "rel err vs table oracle %.2e, vs quadrature %.2e (table's own %.2e)" % e)
+
+
+@pytest.mark.parametrize("prec_name", ["FP32", "FP32_BF16TABLE"])
+def test_psf_split_bf16_matches_fp32_matrix_cores(ragged_dense, prec_name):
+    """The contraction on BF16 matrix cores with three-way split operands
+    (default) against the FP32 matrix-core contraction: same PSFs within
+    the split's rounding (~3e-6 norm-wise)."""
+    w, _, ctx = ragged_dense
+    f = _fftt()
+    prec = getattr(f, prec_name)
+    vox = np.random.default_rng(6).choice(np.flatnonzero(w.mask), 40, replace=False)
+    a = host(ctx.psf(vox, SIGMA, prec=prec)).reshape(len(vox), w.n)
+    ctx.set_tuning(psf_math=1)
+    try:
+        b = host(ctx.psf(vox, SIGMA, prec=prec)).reshape(len(vox), w.n)
+    finally:
+        ctx.set_tuning(psf_math=0)
+    e = max(rel(a[k], b[k]) for k in range(len(vox)))
+    say("split BF16 vs FP32 matrix cores", prec_name, "worst rel %.2e" % e)
+    assert e < 1e-5
