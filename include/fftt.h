@@ -252,6 +252,17 @@ fftt_status fftt_hessian_lowrank(fftt_ctx *ctx, fftt_precision prec, double nois
                                  const void *omega, int32_t l, int32_t q, int32_t k,
                                  double *eigvals, void *eigvecs, int32_t *rank_out);
 
+/* Gauss-Newton Hessian of the misfit applied to n_vec model vectors:
+ * y_k = J^T J x_k / sigma^2 (bands summed; eq. resolution_2's H_misfit).
+ * x, y: device [n_vec][N] in the precision's type.  FP32 / BF16-table
+ * operators with 1 to 3 bands in 3D run as one batch (FFTT_TUNE_HESS_BATCHED):
+ * per tile the products with all vectors are contractions on the BF16 matrix
+ * cores, every FP32 operand split in two BF16 parts (hi hi + hi lo + lo hi,
+ * FP32 accumulation; ~1e-6 relative against the one-vector path), partials
+ * summed per pair in FP64 in a fixed order.  Asynchronous. */
+fftt_status fftt_hessian_apply(fftt_ctx *ctx, fftt_precision prec, double noise_sigma,
+                               const void *x, int32_t n_vec, void *y);
+
 /* Diagonals of the low-rank posterior covariance and resolution matrix
  * (eq. posterior_app / resolution_app with Gamma_pr = I) from k eigenpairs
  * of H:  d_i = lambda_i / (lambda_i + alpha),
@@ -304,6 +315,11 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *     0 (default) = BF16 matrix cores with every FP32 operand split in two
  *     BF16 parts and three products (hi hi + hi lo + lo hi, FP32
  *     accumulation; 1 to 3 bands, 4 bands use FP32), 1 = FP32 matrix cores.
+ *   FFTT_TUNE_HESS_BATCHED: 1 (default) = products of the Gauss-Newton
+ *     Hessian with blocks of vectors (fftt_hessian_apply, the low-rank
+ *     eigensolver) run batched on the matrix cores where they can (FP32 /
+ *     BF16-table operators with table evaluation, 1 to 3 bands, 3D, LDS),
+ *     0 = one J and one J^T per vector.
  *   FFTT_TUNE_RECIPROCITY: 1 (default) = a pair (s, r) and its reverse
  *     (r, s) have the same row of J (source-receiver reciprocity, Sec. II-B;
  *     the detour and L are symmetric), so each unordered pair is evaluated
@@ -315,7 +331,8 @@ enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_
        FFTT_TUNE_SPLIT_JT = 3, FFTT_TUNE_SPLIT_J = 4, FFTT_TUNE_STAGED = 5,
        FFTT_TUNE_UNROLL_JT_STAGED = 6, FFTT_TUNE_UNROLL_J_STAGED = 7,
        FFTT_TUNE_STAGED_TABLE = 8, FFTT_TUNE_RECIPROCITY = 9,
-       FFTT_TUNE_STAGED_BLOCK = 10, FFTT_TUNE_KERNEL_EVAL = 11, FFTT_TUNE_PSF_MATH = 12 };
+       FFTT_TUNE_STAGED_BLOCK = 10, FFTT_TUNE_KERNEL_EVAL = 11, FFTT_TUNE_PSF_MATH = 12,
+       FFTT_TUNE_HESS_BATCHED = 13 };
 fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
 
 /* Current value of a tuning key (FFTT_E_INVALID for an unknown key). */

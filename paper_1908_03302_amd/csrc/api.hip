@@ -543,6 +543,56 @@ fftt_status hess_apply(fftt_ctx* c, fftt_precision prec, double isg2, const void
     return apply_JT_one(c, prec, dT, y);
 }
 
+// Y [r][Nm] = H X for r vectors: batched on the matrix cores (split BF16)
+// for FP32 / BF16-table operators with 1 to 3 bands in 3D when the staged
+// layouts fit LDS, in column batches whose partials stay below 8 GB; one
+// vector at a time otherwise.
+fftt_status hess_block(fftt_ctx* c, fftt_precision prec, double isg2, const void* X, void* Y,
+                       int r, void* dT) {
+    const bool fp64 = prec == FFTT_FP64;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    const int64_t N = c->Nm;
+    const int fmt = staged_table(c, prec);
+    const double budget = 8e9;
+    int cb = 0;
+    if (c->hess_batched && !fp64 && c->nb <= 3 && !c->nxy2 && c->staged &&
+        op_table(c, prec) != STAB_SERIES &&
+        jmb3_lds_bytes(c->nb, c->ntab, fmt, c->n_tx) <= c->lds_limit &&
+        psf_lds_bytes(c->nb, c->ntab, fmt, c->n_tx, true) <= c->lds_limit && c->nnz > 0) {
+        const double per_col = (double)c->nb * (double)c->nnz * sizeof(float);
+        cb = (int)std::min<double>(r, std::floor(budget / per_col));
+        if (cb < std::min(r, 32)) cb = 0;
+    }
+    if (cb == 0) {
+        for (int i = 0; i < r; ++i) {
+            fftt_status st = hess_apply(c, prec, isg2, static_cast<const char*>(X) + (size_t)i * N * es,
+                                        dT, static_cast<char*>(Y) + (size_t)i * N * es);
+            if (st != FFTT_OK) return st;
+        }
+        return FFTT_OK;
+    }
+    const int S = reduce_slices(c->Mk, c->n_cu);
+    ApplyArgs a = base_args(c);
+    a.tab = staged_table_ptr(c, fmt);
+    a.stage_q = (int)c->n_tx;
+    for (int c0 = 0; c0 < r; c0 += cb) {
+        const int n = std::min(cb, r - c0);
+        const int64_t ldw = ((int64_t)n + 31) / 32 * 32;
+        FFTT_HIP(c, c->d_hb_part.alloc((size_t)c->nb * c->nnz * n * sizeof(float)));
+        FFTT_HIP(c, c->d_hb_red.alloc((size_t)c->nb * S * c->Mk * n * sizeof(double)));
+        FFTT_HIP(c, c->d_hb_w.alloc((size_t)c->nb * c->Mk * ldw * sizeof(float)));
+        FFTT_HIP(c, launch_fill(c->stream, false, c->d_hb_w.p, (int64_t)c->nb * c->Mk * ldw));
+        float* out = static_cast<float*>(Y) + (size_t)c0 * N;
+        FFTT_HIP(c, launch_fill(c->stream, false, out, (int64_t)n * N));
+        FFTT_HIP(c, launch_hess_block(c->stream, fmt, a, static_cast<const float*>(X) + (size_t)c0 * N,
+                                      N, n, c->d_hb_part.as<float>(), c->d_gptr.as<int64_t>(),
+                                      c->d_desc.p, S, c->d_hb_red.as<double>(),
+                                      c->d_C.as<double>(), c->d_kptr.as<int32_t>(), isg2,
+                                      c->d_hb_w.as<float>(), ldw, out));
+    }
+    return FFTT_OK;
+}
+
 // Orthonormal basis of the columns of Y ([l][N]) by the eigen-decomposition
 // of the FP64 Gram matrix (G = U S U^T, Q = Y U_r S_r^-1/2 over the r
 // eigenvalues above rel_tol S_max), done twice; the basis overwrites Y (the
@@ -894,23 +944,16 @@ fftt_status fftt_hessian_lowrank(fftt_ctx* c, fftt_precision prec, double noise_
     char* A = c->d_lr.as<char>();
     char* B = A + (size_t)l * N * es;
     void* dT = c->d_solve.p;
-    auto col = [&](const void* base, int i) {
-        return static_cast<const char*>(base) + (size_t)i * N * es;
-    };
     // A = H Omega, orthonormalised
-    for (int i = 0; i < l; ++i) {
-        st = hess_apply(c, prec, isg2, col(omega, i), dT, A + (size_t)i * N * es);
-        if (st != FFTT_OK) return st;
-    }
+    st = hess_block(c, prec, isg2, omega, A, l, dT);
+    if (st != FFTT_OK) return st;
     int r = 0;
     st = orth_block(c, fp64, A, B, l, tol, &r);
     if (st != FFTT_OK) return st;
     // subspace iterations: A = orth(H A)
     for (int it = 0; it < q && r > 0; ++it) {
-        for (int i = 0; i < r; ++i) {
-            st = hess_apply(c, prec, isg2, col(A, i), dT, B + (size_t)i * N * es);
-            if (st != FFTT_OK) return st;
-        }
+        st = hess_block(c, prec, isg2, A, B, r, dT);
+        if (st != FFTT_OK) return st;
         std::swap(A, B);
         st = orth_block(c, fp64, A, B, r, tol, &r);
         if (st != FFTT_OK) return st;
@@ -920,10 +963,8 @@ fftt_status fftt_hessian_lowrank(fftt_ctx* c, fftt_precision prec, double noise_
     FFTT_HIP(c, launch_fill(c->stream, fp64, eigvecs, (int64_t)k * N));
     if (r > 0) {
         // Rayleigh-Ritz: T = Q^T H Q, T = U Theta U^T, Ritz vectors Q U
-        for (int i = 0; i < r; ++i) {
-            st = hess_apply(c, prec, isg2, col(A, i), dT, B + (size_t)i * N * es);
-            if (st != FFTT_OK) return st;
-        }
+        st = hess_block(c, prec, isg2, A, B, r, dT);
+        if (st != FFTT_OK) return st;
         FFTT_HIP(c, c->d_lr_part.alloc(gram_part_doubles(r, r, N) * sizeof(double)));
         FFTT_HIP(c, c->d_lr_small.alloc((size_t)r * r * sizeof(double)));
         FFTT_HIP(c, launch_gram(c->stream, fp64, A, r, B, r, N, c->d_lr_part.as<double>(),
@@ -950,6 +991,20 @@ fftt_status fftt_hessian_lowrank(fftt_ctx* c, fftt_precision prec, double noise_
     FFTT_HIP(c, hipStreamSynchronize(c->stream));
     std::copy(evals.begin(), evals.end(), eigvals);
     return FFTT_OK;
+}
+
+fftt_status fftt_hessian_apply(fftt_ctx* c, fftt_precision prec, double noise_sigma,
+                               const void* x, int32_t n_vec, void* y) {
+    if (!c) return FFTT_E_INVALID;
+    if (prec < FFTT_FP64 || prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "hessian_apply: unknown precision");
+    if (!x || !y || n_vec < 1) FFTT_BAD(c, "hessian_apply: null buffer or n_vec < 1");
+    if (!(noise_sigma > 0) || !std::isfinite(noise_sigma))
+        FFTT_BAD(c, "hessian_apply: noise_sigma must be > 0");
+    fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
+    FFTT_HIP(c, c->d_solve.alloc((size_t)c->nb * c->M * es));
+    return hess_block(c, prec, 1.0 / (noise_sigma * noise_sigma), x, y, n_vec, c->d_solve.p);
 }
 
 fftt_status fftt_lowrank_diag(fftt_ctx* c, fftt_precision prec, const double* eigvals,
@@ -1041,6 +1096,7 @@ fftt_status fftt_get_tuning(fftt_ctx* c, int32_t key, int32_t* value) {
         case FFTT_TUNE_STAGED_BLOCK: *value = c->staged_block_max; return FFTT_OK;
         case FFTT_TUNE_KERNEL_EVAL: *value = c->eval_series; return FFTT_OK;
         case FFTT_TUNE_PSF_MATH: *value = c->psf_fp32_math; return FFTT_OK;
+        case FFTT_TUNE_HESS_BATCHED: *value = c->hess_batched; return FFTT_OK;
     }
     FFTT_BAD(c, "unknown tuning key");
 }
@@ -1212,6 +1268,10 @@ fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
         case FFTT_TUNE_PSF_MATH:
             if (value != 0 && value != 1) FFTT_BAD(c, "PSF math must be 0 or 1");
             c->psf_fp32_math = value;
+            return FFTT_OK;
+        case FFTT_TUNE_HESS_BATCHED:
+            if (value != 0 && value != 1) FFTT_BAD(c, "batched Hessian must be 0 or 1");
+            c->hess_batched = value;
             return FFTT_OK;
         case FFTT_TUNE_SPLIT_JT:
         case FFTT_TUNE_SPLIT_J:

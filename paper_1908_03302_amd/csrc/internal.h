@@ -154,6 +154,16 @@ hipError_t launch_psf(hipStream_t s, int tabfmt, const ApplyArgs& a, const int32
                       const int32_t* plane, const double* C, const int32_t* kptr, double s2,
                       float* W, int64_t ldw, int n, float* out, const void* col_tab, bool b3);
 size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, bool b3);
+// Gauss-Newton Hessian of l dense vectors (1 to 3 bands, split-BF16 matrix
+// cores): out [l][N] (zeroed) = sum_b J_b^T J_b Q * scale; part: [nb][nnz][l]
+// partials, red: [nb][S][Mk][l] FP64, W: [nb][Mk][ldw] (zeroed, ldw a
+// multiple of 32 >= l); Q: [l][ldq] model vectors.
+hipError_t launch_hess_block(hipStream_t s, int tabfmt, const ApplyArgs& a, const float* Q,
+                             int64_t ldq, int l, float* part, const int64_t* gptr,
+                             const void* desc, int S, double* red, const double* C,
+                             const int32_t* kptr, double scale, float* W, int64_t ldw,
+                             float* out);
+size_t jmb3_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx);
 // J per-pair sum: S slices per 64-pair group (reduce_slices), FP64 scratch
 // red [nb][S][Mk], then the rows of every caller pair of a group.
 int reduce_slices(int64_t Mk, int n_cu);
@@ -268,12 +278,14 @@ struct fftt_ctx {
     int staged_pair_table = 0; // FP32 staged kernels: 0 node table, 1 (h, slope) pairs
     int staged_block_max = 0;  // cap on the staged block size (0: LDS decides)
     int psf_fp32_math = 0;     // batched PSFs: 0 split-BF16 matrix cores (1-3 bands), 1 FP32
+    int hess_batched = 1;      // Hessian blocks on the matrix cores where possible
     size_t lds_limit = 65536;
 
     // work buffers
     fftt::DevBuf d_w, d_part, d_red, d_solve, d_scal, d_diag;
     fftt::DevBuf d_lr, d_lr_part, d_lr_small;   // low-rank analysis: blocks, Gram scratch
     fftt::DevBuf d_z3;                          // 2D: the prism's J^T before the z sum
+    fftt::DevBuf d_hb_part, d_hb_red, d_hb_w;   // batched Hessian: partials, sums, weights
     fftt::DevBuf d_psfw, d_psfd;   // batched PSF weights, (tile, lane) of each voxel
 
     // optional event timing of the main kernels (index: 0 J, 1 J^T, 2 reduction)

@@ -2010,6 +2010,248 @@ __global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __rest
     }
 }
 
+// ---- batched J for dense right-hand sides (Gauss-Newton Hessian blocks)
+//
+// part[b][e][k] = sum_j H_b[j][e] Q[k][j] for the entries e of a tile and l
+// right-hand sides Q ([l][ldq] model vectors): per 64-entry chunk a dense
+// (64 entries x 64 voxels)(64 voxels x 32 columns) product per wavefront on
+// the BF16 matrix cores with three-way split operands (as k_psfb3).  H is
+// kept entry-major ([entry][voxel] BF16 rows of 72) so a lane's 8 K-values
+// (voxels) are one 16-byte read; the tile's 64 x 32 block of Q is loaded
+// and split once per tile.  Each chunk's K range is the whole tile, so the
+// chunk's 64 x 32 result is final and stored at once.
+
+template <int NB, class TabT>
+__global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restrict__ Q,
+                                               int64_t ldq, int l, float* __restrict__ part) {
+    constexpr int CH = 64, RS = 36;           // entries per chunk, dwords per entry row
+    constexpr int HB = NB * CH * RS;          // dwords of one hi (or lo) buffer
+    const TabT* st = stage_table<TabT>(A, NB);
+    float2* sx = staged_tx<TabT>(A, NB);
+    uint32_t* hbuf = reinterpret_cast<uint32_t*>(sx + A.n_tx * 64);
+    uint16_t* hb16 = reinterpret_cast<uint16_t*>(hbuf);
+    int* svid = reinterpret_cast<int*>(hbuf + 4 * HB);   // [64] model index of each voxel
+    const int64_t a = xcd_tile(blockIdx.x);
+    if (a >= A.n_act) return;
+    const int lane = threadIdx.x & 63;
+    const LaneVox V = lane_vox(A, a, lane);
+    stage_distances(A, a, V, sx, lane, 0, (int)A.n_tx);   // ends with a barrier
+    const int W_ = (int)(blockDim.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (wave == 0)
+        svid[lane] = V.act ? (int)(A.nxy ? V.vidx % A.nxy : V.vidx) : -1;
+    const int k0 = ((int)blockIdx.y * W_ + wave) * 32;
+    const bool active = k0 < l;
+    const float nm1 = (float)(A.ntab - 1);
+    const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
+    const int col = lane & 31;
+    const int up = lane >> 5;
+    // H of a chunk: waves split the entries, lane = voxel, BF16 hi / lo
+    auto produce = [&](uint16_t* hh, uint16_t* hl, int64_t c0) {
+        for (int i = wave; i < CH; i += W_) {
+            const int64_t e = c0 + i;
+            const bool ok = e < t1;
+            const Entry E = A.ents[ok ? e : t0];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float h = ok ? psf_h(A, st, sx, E, b, nm1, lane) : 0.0f;
+                const __bf16 hi = (__bf16)h;
+                const int o = ((b * CH + i) * RS) * 2 + lane;
+                hh[o] = __builtin_bit_cast(uint16_t, hi);
+                hl[o] = __builtin_bit_cast(uint16_t, (__bf16)(h - (float)hi));
+            }
+        }
+    };
+    if (t0 < t1) produce(hb16, hb16 + 2 * HB, t0);
+    __syncthreads();
+    // this wave's columns of Q on the tile's voxels, split once
+    bf16x8 qh[4], ql[4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int vid = svid[16 * s4 + 8 * up + i];
+            const float q = (active && k0 + col < l && vid >= 0)
+                                ? Q[(int64_t)(k0 + col) * ldq + vid] : 0.0f;
+            const __bf16 x = (__bf16)q;
+            qh[s4][i] = x;
+            ql[s4][i] = (__bf16)(q - (float)x);
+        }
+    int buf = 0;
+    for (int64_t c0 = t0; c0 < t1; c0 += CH, buf ^= 1) {
+        const uint32_t* hh = hbuf + buf * 2 * HB;
+        const uint32_t* hl = hh + HB;
+        if (c0 + CH < t1)
+            produce(hb16 + (buf ^ 1) * 4 * HB, hb16 + (buf ^ 1) * 4 * HB + 2 * HB, c0 + CH);
+        if (active) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                f32x16v acc[2] = {};
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        const int o = (b * CH + 32 * mb + col) * RS + 8 * s4 + 4 * up;
+                        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(hh + o);
+                        const bf16x8 al = *reinterpret_cast<const bf16x8*>(hl + o);
+                        acc[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, qh[s4], acc[mb], 0, 0, 0);
+                        acc[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ql[s4], acc[mb], 0, 0, 0);
+                        acc[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, qh[s4], acc[mb], 0, 0, 0);
+                    }
+                // D: register q of lane -> entry row 8 (q / 4) + 4 up + q % 4
+                if (k0 + col < l) {
+#pragma unroll
+                    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) {
+                            const int64_t e = c0 + 32 * mb + 8 * (q / 4) + 4 * up + (q & 3);
+                            if (e < t1) part[((int64_t)b * A.nnz + e) * l + k0 + col] = acc[mb][q];
+                        }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Per-pair sums of the batched partials over the tiles (RunDesc groups as
+// in k_reduce), eight columns per workgroup: red[b][s][p][k] over slice s
+// of the group's descriptors, FP64, waves combined in order.
+constexpr int kRedCols = 8;
+constexpr int kRedColWaves = 4;
+
+__global__ __launch_bounds__(64 * kRedColWaves) void k_reduce_cols(
+    const float* __restrict__ part, int64_t nnz, int l, const int64_t* __restrict__ gptr,
+    const RunDesc* __restrict__ desc, int64_t Mk, int nb, int S, double* __restrict__ red) {
+    __shared__ double s_acc[kRedColWaves][64][kRedCols];
+    const int64_t g = blockIdx.x;
+    const int sl = (int)blockIdx.y;
+    const int c0 = (int)blockIdx.z * kRedCols;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t d0 = gptr[g], len = gptr[g + 1] - d0;
+    const int64_t s0 = d0 + len * sl / S, s1 = d0 + len * (sl + 1) / S;
+    const int64_t chunk = (s1 - s0 + kRedColWaves - 1) / kRedColWaves;
+    const int64_t k0 = min(s1, s0 + wave * chunk), k1 = min(s1, k0 + chunk);
+    const int64_t p = 64 * g + lane;
+    const int nc = min(kRedCols, l - c0);
+    for (int b = 0; b < nb; ++b) {
+        double acc[kRedCols];
+#pragma unroll
+        for (int c = 0; c < kRedCols; ++c) acc[c] = 0.0;
+        for (int64_t k = k0; k < k1; ++k) {
+            const RunDesc d = desc[k];
+            if ((d.mask >> lane) & 1ull) {
+                const float* row = part + ((int64_t)b * nnz + d.start + __popcll(d.mask & below)) * l + c0;
+#pragma unroll
+                for (int c = 0; c < kRedCols; ++c)
+                    if (c < nc) acc[c] += (double)row[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kRedCols; ++c) s_acc[wave][lane][c] = acc[c];
+        __syncthreads();
+        if (wave == 0 && p < Mk) {
+            for (int c = 0; c < nc; ++c) {
+                double t = s_acc[0][lane][c];
+                for (int w = 1; w < kRedColWaves; ++w) t += s_acc[w][lane][c];
+                red[(((int64_t)b * S + sl) * Mk + p) * l + c0 + c] = t;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// J^T weights of the Hessian product: W[b][p][k] = m_p C_p^2 scale sum_s red.
+__global__ void k_hess_weights(const double* __restrict__ red, int S, int64_t Mk, int l, int nb,
+                               const double* __restrict__ C, const int32_t* __restrict__ kptr,
+                               double scale, float* __restrict__ W, int64_t ldw) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nb * Mk * l) return;
+    const int64_t k = i % l, p = (i / l) % Mk, b = i / (l * Mk);
+    double t = 0.0;
+    for (int s = 0; s < S; ++s) t += red[((b * S + s) * Mk + p) * l + k];
+    const double m = (double)(kptr[p + 1] - kptr[p]);
+    W[(b * Mk + p) * ldw + k] = (float)(m * C[p] * C[p] * scale * t);
+}
+
+size_t jmb3_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
+    const size_t tbytes = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
+    return ((tbytes + 15) & ~(size_t)15) + (size_t)n_tx * 64 * sizeof(float2) +
+           4 * (size_t)nb * 64 * 36 * sizeof(uint32_t) + 64 * sizeof(int);
+}
+
+size_t psfb3_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx);
+
+template <int NB>
+static hipError_t launch_hess_nb(hipStream_t s, int tabfmt, const ApplyArgs& a, const float* Q,
+                                 int64_t ldq, int l, float* part, const int64_t* gptr,
+                                 const void* desc, int S, double* red, const double* C,
+                                 const int32_t* kptr, double scale, float* W, int64_t ldw,
+                                 float* out) {
+    const int wpb = a.waves_per_block;
+    const unsigned nbat = (unsigned)((l + 32 * wpb - 1) / (32 * wpb));
+    const unsigned grid = (unsigned)xcd_grid(a.n_act);
+    auto run = [&](auto kern, size_t lds, auto... args) -> hipError_t {
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kern, dim3(grid, nbat), dim3(64 * wpb), lds, s, a, args...);
+        return hipGetLastError();
+    };
+    if (a.n_act == 0) return hipSuccess;
+    const size_t lj = jmb3_lds_bytes(NB, a.ntab, tabfmt, a.n_tx);
+    hipError_t e = hipErrorInvalidValue;
+    switch (tabfmt) {
+        case STAB_NODE32: e = run(k_jmb3<NB, float>, lj, Q, ldq, l, part); break;
+        case STAB_PAIR32: e = run(k_jmb3<NB, float2>, lj, Q, ldq, l, part); break;
+        case STAB_BF16: e = run(k_jmb3<NB, uint32_t>, lj, Q, ldq, l, part); break;
+    }
+    if (e != hipSuccess) return e;
+    const int64_t G = (a.M + 63) / 64;
+    hipLaunchKernelGGL(k_reduce_cols,
+                       dim3((unsigned)G, (unsigned)S, (unsigned)((l + kRedCols - 1) / kRedCols)),
+                       dim3(64 * kRedColWaves), 0, s, part, a.nnz, l, gptr,
+                       static_cast<const RunDesc*>(desc), a.M, NB, S, red);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nw = (int64_t)NB * a.M * l;
+    hipLaunchKernelGGL(k_hess_weights, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, red, S,
+                       a.M, l, NB, C, kptr, scale, W, ldw);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lp = psfb3_lds_bytes(NB, a.ntab, tabfmt, a.n_tx);
+    switch (tabfmt) {
+        case STAB_NODE32: return run(k_psfb3<NB, float>, lp, (const float*)W, ldw, l, out);
+        case STAB_PAIR32: return run(k_psfb3<NB, float2>, lp, (const float*)W, ldw, l, out);
+        case STAB_BF16: return run(k_psfb3<NB, uint32_t>, lp, (const float*)W, ldw, l, out);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_hess_block(hipStream_t s, int tabfmt, const ApplyArgs& a, const float* Q,
+                             int64_t ldq, int l, float* part, const int64_t* gptr,
+                             const void* desc, int S, double* red, const double* C,
+                             const int32_t* kptr, double scale, float* W, int64_t ldw,
+                             float* out) {
+    switch (a.nb) {
+        case 1:
+            return launch_hess_nb<1>(s, tabfmt, a, Q, ldq, l, part, gptr, desc, S, red, C, kptr,
+                                     scale, W, ldw, out);
+        case 2:
+            return launch_hess_nb<2>(s, tabfmt, a, Q, ldq, l, part, gptr, desc, S, red, C, kptr,
+                                     scale, W, ldw, out);
+        case 3:
+            return launch_hess_nb<3>(s, tabfmt, a, Q, ldq, l, part, gptr, desc, S, red, C, kptr,
+                                     scale, W, ldw, out);
+    }
+    return hipErrorInvalidValue;
+}
+
 size_t psfb3_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
     const size_t tbytes = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
     const int ch = psfb3_chunk(nb);

@@ -26,7 +26,7 @@ EXPORTS = ["fftt_create", "fftt_destroy", "fftt_last_error", "fftt_set_stream",
            "fftt_psf", "fftt_profile", "fftt_kernel_time", "fftt_set_tuning", "fftt_get_tuning",
            "fftt_autotune", "fftt_set_kernel_series", "fftt_build_series_from_pulse",
            "fftt_coverage", "fftt_hessian_lowrank", "fftt_lowrank_diag",
-           "fftt_set_geometry_2d"]
+           "fftt_set_geometry_2d", "fftt_hessian_apply"]
 TUNE_WAVES_PER_BLOCK, TUNE_UNROLL_JT, TUNE_UNROLL_J, TUNE_SPLIT_JT, TUNE_SPLIT_J = 0, 1, 2, 3, 4
 TUNE_STAGED, TUNE_UNROLL_JT_STAGED, TUNE_UNROLL_J_STAGED = 5, 6, 7
 TUNE_STAGED_TABLE = 8
@@ -34,6 +34,7 @@ TUNE_RECIPROCITY = 9
 TUNE_STAGED_BLOCK = 10
 TUNE_KERNEL_EVAL = 11
 TUNE_PSF_MATH = 12
+TUNE_HESS_BATCHED = 13
 
 
 class SolveOpts(C.Structure):
@@ -96,6 +97,7 @@ def load():
     L.fftt_hessian_lowrank.argtypes = [vp, C.c_int, C.c_double, vp, C.c_int32, C.c_int32,
                                        C.c_int32, dp, vp, C.POINTER(C.c_int32)]
     L.fftt_lowrank_diag.argtypes = [vp, C.c_int, dp, vp, C.c_int32, C.c_double, vp, vp]
+    L.fftt_hessian_apply.argtypes = [vp, C.c_int, C.c_double, vp, C.c_int32, vp]
     L.fftt_profile.argtypes = [vp, C.c_int32]
     L.fftt_set_tuning.argtypes = [vp, C.c_int32, C.c_int32]
     L.fftt_get_tuning.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
@@ -245,7 +247,7 @@ class Context:
     def set_tuning(self, waves_per_block=None, unroll_jt=None, unroll_j=None, split_jt=None,
                    split_j=None, staged=None, unroll_jt_staged=None, unroll_j_staged=None,
                    staged_table=None, reciprocity=None, staged_block=None, kernel_eval=None,
-                   psf_math=None):
+                   psf_math=None, hess_batched=None):
         for key, v in ((TUNE_WAVES_PER_BLOCK, waves_per_block), (TUNE_UNROLL_JT, unroll_jt),
                        (TUNE_UNROLL_J, unroll_j), (TUNE_SPLIT_JT, split_jt),
                        (TUNE_SPLIT_J, split_j), (TUNE_STAGED, staged),
@@ -254,7 +256,7 @@ class Context:
                        (TUNE_STAGED_TABLE, staged_table),
                        (TUNE_RECIPROCITY, reciprocity),
                        (TUNE_STAGED_BLOCK, staged_block), (TUNE_KERNEL_EVAL, kernel_eval),
-                       (TUNE_PSF_MATH, psf_math)):
+                       (TUNE_PSF_MATH, psf_math), (TUNE_HESS_BATCHED, hess_batched)):
             if v is not None:
                 self._check(self.L.fftt_set_tuning(self.h, key, int(v)), "set_tuning")
 
@@ -263,7 +265,8 @@ class Context:
                    "staged": TUNE_STAGED, "unroll_jt_staged": TUNE_UNROLL_JT_STAGED,
                    "unroll_j_staged": TUNE_UNROLL_J_STAGED, "staged_table": TUNE_STAGED_TABLE,
                    "reciprocity": TUNE_RECIPROCITY, "staged_block": TUNE_STAGED_BLOCK,
-                   "kernel_eval": TUNE_KERNEL_EVAL, "psf_math": TUNE_PSF_MATH}
+                   "kernel_eval": TUNE_KERNEL_EVAL, "psf_math": TUNE_PSF_MATH,
+                   "hess_batched": TUNE_HESS_BATCHED}
 
     def get_tuning(self):
         """All tuning keys and their current values."""
@@ -361,6 +364,16 @@ class Context:
             int(l), int(q), int(k), _dp(ev), self._tensor(eigvecs, prec, k * self.N, "eigvecs"),
             C.byref(r)), "hessian_lowrank")
         return ev, eigvecs, r.value
+
+    def hessian_apply(self, x, n_vec, noise_sigma=1.0, prec=FP32, y=None):
+        """y_k = J^T J x_k / sigma^2 for n_vec vectors ([n_vec][N] tensors)."""
+        if y is None:
+            y = self._torch.empty(n_vec * self.N, dtype=_dtype_for(prec), device=x.device)
+        self._bind_stream()
+        self._check(self.L.fftt_hessian_apply(
+            self.h, int(prec), float(noise_sigma), self._tensor(x, prec, n_vec * self.N, "x"),
+            int(n_vec), self._tensor(y, prec, n_vec * self.N, "y")), "hessian_apply")
+        return y
 
     def lowrank_diag(self, eigvals, eigvecs, alpha, prec=FP32):
         """(posterior variance, resolution) diagonals [N] from k eigenpairs."""

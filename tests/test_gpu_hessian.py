@@ -1,0 +1,127 @@
+"""Products of the Gauss-Newton Hessian H = sum_b J_b^T J_b / sigma^2 with
+blocks of vectors (fftt_hessian_apply) through the C ABI: the batched
+matrix-core path (split BF16 operands, FP32 accumulation) against the
+oracle's dense H and against the library's one-vector path.
+
+Bars (norm-wise per vector): batched FP32 vs the oracle's table-mode H 1e-5;
+batched vs one-vector path 1e-5; FP64 (one-vector path) 1e-11.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_03302_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _fftt():
+    from paper_1908_03302_amd import fftt
+    return fftt
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ragged_bands(fcs):
+    g = I.centred_grid((37, 29, 11), 1.0e-3)
+    tx = I.ring(24, 0.03, 0.0005, phase=0.1)
+    return I.Workload(
+        name="ragged%d" % len(fcs), c0=1500.0, tx=tx, pairs=I.all_ordered_pairs(24), grid=g,
+        mask=I.cylinder_mask(g, 0.02), pulses=[I.sampled_pulse(f, 1.0) for f in fcs],
+        r_max=[I.R_MAX[f] for f in fcs], n_table=4096)
+
+
+@pytest.mark.parametrize("wname,l", [("small", 40), ("small", 70), ("ragged1", 5),
+                                     ("ragged2", 33), ("ragged3", 12)])
+def test_hessian_block_vs_oracle(wname, l):
+    f = _fftt()
+    if wname == "small":
+        w = I.small_fp64()
+    else:
+        w = ragged_bands([(1e6,), (1e6, 2e6), (0.5e6, 1e6, 2e6)][int(wname[-1]) - 1])
+    sig = 5e-9
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    Js = [ot.block(band=b) for b in range(w.n_bands)]
+    X = I.random_vector(l * w.n, 90 + l).reshape(l, w.n) * np.asarray(w.mask, float)
+    ref = sum(Jb.T @ (Jb @ X.T) for Jb in Js).T / sig ** 2
+    ctx = f.context_for_workload(w)
+    yb = host(ctx.hessian_apply(dev(X, torch.float32), l, sig, prec=f.FP32)).reshape(l, w.n)
+    ctx.set_tuning(hess_batched=0)
+    try:
+        yv = host(ctx.hessian_apply(dev(X, torch.float32), l, sig, prec=f.FP32)).reshape(l, w.n)
+        y64 = host(ctx.hessian_apply(dev(X, torch.float64), l, sig, prec=f.FP64)).reshape(l, w.n)
+    finally:
+        ctx.set_tuning(hess_batched=1)
+    eb = max(rel(yb[k], ref[k]) for k in range(l))
+    ev = max(rel(yv[k], ref[k]) for k in range(l))
+    ebv = max(rel(yb[k], yv[k]) for k in range(l))
+    e64 = max(rel(y64[k], ref[k]) for k in range(l))
+    say(wname, "l", l, "batched %.2e one-vector %.2e batched vs one-vector %.2e FP64 %.2e"
+        % (eb, ev, ebv, e64))
+    assert eb < 1e-5 and ebv < 1e-5 and ev < 1e-5 and e64 < 1e-11
+
+
+def test_hessian_block_ring2d():
+    """Full-size 128-element ring: 16 vectors batched against the one-vector
+    path, and the batched time against sixteen J + J^T."""
+    import time
+    f = _fftt()
+    w = I.ring2d()
+    say("ring2d hessian: set-up")
+    ctx = f.context_for_workload(w)
+    ctx.prepare()
+    l = 16
+    X = dev(I.random_vector(l * w.n, 95).reshape(l, w.n) * np.asarray(w.mask, float),
+            torch.float32)
+    ctx.hessian_apply(X, l, w.noise_sigma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    yb = ctx.hessian_apply(X, l, w.noise_sigma)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    ctx.set_tuning(hess_batched=0)
+    try:
+        t0 = time.perf_counter()
+        yv = ctx.hessian_apply(X, l, w.noise_sigma)
+        torch.cuda.synchronize()
+        tv = time.perf_counter() - t0
+    finally:
+        ctx.set_tuning(hess_batched=1)
+    B, V = host(yb).reshape(l, w.n), host(yv).reshape(l, w.n)
+    e = max(rel(B[k], V[k]) for k in range(l))
+    say("ring2d H of %d vectors: batched %.1f ms, one-vector %.1f ms, rel %.2e"
+        % (l, 1e3 * tb, 1e3 * tv, e))
+    assert e < 1e-5
+
+
+def test_hessian_apply_errors():
+    f = _fftt()
+    w = I.small_fp64()
+    ctx = f.context_for_workload(w)
+    x = dev(np.zeros(w.n), torch.float32)
+    with pytest.raises(f.FFTTError):
+        ctx.hessian_apply(x, 1, 0.0)
+    with pytest.raises(ValueError):
+        ctx.hessian_apply(x, 2, 1.0)      # buffer holds one vector
