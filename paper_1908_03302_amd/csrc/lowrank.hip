@@ -16,12 +16,14 @@ namespace fftt {
 
 namespace {
 
-constexpr int kGT = 16;              // Gram tile (vectors per side)
-constexpr int kGJ = 64;              // rows per LDS stage
-constexpr int64_t kGChunk = 16384;   // rows of one partial Gram block
+constexpr int kGT = 64;              // Gram tile (vectors per side)
+constexpr int kGJ = 32;              // rows per LDS stage
+constexpr int64_t kGChunk = 4096;    // rows of one partial Gram block
 
-// part[z][a][b] = sum_{j in chunk z} A[a][j] B[b][j] for one 16 x 16 tile of
-// (a, b); grid (ceil(la/16), ceil(lb/16), chunks), 256 threads.
+// part[z][a][b] = sum_{j in chunk z} A[a][j] B[b][j] for one 64 x 64 tile of
+// (a, b); grid (ceil(la/64), ceil(lb/64), chunks), 256 threads, each
+// accumulating a 4 x 4 block (a = ta + 16 i, b = tb + 16 j) in registers so
+// that one pair of LDS reads feeds two FMAs.
 template <class T>
 __global__ __launch_bounds__(256) void k_gram_part(const T* __restrict__ A, int la,
                                                    const T* __restrict__ B, int lb, int64_t n,
@@ -30,8 +32,12 @@ __global__ __launch_bounds__(256) void k_gram_part(const T* __restrict__ A, int 
     const int a0 = blockIdx.x * kGT, b0 = blockIdx.y * kGT;
     const int64_t j0 = (int64_t)blockIdx.z * kGChunk;
     const int64_t j1 = min(n, j0 + kGChunk);
-    const int tb = threadIdx.x & (kGT - 1), ta = threadIdx.x / kGT;
-    double acc = 0.0;
+    const int ta = threadIdx.x / 16, tb = threadIdx.x % 16;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
     for (int64_t jb = j0; jb < j1; jb += kGJ) {
         for (int t = threadIdx.x; t < kGT * kGJ; t += 256) {
             const int r = t / kGJ, col = t % kGJ;
@@ -40,12 +46,28 @@ __global__ __launch_bounds__(256) void k_gram_part(const T* __restrict__ A, int 
             sb[r][col] = (b0 + r < lb && j < j1) ? (double)B[(int64_t)(b0 + r) * n + j] : 0.0;
         }
         __syncthreads();
-#pragma unroll 8
-        for (int col = 0; col < kGJ; ++col) acc = fma(sa[ta][col], sb[tb][col], acc);
+#pragma unroll 4
+        for (int col = 0; col < kGJ; ++col) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                av[i] = sa[ta + 16 * i][col];
+                bv[i] = sb[tb + 16 * i][col];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
         __syncthreads();
     }
-    if (a0 + ta < la && b0 + tb < lb)
-        part[((int64_t)blockIdx.z * la + a0 + ta) * lb + b0 + tb] = acc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int a = a0 + ta + 16 * i, b = b0 + tb + 16 * j;
+            if (a < la && b < lb) part[((int64_t)blockIdx.z * la + a) * lb + b] = acc[i][j];
+        }
 }
 
 // out[i] = sum_z part[z][i], chunks added in order.
