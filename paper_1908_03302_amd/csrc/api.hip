@@ -561,6 +561,7 @@ fftt_status hess_block(fftt_ctx* c, fftt_precision prec, double isg2, const void
         psf_lds_bytes(c->nb, c->ntab, fmt, c->n_tx, true) <= c->lds_limit && c->nnz > 0) {
         const double per_col = (double)c->nb * (double)c->nnz * sizeof(float);
         cb = (int)std::min<double>(r, std::floor(budget / per_col));
+        if (cb < r) cb &= ~7;   // budget-bound batches: whole 8-column partial rows
         if (cb < std::min(r, 32)) cb = 0;
     }
     if (cb == 0) {
@@ -578,7 +579,7 @@ fftt_status hess_block(fftt_ctx* c, fftt_precision prec, double isg2, const void
     for (int c0 = 0; c0 < r; c0 += cb) {
         const int n = std::min(cb, r - c0);
         const int64_t ldw = ((int64_t)n + 31) / 32 * 32;
-        FFTT_HIP(c, c->d_hb_part.alloc((size_t)c->nb * c->nnz * n * sizeof(float)));
+        FFTT_HIP(c, c->d_hb_part.alloc((size_t)c->nb * c->nnz * hess_part_ld(n) * sizeof(float)));
         FFTT_HIP(c, c->d_hb_red.alloc((size_t)c->nb * S * c->Mk * n * sizeof(double)));
         FFTT_HIP(c, c->d_hb_w.alloc((size_t)c->nb * c->Mk * ldw * sizeof(float)));
         FFTT_HIP(c, launch_fill(c->stream, false, c->d_hb_w.p, (int64_t)c->nb * c->Mk * ldw));

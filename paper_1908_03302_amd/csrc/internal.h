@@ -154,9 +154,12 @@ hipError_t launch_psf(hipStream_t s, int tabfmt, const ApplyArgs& a, const int32
                       const int32_t* plane, const double* C, const int32_t* kptr, double s2,
                       float* W, int64_t ldw, int n, float* out, const void* col_tab, bool b3);
 size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, bool b3);
+// Row length (floats) of the Hessian partials of l columns: l rounded up to
+// a multiple of 8.
+constexpr int hess_part_ld(int l) { return (l + 7) & ~7; }
 // Gauss-Newton Hessian of l dense vectors (1 to 3 bands, split-BF16 matrix
-// cores): out [l][N] (zeroed) = sum_b J_b^T J_b Q * scale; part: [nb][nnz][l]
-// partials, red: [nb][S][Mk][l] FP64, W: [nb][Mk][ldw] (zeroed, ldw a
+// cores): out [l][N] (zeroed) = sum_b J_b^T J_b Q * scale; part:
+// [nb][nnz][hess_part_ld(l)] partials, red: [nb][S][Mk][l] FP64, W: [nb][Mk][ldw] (zeroed, ldw a
 // multiple of 32 >= l); Q: [l][ldq] model vectors.
 hipError_t launch_hess_block(hipStream_t s, int tabfmt, const ApplyArgs& a, const float* Q,
                              int64_t ldq, int l, float* part, const int64_t* gptr,

@@ -2046,6 +2046,7 @@ __global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restr
     const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
     const int col = lane & 31;
     const int up = lane >> 5;
+    const int lp = hess_part_ld(l);
     // H of a chunk: waves split the entries, lane = voxel, BF16 hi / lo
     auto produce = [&](uint16_t* hh, uint16_t* hl, int64_t c0) {
         for (int i = wave; i < CH; i += W_) {
@@ -2105,7 +2106,7 @@ __global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restr
 #pragma unroll
                         for (int q = 0; q < 16; ++q) {
                             const int64_t e = c0 + 32 * mb + 8 * (q / 4) + 4 * up + (q & 3);
-                            if (e < t1) part[((int64_t)b * A.nnz + e) * l + k0 + col] = acc[mb][q];
+                            if (e < t1) part[((int64_t)b * A.nnz + e) * lp + k0 + col] = acc[mb][q];
                         }
                 }
             }
@@ -2116,17 +2117,27 @@ __global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restr
 
 // Per-pair sums of the batched partials over the tiles (RunDesc groups as
 // in k_reduce), eight columns per workgroup: red[b][s][p][k] over slice s
-// of the group's descriptors, FP64, waves combined in order.
+// of the group's descriptors, FP64, waves combined in order.  Partial rows
+// hold hess_part_ld(l) floats, so a lane's eight columns are two aligned
+// 16-byte loads.  One-dimensional grid: the column chunks of one (group,
+// slice) are consecutive workgroups of one XCD, so the partial rows they
+// share come from HBM once and from that XCD's L2 for the others.
 constexpr int kRedCols = 8;
 constexpr int kRedColWaves = 4;
+constexpr int kRedUnroll = 8;
 
 __global__ __launch_bounds__(64 * kRedColWaves) void k_reduce_cols(
     const float* __restrict__ part, int64_t nnz, int l, const int64_t* __restrict__ gptr,
     const RunDesc* __restrict__ desc, int64_t Mk, int nb, int S, double* __restrict__ red) {
     __shared__ double s_acc[kRedColWaves][64][kRedCols];
-    const int64_t g = blockIdx.x;
-    const int sl = (int)blockIdx.y;
-    const int c0 = (int)blockIdx.z * kRedCols;
+    const int nz = (l + kRedCols - 1) / kRedCols;
+    const int64_t slot = (int64_t)blockIdx.x / kXcds;
+    const int64_t wi = (slot / nz) * kXcds + (int64_t)blockIdx.x % kXcds;
+    if (wi >= (Mk + 63) / 64 * S) return;
+    const int64_t g = wi / S;
+    const int sl = (int)(wi % S);
+    const int c0 = (int)(slot % nz) * kRedCols;
+    const int lp = hess_part_ld(l);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -2140,14 +2151,42 @@ __global__ __launch_bounds__(64 * kRedColWaves) void k_reduce_cols(
         double acc[kRedCols];
 #pragma unroll
         for (int c = 0; c < kRedCols; ++c) acc[c] = 0.0;
-        for (int64_t k = k0; k < k1; ++k) {
+        // kRedUnroll descriptors per step, loads first: a lane outside a run
+        // reads the run's first row and adds an exact 0.0, so every sum is
+        // taken in descriptor order as with one descriptor at a time
+        const float* pb = part + (int64_t)b * nnz * lp + c0;
+        auto add = [&](bool on, float4 u, float4 v) {
+            acc[0] += on ? (double)u.x : 0.0;
+            acc[1] += on ? (double)u.y : 0.0;
+            acc[2] += on ? (double)u.z : 0.0;
+            acc[3] += on ? (double)u.w : 0.0;
+            acc[4] += on ? (double)v.x : 0.0;
+            acc[5] += on ? (double)v.y : 0.0;
+            acc[6] += on ? (double)v.z : 0.0;
+            acc[7] += on ? (double)v.w : 0.0;
+        };
+        auto fetch = [&](int64_t k, bool& on, float4& u, float4& v) {
             const RunDesc d = desc[k];
-            if ((d.mask >> lane) & 1ull) {
-                const float* row = part + ((int64_t)b * nnz + d.start + __popcll(d.mask & below)) * l + c0;
+            on = (d.mask >> lane) & 1ull;
+            const float4* row = reinterpret_cast<const float4*>(
+                pb + (d.start + (on ? __popcll(d.mask & below) : 0)) * lp);
+            u = row[0];
+            v = row[1];
+        };
+        int64_t k = k0;
+        for (; k + kRedUnroll <= k1; k += kRedUnroll) {
+            bool on[kRedUnroll];
+            float4 u[kRedUnroll], v[kRedUnroll];
 #pragma unroll
-                for (int c = 0; c < kRedCols; ++c)
-                    if (c < nc) acc[c] += (double)row[c];
-            }
+            for (int i = 0; i < kRedUnroll; ++i) fetch(k + i, on[i], u[i], v[i]);
+#pragma unroll
+            for (int i = 0; i < kRedUnroll; ++i) add(on[i], u[i], v[i]);
+        }
+        for (; k < k1; ++k) {
+            bool on;
+            float4 u, v;
+            fetch(k, on, u, v);
+            add(on, u, v);
         }
 #pragma unroll
         for (int c = 0; c < kRedCols; ++c) s_acc[wave][lane][c] = acc[c];
@@ -2213,9 +2252,9 @@ static hipError_t launch_hess_nb(hipStream_t s, int tabfmt, const ApplyArgs& a, 
     }
     if (e != hipSuccess) return e;
     const int64_t G = (a.M + 63) / 64;
-    hipLaunchKernelGGL(k_reduce_cols,
-                       dim3((unsigned)G, (unsigned)S, (unsigned)((l + kRedCols - 1) / kRedCols)),
-                       dim3(64 * kRedColWaves), 0, s, part, a.nnz, l, gptr,
+    const int64_t nrc = (G * S + kXcds - 1) / kXcds * kXcds * ((l + kRedCols - 1) / kRedCols);
+    hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)nrc), dim3(64 * kRedColWaves), 0, s, part,
+                       a.nnz, l, gptr,
                        static_cast<const RunDesc*>(desc), a.M, NB, S, red);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
