@@ -572,7 +572,7 @@ fftt_status hess_block(fftt_ctx* c, fftt_precision prec, double isg2, const void
         }
         return FFTT_OK;
     }
-    const int S = reduce_slices(c->Mk, c->n_cu);
+    const int S = hess_slices(c->Mk, c->n_cu);
     ApplyArgs a = base_args(c);
     a.tab = staged_table_ptr(c, fmt);
     a.stage_q = (int)c->n_tx;

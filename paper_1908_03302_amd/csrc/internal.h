@@ -157,10 +157,13 @@ size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, bool b3);
 // Row length (floats) of the Hessian partials of l columns: l rounded up to
 // a multiple of 8.
 constexpr int hess_part_ld(int l) { return (l + 7) & ~7; }
+// Slices per 64-pair group of the Hessian partial sums (red's S).
+int hess_slices(int64_t Mk, int n_cu);
 // Gauss-Newton Hessian of l dense vectors (1 to 3 bands, split-BF16 matrix
 // cores): out [l][N] (zeroed) = sum_b J_b^T J_b Q * scale; part:
-// [nb][nnz][hess_part_ld(l)] partials, red: [nb][S][Mk][l] FP64, W: [nb][Mk][ldw] (zeroed, ldw a
-// multiple of 32 >= l); Q: [l][ldq] model vectors.
+// [nb][nnz][hess_part_ld(l)] partials, red: [nb][S][Mk][l] FP64 with
+// S = hess_slices(Mk, n_cu), W: [nb][Mk][ldw] (zeroed, ldw a multiple of 32
+// >= l); Q: [l][ldq] model vectors.
 hipError_t launch_hess_block(hipStream_t s, int tabfmt, const ApplyArgs& a, const float* Q,
                              int64_t ldq, int l, float* part, const int64_t* gptr,
                              const void* desc, int S, double* red, const double* C,

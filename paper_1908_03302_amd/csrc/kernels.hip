@@ -1655,6 +1655,51 @@ hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz
 
 using f32x16 = __attribute__((__vector_size__(16 * sizeof(float)))) float;
 
+// The PSF kernels' output step: one [32][33] float LDS slot per wave (up to
+// 16 waves), taken from the start of the dynamic LDS once the tile is done.
+constexpr int kPsfOutSlot = 32 * 33;
+constexpr size_t kPsfOutLds = 16 * kPsfOutSlot * sizeof(float);
+
+// Writes a wave's 64-voxel x 32-column block of PSFs (columns k0 .. k0 + 31
+// below n) of tile t.  The block is two 32 x 32 matrix-core results, lo for
+// voxels 0-31 and hi for 32-63, where register q of lane l holds voxel
+// 8 (q / 4) + 4 (l / 32) + q % 4 of the half in column l % 32.  Each half
+// goes through the wave's LDS slot so that a store covers 32 voxels of two
+// columns (runs of four x-neighbours) rather than one voxel in each of 32
+// columns a whole volume apart.  Every lane of the wave takes part; the
+// workgroup must be done with the LDS.
+template <class V>
+__device__ __forceinline__ void store_psf_block(const ApplyArgs& A, int64_t t, const V& c_lo,
+                                                const V& c_hi, int k0, int n, int wave,
+                                                int lane, float* __restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    float* slot = reinterpret_cast<float*>(smem) + wave * kPsfOutSlot;
+    const int64_t N = (int64_t)A.g.dims[0] * A.g.dims[1] * A.g.dims[2];
+    const int col = lane & 31, up = lane >> 5;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            slot[col * 33 + 8 * (q / 4) + 4 * up + (q & 3)] = h ? c_hi[q] : c_lo[q];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        bool inside, act;
+        int64_t vidx, v[3];
+        voxel_of_lane(A, t, col + 32 * h, inside, act, vidx, v);
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int c = 2 * it + up;
+            const float val = slot[c * 33 + col];
+            if (inside && k0 + c < n) out[(int64_t)(k0 + c) * N + vidx] = act ? val : 0.0f;
+        }
+        // the slot's reads complete before the next half overwrites it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 template <int NB, class TabT>
 __global__ __launch_bounds__(64) void k_psf_cols(ApplyArgs A, const int32_t* __restrict__ ptile,
                                                  const int32_t* __restrict__ plane,
@@ -1723,20 +1768,46 @@ inline int64_t xcd_grid(int64_t n) {
     return (n + round - 1) / round * round;
 }
 
+// Entries a wave of a chunk producer evaluates together: their loads are
+// issued at once, so the entry -> distance -> table chains overlap.
+constexpr int kProduceBatch = 4;
+
+// The batch of entries c0 + i0 + u * W_ (u < kProduceBatch) of a chunk of CH:
+// slots past the chunk or the tile take entry t0 (always valid) and ok = 0.
+template <int CH>
+__device__ __forceinline__ void produce_batch(const ApplyArgs& A, int64_t c0, int i0, int W_,
+                                              int64_t t0, int64_t t1,
+                                              Entry (&E)[kProduceBatch],
+                                              bool (&ok)[kProduceBatch]) {
+#pragma unroll
+    for (int u = 0; u < kProduceBatch; ++u) {
+        const int i = i0 + u * W_;
+        const int64_t e = c0 + i;
+        ok[u] = i < CH && e < t1;
+        E[u] = A.ents[ok[u] ? e : t0];
+    }
+}
+
 // H (and the pair index) of chunk entries c0 .. c0 + CH - 1 into one buffer;
 // the workgroup's waves split the entries.
 template <int NB, int CH, class TabT>
 __device__ __forceinline__ void psf_chunk_h(const ApplyArgs& A, const TabT* st, const float2* sx,
                                             float* hb, int* pb, int64_t c0, int64_t t0,
                                             int64_t t1, float nm1, int wave, int W_, int lane) {
-    for (int i = wave; i < CH; i += W_) {
-        const int64_t e = c0 + i;
-        const bool ok = e < t1;
-        const Entry E = A.ents[ok ? e : t0];
+    for (int i0 = wave; i0 < CH; i0 += kProduceBatch * W_) {
+        Entry E[kProduceBatch];
+        bool ok[kProduceBatch];
+        produce_batch<CH>(A, c0, i0, W_, t0, t1, E, ok);
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            hb[(b * CH + i) * 64 + lane] = ok ? psf_h(A, st, sx, E, b, nm1, lane) : 0.0f;
-        if (lane == 0) pb[i] = ok ? E.p : -1;
+        for (int u = 0; u < kProduceBatch; ++u) {
+            const int i = i0 + u * W_;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float h = psf_h(A, st, sx, E[u], b, nm1, lane);
+                if (i < CH) hb[(b * CH + i) * 64 + lane] = ok[u] ? h : 0.0f;
+            }
+            if (lane == 0 && i < CH) pb[i] = ok[u] ? E[u].p : -1;
+        }
     }
 }
 
@@ -1839,22 +1910,8 @@ __global__ __launch_bounds__(1024) void k_psf32(ApplyArgs A, const float* __rest
         }
         __syncthreads();
     }
-    // D layout of the 32x32 block: register q of lane l holds row
-    // 8 (q / 4) + 4 (l / 32) + q % 4, column l % 32.
-    if (!active || k0 + col >= n) return;
-    float* __restrict__ o = out + (int64_t)(k0 + col) * A.g.dims[0] * A.g.dims[1] * A.g.dims[2];
-    const int64_t t = A.tiles[a];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int i = 8 * (q / 4) + 4 * up + (q & 3);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            bool inside, act;
-            int64_t vidx, v[3];
-            voxel_of_lane(A, t, i + 32 * h, inside, act, vidx, v);
-            if (inside) o[vidx] = act ? (h ? c_hi[q] : c_lo[q]) : 0.0f;
-        }
-    }
+    if (!active) return;
+    store_psf_block(A, A.tiles[a], c_lo, c_hi, k0, n, wave, lane, out);
 }
 
 // ---- the same contraction with BF16 matrix-core steps, split three ways
@@ -1887,23 +1944,39 @@ __device__ __forceinline__ void psfb3_chunk_h(const ApplyArgs& A, const TabT* st
                                               int64_t t0, int64_t t1, float nm1, int wave,
                                               int W_, int lane) {
     constexpr int RS = (CH + 8) / 2;   // row stride in dwords
-    for (int i2 = wave; i2 < CH / 2; i2 += W_) {
-        const int64_t e0 = c0 + 2 * i2, e1 = e0 + 1;
-        const bool ok0 = e0 < t1, ok1 = e1 < t1;
-        const Entry E0 = A.ents[ok0 ? e0 : t0], E1 = A.ents[ok1 ? e1 : t0];
+    // entry pairs per batch (one with several bands, within the registers)
+    constexpr int PB = NB == 1 ? kProduceBatch / 2 : 1;
+    for (int j0 = wave; j0 < CH / 2; j0 += PB * W_) {
+        Entry E[2 * PB];
+        bool ok[2 * PB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const float h0 = ok0 ? psf_h(A, st, sx, E0, b, nm1, lane) : 0.0f;
-            const float h1 = ok1 ? psf_h(A, st, sx, E1, b, nm1, lane) : 0.0f;
-            const __bf16 a0 = (__bf16)h0, a1 = (__bf16)h1;
-            const __bf16 l0 = (__bf16)(h0 - (float)a0), l1 = (__bf16)(h1 - (float)a1);
-            const int o = (b * 64 + lane) * RS + i2;
-            hh[o] = bf16_bits(a0) | (bf16_bits(a1) << 16);
-            hl[o] = bf16_bits(l0) | (bf16_bits(l1) << 16);
+        for (int u = 0; u < 2 * PB; ++u) {
+            const int i2 = j0 + (u / 2) * W_;
+            const int64_t e = c0 + 2 * i2 + (u & 1);
+            ok[u] = i2 < CH / 2 && e < t1;
+            E[u] = A.ents[ok[u] ? e : t0];
         }
-        if (lane == 0) {
-            pb[2 * i2] = ok0 ? E0.p : -1;
-            pb[2 * i2 + 1] = ok1 ? E1.p : -1;
+#pragma unroll
+        for (int v = 0; v < PB; ++v) {
+            const int i2 = j0 + v * W_;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                float h0 = psf_h(A, st, sx, E[2 * v], b, nm1, lane);
+                float h1 = psf_h(A, st, sx, E[2 * v + 1], b, nm1, lane);
+                h0 = ok[2 * v] ? h0 : 0.0f;
+                h1 = ok[2 * v + 1] ? h1 : 0.0f;
+                const __bf16 a0 = (__bf16)h0, a1 = (__bf16)h1;
+                const __bf16 l0 = (__bf16)(h0 - (float)a0), l1 = (__bf16)(h1 - (float)a1);
+                const int o = (b * 64 + lane) * RS + i2;
+                if (i2 < CH / 2) {
+                    hh[o] = bf16_bits(a0) | (bf16_bits(a1) << 16);
+                    hl[o] = bf16_bits(l0) | (bf16_bits(l1) << 16);
+                }
+            }
+            if (lane == 0 && i2 < CH / 2) {
+                pb[2 * i2] = ok[2 * v] ? E[2 * v].p : -1;
+                pb[2 * i2 + 1] = ok[2 * v + 1] ? E[2 * v + 1].p : -1;
+            }
         }
     }
 }
@@ -1994,20 +2067,8 @@ __global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __rest
         }
         __syncthreads();
     }
-    if (!active || k0 + col >= n) return;
-    float* __restrict__ o = out + (int64_t)(k0 + col) * A.g.dims[0] * A.g.dims[1] * A.g.dims[2];
-    const int64_t t = A.tiles[a];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int i = 8 * (q / 4) + 4 * up + (q & 3);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            bool inside, act;
-            int64_t vidx, v[3];
-            voxel_of_lane(A, t, i + 32 * h, inside, act, vidx, v);
-            if (inside) o[vidx] = act ? (h ? c_hi[q] : c_lo[q]) : 0.0f;
-        }
-    }
+    if (!active) return;
+    store_psf_block(A, A.tiles[a], c_lo, c_hi, k0, n, wave, lane, out);
 }
 
 // ---- batched J for dense right-hand sides (Gauss-Newton Hessian blocks)
@@ -2049,17 +2110,24 @@ __global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restr
     const int lp = hess_part_ld(l);
     // H of a chunk: waves split the entries, lane = voxel, BF16 hi / lo
     auto produce = [&](uint16_t* hh, uint16_t* hl, int64_t c0) {
-        for (int i = wave; i < CH; i += W_) {
-            const int64_t e = c0 + i;
-            const bool ok = e < t1;
-            const Entry E = A.ents[ok ? e : t0];
+        for (int i0 = wave; i0 < CH; i0 += kProduceBatch * W_) {
+            Entry E[kProduceBatch];
+            bool ok[kProduceBatch];
+            produce_batch<CH>(A, c0, i0, W_, t0, t1, E, ok);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const float h = ok ? psf_h(A, st, sx, E, b, nm1, lane) : 0.0f;
-                const __bf16 hi = (__bf16)h;
-                const int o = ((b * CH + i) * RS) * 2 + lane;
-                hh[o] = __builtin_bit_cast(uint16_t, hi);
-                hl[o] = __builtin_bit_cast(uint16_t, (__bf16)(h - (float)hi));
+            for (int u = 0; u < kProduceBatch; ++u) {
+                const int i = i0 + u * W_;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    float h = psf_h(A, st, sx, E[u], b, nm1, lane);
+                    h = ok[u] ? h : 0.0f;
+                    const __bf16 hi = (__bf16)h;
+                    const int o = ((b * CH + i) * RS) * 2 + lane;
+                    if (i < CH) {
+                        hh[o] = __builtin_bit_cast(uint16_t, hi);
+                        hl[o] = __builtin_bit_cast(uint16_t, (__bf16)(h - (float)hi));
+                    }
+                }
             }
         }
     };
@@ -2116,35 +2184,29 @@ __global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restr
 }
 
 // Per-pair sums of the batched partials over the tiles (RunDesc groups as
-// in k_reduce), eight columns per workgroup: red[b][s][p][k] over slice s
-// of the group's descriptors, FP64, waves combined in order.  Partial rows
-// hold hess_part_ld(l) floats, so a lane's eight columns are two aligned
-// 16-byte loads.  One-dimensional grid: the column chunks of one (group,
-// slice) are consecutive workgroups of one XCD, so the partial rows they
-// share come from HBM once and from that XCD's L2 for the others.
+// in k_reduce): red[b][s][p][k] over slice s of the group's descriptors,
+// FP64, descriptors in order.  A workgroup takes one (group, slice) and up
+// to kRedColWaves column chunks of eight, one per wave: its waves walk the
+// same descriptors, so a partial row comes from HBM once and from the CU's
+// caches for its other chunks.  Partial rows hold hess_part_ld(l) floats,
+// so a lane's eight columns are two aligned 16-byte loads.
 constexpr int kRedCols = 8;
-constexpr int kRedColWaves = 4;
+constexpr int kRedColWaves = 16;
 constexpr int kRedUnroll = 8;
 
 __global__ __launch_bounds__(64 * kRedColWaves) void k_reduce_cols(
     const float* __restrict__ part, int64_t nnz, int l, const int64_t* __restrict__ gptr,
     const RunDesc* __restrict__ desc, int64_t Mk, int nb, int S, double* __restrict__ red) {
-    __shared__ double s_acc[kRedColWaves][64][kRedCols];
-    const int nz = (l + kRedCols - 1) / kRedCols;
-    const int64_t slot = (int64_t)blockIdx.x / kXcds;
-    const int64_t wi = (slot / nz) * kXcds + (int64_t)blockIdx.x % kXcds;
-    if (wi >= (Mk + 63) / 64 * S) return;
-    const int64_t g = wi / S;
-    const int sl = (int)(wi % S);
-    const int c0 = (int)(slot % nz) * kRedCols;
-    const int lp = hess_part_ld(l);
+    const int64_t g = blockIdx.x;
+    const int sl = (int)blockIdx.y;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int c0 = ((int)blockIdx.z * kRedColWaves + wave) * kRedCols;
+    if (c0 >= l) return;
     const int lane = threadIdx.x & 63;
+    const int lp = hess_part_ld(l);
     const uint64_t below = (1ull << lane) - 1ull;
     const int64_t d0 = gptr[g], len = gptr[g + 1] - d0;
-    const int64_t s0 = d0 + len * sl / S, s1 = d0 + len * (sl + 1) / S;
-    const int64_t chunk = (s1 - s0 + kRedColWaves - 1) / kRedColWaves;
-    const int64_t k0 = min(s1, s0 + wave * chunk), k1 = min(s1, k0 + chunk);
+    const int64_t k0 = d0 + len * sl / S, k1 = d0 + len * (sl + 1) / S;
     const int64_t p = 64 * g + lane;
     const int nc = min(kRedCols, l - c0);
     for (int b = 0; b < nb; ++b) {
@@ -2188,18 +2250,19 @@ __global__ __launch_bounds__(64 * kRedColWaves) void k_reduce_cols(
             fetch(k, on, u, v);
             add(on, u, v);
         }
+        if (p < Mk) {
+            double* r = red + (((int64_t)b * S + sl) * Mk + p) * l + c0;
 #pragma unroll
-        for (int c = 0; c < kRedCols; ++c) s_acc[wave][lane][c] = acc[c];
-        __syncthreads();
-        if (wave == 0 && p < Mk) {
-            for (int c = 0; c < nc; ++c) {
-                double t = s_acc[0][lane][c];
-                for (int w = 1; w < kRedColWaves; ++w) t += s_acc[w][lane][c];
-                red[(((int64_t)b * S + sl) * Mk + p) * l + c0 + c] = t;
-            }
+            for (int c = 0; c < kRedCols; ++c)
+                if (c < nc) r[c] = acc[c];
         }
-        __syncthreads();
     }
+}
+
+int hess_slices(int64_t Mk, int n_cu) {
+    const int64_t G = (Mk + 63) / 64;
+    const int64_t want = (16 * (int64_t)std::max(n_cu, 1) + G - 1) / std::max<int64_t>(G, 1);
+    return (int)std::min<int64_t>(std::max<int64_t>(want, 1), 64);
 }
 
 // J^T weights of the Hessian product: W[b][p][k] = m_p C_p^2 scale sum_s red.
@@ -2252,9 +2315,11 @@ static hipError_t launch_hess_nb(hipStream_t s, int tabfmt, const ApplyArgs& a, 
     }
     if (e != hipSuccess) return e;
     const int64_t G = (a.M + 63) / 64;
-    const int64_t nrc = (G * S + kXcds - 1) / kXcds * kXcds * ((l + kRedCols - 1) / kRedCols);
-    hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)nrc), dim3(64 * kRedColWaves), 0, s, part,
-                       a.nnz, l, gptr,
+    const int nz = (l + kRedCols - 1) / kRedCols;
+    hipLaunchKernelGGL(k_reduce_cols,
+                       dim3((unsigned)G, (unsigned)S,
+                            (unsigned)((nz + kRedColWaves - 1) / kRedColWaves)),
+                       dim3(64 * std::min(nz, kRedColWaves)), 0, s, part, a.nnz, l, gptr,
                        static_cast<const RunDesc*>(desc), a.M, NB, S, red);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -2294,8 +2359,10 @@ hipError_t launch_hess_block(hipStream_t s, int tabfmt, const ApplyArgs& a, cons
 size_t psfb3_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
     const size_t tbytes = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
     const int ch = psfb3_chunk(nb);
-    return ((tbytes + 15) & ~(size_t)15) + (size_t)n_tx * 64 * sizeof(float2) +
-           2 * (2 * (size_t)nb * 64 * ((ch + 8) / 2) * sizeof(uint32_t) + (size_t)ch * sizeof(int));
+    return std::max(((tbytes + 15) & ~(size_t)15) + (size_t)n_tx * 64 * sizeof(float2) +
+                        2 * (2 * (size_t)nb * 64 * ((ch + 8) / 2) * sizeof(uint32_t) +
+                             (size_t)ch * sizeof(int)),
+                    kPsfOutLds);
 }
 
 size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, bool b3) {
@@ -2303,8 +2370,9 @@ size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, bool b3) {
     const size_t tbytes = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
     const int ch = nb == 1 ? psf_chunk<1>()
                  : (nb == 2 ? psf_chunk<2>() : (nb == 3 ? psf_chunk<3>() : psf_chunk<4>()));
-    return ((tbytes + 15) & ~(size_t)15) + (size_t)n_tx * 64 * sizeof(float2) +
-           2 * ((size_t)nb * ch * 64 * sizeof(float) + (size_t)ch * sizeof(int));
+    return std::max(((tbytes + 15) & ~(size_t)15) + (size_t)n_tx * 64 * sizeof(float2) +
+                        2 * ((size_t)nb * ch * 64 * sizeof(float) + (size_t)ch * sizeof(int)),
+                    kPsfOutLds);
 }
 
 template <int NB>
