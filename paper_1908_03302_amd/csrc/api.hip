@@ -376,6 +376,8 @@ fftt_status psf_batched(fftt_ctx* c, fftt_precision prec, const int64_t* voxels,
         desc[n + k] = (int32_t)((x % kTile) + kTile * ((y % kTile) + kTile * (z % kTile)));
     }
     const int64_t ldw = ((int64_t)n + 31) / 32 * 32;
+    if (!psf_weights_fit(c->Mk, ldw))
+        FFTT_BAD(c, "psf: too many PSFs in one call (kernel pairs x n must stay below 2^30)");
     FFTT_HIP(c, c->d_psfd.alloc(desc.size() * sizeof(int32_t)));
     FFTT_HIP(c, hipMemcpyAsync(c->d_psfd.p, desc.data(), desc.size() * sizeof(int32_t),
                                hipMemcpyHostToDevice, c->stream));
@@ -562,7 +564,7 @@ fftt_status hess_block(fftt_ctx* c, fftt_precision prec, double isg2, const void
         const double per_col = (double)c->nb * (double)c->nnz * sizeof(float);
         cb = (int)std::min<double>(r, std::floor(budget / per_col));
         if (cb < r) cb &= ~7;   // budget-bound batches: whole 8-column partial rows
-        if (cb < std::min(r, 32)) cb = 0;
+        if (cb < std::min(r, 32) || !psf_weights_fit(c->Mk, ((int64_t)cb + 31) / 32 * 32)) cb = 0;
     }
     if (cb == 0) {
         for (int i = 0; i < r; ++i) {

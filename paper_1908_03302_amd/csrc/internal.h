@@ -154,14 +154,20 @@ hipError_t launch_psf(hipStream_t s, int tabfmt, const ApplyArgs& a, const int32
                       const int32_t* plane, const double* C, const int32_t* kptr, double s2,
                       float* W, int64_t ldw, int n, float* out, const void* col_tab, bool b3);
 size_t psf_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx, bool b3);
-// Row length (floats) of the Hessian partials of l columns: l rounded up to
-// a multiple of 8.
+// The PSF / Hessian contractions address a band's weights W [M][ldw] with
+// 32-bit byte offsets built from 24-bit products.
+inline bool psf_weights_fit(int64_t M, int64_t ldw) {
+    return M * ldw < (int64_t(1) << 30) && ldw < (int64_t(1) << 22);
+}
+// Columns of the Hessian partials of l columns: l rounded up to a multiple
+// of 8.  They are stored in blocks of 32 columns, [nb][block][nnz][width],
+// width 32 but for the last block (the rest of the columns).
 constexpr int hess_part_ld(int l) { return (l + 7) & ~7; }
 // Slices per 64-pair group of the Hessian partial sums (red's S).
 int hess_slices(int64_t Mk, int n_cu);
 // Gauss-Newton Hessian of l dense vectors (1 to 3 bands, split-BF16 matrix
 // cores): out [l][N] (zeroed) = sum_b J_b^T J_b Q * scale; part:
-// [nb][nnz][hess_part_ld(l)] partials, red: [nb][S][Mk][l] FP64 with
+// nb * nnz * hess_part_ld(l) partials, red: [nb][S][Mk][l] FP64 with
 // S = hess_slices(Mk, n_cu), W: [nb][Mk][ldw] (zeroed, ldw a multiple of 32
 // >= l); Q: [l][ldq] model vectors.
 hipError_t launch_hess_block(hipStream_t s, int tabfmt, const ApplyArgs& a, const float* Q,

@@ -1768,6 +1768,18 @@ inline int64_t xcd_grid(int64_t n) {
     return (n + round - 1) / round * round;
 }
 
+// Weights of the PSF contractions, W [nb][M][ldw] FP32: wrow is a wave's
+// block of columns in one band (uniform), the gather for kernel pair p and
+// the lane's column one 24-bit multiply-add on a 32-bit byte offset (the
+// launches require M ldw < 2^30 and ldw < 2^22).  The chunk producers give
+// padding entries pair 0: their H is exactly zero and W is finite, so the
+// row they read adds nothing.
+__device__ __forceinline__ float psf_weight(const float* wrow, int p, uint32_t ldw4,
+                                            uint32_t col4) {
+    const uint32_t off = __umul24((uint32_t)p, ldw4) + col4;
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(wrow) + off);
+}
+
 // Entries a wave of a chunk producer evaluates together: their loads are
 // issued at once, so the entry -> distance -> table chains overlap.
 constexpr int kProduceBatch = 4;
@@ -1806,7 +1818,7 @@ __device__ __forceinline__ void psf_chunk_h(const ApplyArgs& A, const TabT* st, 
                 const float h = psf_h(A, st, sx, E[u], b, nm1, lane);
                 if (i < CH) hb[(b * CH + i) * 64 + lane] = ok[u] ? h : 0.0f;
             }
-            if (lane == 0 && i < CH) pb[i] = ok[u] ? E[u].p : -1;
+            if (lane == 0 && i < CH) pb[i] = ok[u] ? E[u].p : 0;
         }
     }
 }
@@ -1835,6 +1847,7 @@ __global__ __launch_bounds__(1024) void k_psf32(ApplyArgs A, const float* __rest
     const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
     const int col = lane & 31;
     const int up = lane >> 5;
+    const uint32_t ldw4 = 4u * (uint32_t)ldw, col4 = 4u * (uint32_t)col;
     f32x16 c_lo = {}, c_hi = {};
     if (t0 < t1)
         psf_chunk_h<NB, CH>(A, st, sx, hbuf, pbuf, t0, t0, t1, nm1, wave, W_, lane);
@@ -1850,13 +1863,9 @@ __global__ __launch_bounds__(1024) void k_psf32(ApplyArgs A, const float* __rest
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int j = 0; j < CH / 2; ++j) {
-                    // unconditional load (row 0 for padding), selected after,
-                    // so the loads stay in flight together
-                    const int p = pb[2 * j + up];
-                    const float v = W[((int64_t)b * A.M + max(p, 0)) * ldw + k0 + col];
-                    bw[b][j] = p >= 0 ? v : 0.0f;
-                }
+                for (int j = 0; j < CH / 2; ++j)
+                    bw[b][j] = psf_weight(W + ((int64_t)b * A.M) * ldw + k0, pb[2 * j + up],
+                                          ldw4, col4);
         }
         if (c0 + CH < t1)
             psf_chunk_h<NB, CH>(A, st, sx, hbuf + (buf ^ 1) * HB, pbuf + (buf ^ 1) * CH, c0 + CH,
@@ -1936,6 +1945,22 @@ __device__ __forceinline__ uint32_t bf16_bits(__bf16 h) {
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// bf16(a) | bf16(b) << 16, both rounded to nearest even in one conversion.
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    const f32x2v v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
+}
+
+// Splits a pair of floats x ~ hi + lo (hi = bf16(x), lo = bf16(x - hi)) into
+// packed words: hi and lo of a in the low halves, of b in the high halves.
+__device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t& hi, uint32_t& lo) {
+    hi = pack_bf16x2(a, b);
+    lo = pack_bf16x2(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
+}
+
 // H of entries c0 .. c0 + CH - 1 split into hi / lo BF16 rows; waves take
 // pairs of entries, each lane (voxel) writes one packed dword per pair.
 template <int NB, int CH, class TabT>
@@ -1965,17 +1990,17 @@ __device__ __forceinline__ void psfb3_chunk_h(const ApplyArgs& A, const TabT* st
                 float h1 = psf_h(A, st, sx, E[2 * v + 1], b, nm1, lane);
                 h0 = ok[2 * v] ? h0 : 0.0f;
                 h1 = ok[2 * v + 1] ? h1 : 0.0f;
-                const __bf16 a0 = (__bf16)h0, a1 = (__bf16)h1;
-                const __bf16 l0 = (__bf16)(h0 - (float)a0), l1 = (__bf16)(h1 - (float)a1);
+                uint32_t wh, wl;
+                split_bf16x2(h0, h1, wh, wl);
                 const int o = (b * 64 + lane) * RS + i2;
                 if (i2 < CH / 2) {
-                    hh[o] = bf16_bits(a0) | (bf16_bits(a1) << 16);
-                    hl[o] = bf16_bits(l0) | (bf16_bits(l1) << 16);
+                    hh[o] = wh;
+                    hl[o] = wl;
                 }
             }
             if (lane == 0 && i2 < CH / 2) {
-                pb[2 * i2] = ok[2 * v] ? E[2 * v].p : -1;
-                pb[2 * i2 + 1] = ok[2 * v + 1] ? E[2 * v + 1].p : -1;
+                pb[2 * i2] = ok[2 * v] ? E[2 * v].p : 0;
+                pb[2 * i2 + 1] = ok[2 * v + 1] ? E[2 * v + 1].p : 0;
             }
         }
     }
@@ -2005,6 +2030,7 @@ __global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __rest
     const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
     const int col = lane & 31;
     const int up = lane >> 5;
+    const uint32_t ldw4 = 4u * (uint32_t)ldw, col4 = 4u * (uint32_t)col;
     f32x16v c_lo = {}, c_hi = {};
     if (t0 < t1)
         psfb3_chunk_h<NB, CH>(A, st, sx, hbuf, hbuf + HB, pbuf, t0, t0, t1, nm1, wave, W_, lane);
@@ -2014,38 +2040,42 @@ __global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __rest
         const uint32_t* hh = hbuf + buf * 2 * HB;
         const uint32_t* hl = hh + HB;
         const int* pb = pbuf + buf * CH;
-        // this chunk's weights, split (requested first), the next chunk's H,
-        // then the matrix-core steps
-        bf16x8 wh[NB][CH / 16], wl[NB][CH / 16];
+        // this chunk's weights (requested first), the next chunk's H, then
+        // the split and the matrix-core steps
+        float wv[NB][CH / 16][8];
         if (active) {
-            float wv[NB][CH / 16][8];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int s = 0; s < CH / 16; ++s)
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        // unconditional load (row 0 for padding), selected after
-                        const int p = pb[16 * s + 8 * up + i];
-                        const float v = W[((int64_t)b * A.M + max(p, 0)) * ldw + k0 + col];
-                        wv[b][s][i] = p >= 0 ? v : 0.0f;
-                    }
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-                for (int s = 0; s < CH / 16; ++s)
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        const __bf16 x = (__bf16)wv[b][s][i];
-                        wh[b][s][i] = x;
-                        wl[b][s][i] = (__bf16)(wv[b][s][i] - (float)x);
-                    }
+                    for (int i = 0; i < 8; ++i)
+                        wv[b][s][i] = psf_weight(W + ((int64_t)b * A.M) * ldw + k0,
+                                                 pb[16 * s + 8 * up + i], ldw4, col4);
         }
         if (c0 + CH < t1)
             psfb3_chunk_h<NB, CH>(A, st, sx, hbuf + (buf ^ 1) * 2 * HB,
                                   hbuf + (buf ^ 1) * 2 * HB + HB, pbuf + (buf ^ 1) * CH, c0 + CH,
                                   t0, t1, nm1, wave, W_, lane);
         if (active) {
+            // the weights split once they are needed (their loads stay in
+            // flight over the H evaluation above)
+            bf16x8 wh[NB][CH / 16], wl[NB][CH / 16];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int s = 0; s < CH / 16; ++s) {
+                    u32x4 h, l;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        uint32_t hk, lk;
+                        split_bf16x2(wv[b][s][2 * k], wv[b][s][2 * k + 1], hk, lk);
+                        h[k] = hk;
+                        l[k] = lk;
+                    }
+                    wh[b][s] = __builtin_bit_cast(bf16x8, h);
+                    wl[b][s] = __builtin_bit_cast(bf16x8, l);
+                }
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -2107,7 +2137,10 @@ __global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restr
     const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
     const int col = lane & 31;
     const int up = lane >> 5;
+    // this wave's block of 32 partial columns: rows of wb floats
     const int lp = hess_part_ld(l);
+    const int wb = min(32, lp - k0);
+    float* __restrict__ pblk = part + (int64_t)k0 * A.nnz;
     // H of a chunk: waves split the entries, lane = voxel, BF16 hi / lo
     auto produce = [&](uint16_t* hh, uint16_t* hl, int64_t c0) {
         for (int i0 = wave; i0 < CH; i0 += kProduceBatch * W_) {
@@ -2168,13 +2201,13 @@ __global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restr
                         acc[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, qh[s4], acc[mb], 0, 0, 0);
                     }
                 // D: register q of lane -> entry row 8 (q / 4) + 4 up + q % 4
-                if (k0 + col < l) {
+                if (col < wb) {
 #pragma unroll
                     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                         for (int q = 0; q < 16; ++q) {
                             const int64_t e = c0 + 32 * mb + 8 * (q / 4) + 4 * up + (q & 3);
-                            if (e < t1) part[((int64_t)b * A.nnz + e) * lp + k0 + col] = acc[mb][q];
+                            if (e < t1) pblk[(int64_t)b * lp * A.nnz + e * wb + col] = acc[mb][q];
                         }
                 }
             }
@@ -2188,8 +2221,9 @@ __global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restr
 // FP64, descriptors in order.  A workgroup takes one (group, slice) and up
 // to kRedColWaves column chunks of eight, one per wave: its waves walk the
 // same descriptors, so a partial row comes from HBM once and from the CU's
-// caches for its other chunks.  Partial rows hold hess_part_ld(l) floats,
-// so a lane's eight columns are two aligned 16-byte loads.
+// caches for its other chunks.  The partials lie in blocks of 32 columns
+// (rows of 32 floats, the last block hess_part_ld(l) - 32 k), so a lane's
+// eight columns are two aligned 16-byte loads.
 constexpr int kRedCols = 8;
 constexpr int kRedColWaves = 16;
 constexpr int kRedUnroll = 8;
@@ -2204,6 +2238,8 @@ __global__ __launch_bounds__(64 * kRedColWaves) void k_reduce_cols(
     if (c0 >= l) return;
     const int lane = threadIdx.x & 63;
     const int lp = hess_part_ld(l);
+    const int cb = c0 & ~31;               // first column of c0's block
+    const int wb = min(32, lp - cb);       // the block's row length
     const uint64_t below = (1ull << lane) - 1ull;
     const int64_t d0 = gptr[g], len = gptr[g + 1] - d0;
     const int64_t k0 = d0 + len * sl / S, k1 = d0 + len * (sl + 1) / S;
@@ -2216,7 +2252,7 @@ __global__ __launch_bounds__(64 * kRedColWaves) void k_reduce_cols(
         // kRedUnroll descriptors per step, loads first: a lane outside a run
         // reads the run's first row and adds an exact 0.0, so every sum is
         // taken in descriptor order as with one descriptor at a time
-        const float* pb = part + (int64_t)b * nnz * lp + c0;
+        const float* pb = part + ((int64_t)b * lp + cb) * nnz + (c0 - cb);
         auto add = [&](bool on, float4 u, float4 v) {
             acc[0] += on ? (double)u.x : 0.0;
             acc[1] += on ? (double)u.y : 0.0;
@@ -2231,7 +2267,7 @@ __global__ __launch_bounds__(64 * kRedColWaves) void k_reduce_cols(
             const RunDesc d = desc[k];
             on = (d.mask >> lane) & 1ull;
             const float4* row = reinterpret_cast<const float4*>(
-                pb + (d.start + (on ? __popcll(d.mask & below) : 0)) * lp);
+                pb + (d.start + (on ? __popcll(d.mask & below) : 0)) * wb);
             u = row[0];
             v = row[1];
         };
@@ -2292,6 +2328,7 @@ static hipError_t launch_hess_nb(hipStream_t s, int tabfmt, const ApplyArgs& a, 
                                  const void* desc, int S, double* red, const double* C,
                                  const int32_t* kptr, double scale, float* W, int64_t ldw,
                                  float* out) {
+    if (!psf_weights_fit(a.M, ldw)) return hipErrorInvalidValue;
     const int wpb = a.waves_per_block;
     const unsigned nbat = (unsigned)((l + 32 * wpb - 1) / (32 * wpb));
     const unsigned grid = (unsigned)xcd_grid(a.n_act);
@@ -2388,6 +2425,7 @@ static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
                        plane, C, kptr, s2, W, ldw);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess || a.n_act == 0) return err;
+    if (!psf_weights_fit(a.M, ldw)) return hipErrorInvalidValue;
     const int wpb = a.waves_per_block;
     const unsigned nbat = (unsigned)((n + 32 * wpb - 1) / (32 * wpb));
     const size_t lds = psf_lds_bytes(NB, a.ntab, tabfmt, a.n_tx, b3);
