@@ -70,37 +70,46 @@ __global__ __launch_bounds__(256) void k_gram_part(const T* __restrict__ A, int 
         }
 }
 
-// out[i] = sum_z part[z][i], chunks added in order.
-__global__ void k_gram_final(const double* __restrict__ part, int64_t chunks, int64_t m,
-                             double* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+// out[i] = sum_z part[z][i], one wave per i: lane t adds chunks t, t + 64,
+// ... in order, then the 64 lane sums are added in a fixed tree.
+__global__ __launch_bounds__(64) void k_gram_final(const double* __restrict__ part,
+                                                   int64_t chunks, int64_t m,
+                                                   double* __restrict__ out) {
+    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x;
     double s = 0.0;
-    for (int64_t z = 0; z < chunks; ++z) s += part[z * m + i];
-    out[i] = s;
+    for (int64_t z = lane; z < chunks; z += 64) s += part[z * m + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) out[i] = s;
 }
 
 using ConstD = const __attribute__((address_space(4))) double;
 
+constexpr int kCombCols = 16;   // output vectors per pass over Y
+
 // out[b][j] = sum_a Y[a][j] X[a][b] for b < m (X: [l][m] FP64, wave-uniform
-// scalar loads); grid (ceil(n/256), ceil(m/16)).
+// scalar loads); grid (ceil(n/256), ceil(m/kCombCols)).  Wider passes (one
+// read of Y for up to 48 outputs) measured slower: fewer waves and a scalar
+// load wait per row of X.
 template <class T>
 __global__ __launch_bounds__(256) void k_combine(const T* __restrict__ Y, int l, int64_t n,
                                                  const double* X, int m, T* __restrict__ out) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int b0 = blockIdx.y * 16;
+    const int b0 = blockIdx.y * kCombCols;
     if (j >= n) return;
     ConstD* x = (ConstD*)X;
-    double acc[16];
+    double acc[kCombCols];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+    for (int t = 0; t < kCombCols; ++t) acc[t] = 0.0;
     for (int a = 0; a < l; ++a) {
         const double y = (double)Y[(int64_t)a * n + j];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = fma(y, x[(int64_t)a * m + min(b0 + t, m - 1)], acc[t]);
+        for (int t = 0; t < kCombCols; ++t)
+            acc[t] = fma(y, x[(int64_t)a * m + min(b0 + t, m - 1)], acc[t]);
     }
 #pragma unroll
-    for (int t = 0; t < 16; ++t)
+    for (int t = 0; t < kCombCols; ++t)
         if (b0 + t < m) out[(int64_t)(b0 + t) * n + j] = (T)acc[t];
 }
 
@@ -136,8 +145,8 @@ hipError_t launch_gram(hipStream_t s, bool fp64, const void* A, int la, const vo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t m = (int64_t)la * lb;
-    hipLaunchKernelGGL(k_gram_final, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, part,
-                       chunks, m, out);
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gram_final, dim3((unsigned)m), dim3(64), 0, s, part, chunks, m, out);
     return hipGetLastError();
 }
 
@@ -148,7 +157,7 @@ size_t gram_part_doubles(int la, int lb, int64_t n) {
 hipError_t launch_combine(hipStream_t s, bool fp64, const void* Y, int l, int64_t n,
                           const double* X, int m, void* out) {
     if (n == 0 || m == 0) return hipSuccess;
-    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((m + 15) / 16));
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((m + kCombCols - 1) / kCombCols));
     if (fp64)
         hipLaunchKernelGGL(k_combine<double>, grid, dim3(256), 0, s, (const double*)Y, l, n, X, m,
                            (double*)out);
