@@ -383,7 +383,8 @@ fftt_status psf_batched(fftt_ctx* c, fftt_precision prec, const int64_t* voxels,
                                hipMemcpyHostToDevice, c->stream));
     FFTT_HIP(c, c->d_psfw.alloc((size_t)c->nb * c->Mk * ldw * sizeof(float)));
     FFTT_HIP(c, launch_fill(c->stream, false, c->d_psfw.p, (int64_t)c->nb * c->Mk * ldw));
-    FFTT_HIP(c, launch_fill(c->stream, false, out, (int64_t)n * c->N));
+    FFTT_HIP(c, fill_runs(c->stream, out, c->N, n, c->d_fill_runs.as<int64_t>(),
+                          c->n_fill_runs));
     ApplyArgs a = base_args(c);
     const int fmt = staged_table(c, prec);
     a.tab = staged_table_ptr(c, fmt);
@@ -799,6 +800,43 @@ fftt_status fftt_set_geometry(fftt_ctx* c, double c0, const double* tx_xyz, int6
     c->act_tiles.clear();
     for (size_t t = 0; t < tact.size(); ++t)
         if (tact[t]) c->act_tiles.push_back((int32_t)t);
+    // voxel index ranges covering every voxel outside the active tiles: the
+    // batched PSFs zero these, then write all voxels of the active tiles, so
+    // zeros written into active voxels are overwritten.  Each range is
+    // widened to whole 128-byte lines, ranges closer than kFillGap voxels are
+    // merged, and the result is split into pieces of at most kFillMax voxels
+    // (one wavefront's share).
+    constexpr int64_t kFillGap = 64, kFillMax = 4096;
+    std::vector<int64_t> merged, runs;
+    for (int64_t k = 0; k < dims[2]; ++k)
+        for (int64_t j = 0; j < dims[1]; ++j) {
+            const uint8_t* trow =
+                tact.data() + c->g.ntile[0] * ((j / kTile) + c->g.ntile[1] * (k / kTile));
+            const int64_t base = dims[0] * (j + dims[1] * k);
+            for (int64_t i = 0; i < dims[0];) {
+                if (trow[i / kTile]) { i = (i / kTile + 1) * kTile; continue; }
+                int64_t e = i;
+                while (e < dims[0] && !trow[e / kTile]) e = (e / kTile + 1) * kTile;
+                e = std::min(e, dims[0]);
+                // widened to whole 128-byte lines (32 floats)
+                const int64_t rs = (base + i) & ~int64_t(31);
+                const int64_t re = std::min(N, (base + e + 31) & ~int64_t(31));
+                const size_t nr = merged.size();
+                if (nr >= 2 && rs - (merged[nr - 2] + merged[nr - 1]) <= kFillGap) {
+                    merged[nr - 1] = std::max(merged[nr - 1], re - merged[nr - 2]);
+                } else {
+                    merged.push_back(rs);
+                    merged.push_back(re - rs);
+                }
+                i = e;
+            }
+        }
+    for (size_t r = 0; r < merged.size(); r += 2)
+        for (int64_t o = 0; o < merged[r + 1]; o += kFillMax) {
+            runs.push_back(merged[r] + o);
+            runs.push_back(std::min(kFillMax, merged[r + 1] - o));
+        }
+    c->n_fill_runs = (int64_t)runs.size() / 2;
 
     FFTT_HIP(c, c->d_tx.alloc(c->tx.size() * sizeof(double)));
     FFTT_HIP(c, c->d_mask.alloc((size_t)N));
@@ -809,6 +847,10 @@ fftt_status fftt_set_geometry(fftt_ctx* c, double c0, const double* tx_xyz, int6
     if (!c->act_tiles.empty())
         FFTT_HIP(c, hipMemcpy(c->d_tiles.p, c->act_tiles.data(),
                               c->act_tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    FFTT_HIP(c, c->d_fill_runs.alloc(std::max<size_t>(runs.size(), 2) * sizeof(int64_t)));
+    if (!runs.empty())
+        FFTT_HIP(c, hipMemcpy(c->d_fill_runs.p, runs.data(), runs.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice));
     st = build_pairs(c);
     if (st != FFTT_OK) return st;
     c->has_geom = true;

@@ -196,6 +196,10 @@ hipError_t solver_cgls_beta(hipStream_t s, double* sc);
 hipError_t solver_lsqr_beta(hipStream_t s, double* sc);
 hipError_t solver_lsqr_alpha_rot(hipStream_t s, double* sc, double damp, int first);
 hipError_t solver_unit(hipStream_t s, bool fp64, void* x, int64_t n, int64_t v);
+// Zeroes the index ranges (start, length pairs, nruns of them) of each of n
+// FP32 vectors of length N.
+hipError_t fill_runs(hipStream_t s, float* out, int64_t N, int n, const int64_t* runs,
+                     int64_t nruns);
 hipError_t solver_jacobi(hipStream_t s, bool fp64, void* minv, const float* diag, int64_t n,
                          double scale, double alpha);
 hipError_t solver_mul(hipStream_t s, bool fp64, void* z, const void* a, const void* b,
@@ -252,9 +256,10 @@ struct fftt_ctx {
     double dV = 0;
     std::vector<uint8_t> mask;
     std::vector<int32_t> act_tiles;
+    int64_t n_fill_runs = 0;              // voxel ranges outside every active tile
 
     // geometry (device)
-    fftt::DevBuf d_tx, d_ps, d_pr, d_kptr, d_kidx, d_L, d_C, d_mask, d_tiles;
+    fftt::DevBuf d_tx, d_ps, d_pr, d_kptr, d_kidx, d_L, d_C, d_mask, d_tiles, d_fill_runs;
 
     // kernel tables
     int nb = 0;

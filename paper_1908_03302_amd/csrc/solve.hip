@@ -250,6 +250,35 @@ __global__ void k_unit(T* __restrict__ x, int64_t n, int64_t v) {
     if (i < n) x[i] = (T)(i == v ? 1.0 : 0.0);
 }
 
+constexpr int kFillCols = 8;   // vectors per wavefront of k_fill_runs
+
+// Zeroes, in each of n vectors of length N, the index ranges [runs[2 r],
+// runs[2 r] + runs[2 r + 1]): one wavefront per (range, kFillCols vectors),
+// 16-byte stores where range and vector starts are multiples of 4.
+__global__ __launch_bounds__(64) void k_fill_runs(float* __restrict__ out, int64_t N, int n,
+                                                  const int64_t* __restrict__ runs) {
+    const int64_t st = runs[2 * (int64_t)blockIdx.x], len = runs[2 * (int64_t)blockIdx.x + 1];
+    const int k0 = (int)blockIdx.y * kFillCols, k1 = min(n, k0 + kFillCols);
+    const bool vec = ((st | len | N) & 3) == 0;
+    for (int k = k0; k < k1; ++k) {
+        float* __restrict__ o = out + (int64_t)k * N + st;
+        if (vec) {
+            for (int64_t i = threadIdx.x; i < len / 4; i += 64)
+                reinterpret_cast<float4*>(o)[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        } else {
+            for (int64_t i = threadIdx.x; i < len; i += 64) o[i] = 0.0f;
+        }
+    }
+}
+
+hipError_t fill_runs(hipStream_t s, float* out, int64_t N, int n, const int64_t* runs,
+                     int64_t nruns) {
+    if (nruns == 0 || n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_runs, dim3((unsigned)nruns, (unsigned)((n + kFillCols - 1) / kFillCols)),
+                       dim3(64), 0, s, out, N, n, runs);
+    return hipGetLastError();
+}
+
 hipError_t solver_unit(hipStream_t s, bool fp64, void* x, int64_t n, int64_t v) {
     if (fp64)
         hipLaunchKernelGGL(k_unit<double>, dim3(nblk(n)), dim3(256), 0, s, (double*)x, n, v);

@@ -53,9 +53,14 @@ def ragged_bands(fcs):
         r_max=[I.R_MAX[f] for f in fcs], n_table=4096)
 
 
-@pytest.mark.parametrize("wname,l", [("small", 40), ("small", 70), ("ragged1", 5),
-                                     ("ragged2", 33), ("ragged3", 12)])
-def test_hessian_block_vs_oracle(wname, l):
+@pytest.mark.parametrize("wname,l,wpb", [("small", 40, 16), ("small", 70, 16), ("small", 1, 16),
+                                         ("small", 32, 16), ("small", 40, 4),
+                                         ("ragged1", 5, 16), ("ragged2", 33, 16),
+                                         ("ragged2", 64, 16), ("ragged3", 12, 16)])
+def test_hessian_block_vs_oracle(wname, l, wpb):
+    """l = 1 and 32: one partial block padded to 8 columns / one whole
+    32-column block; 70 and 64: several blocks; 4 waves per workgroup:
+    several column batches per tile and several entry batches per wave."""
     f = _fftt()
     if wname == "small":
         w = I.small_fp64()
@@ -67,6 +72,7 @@ def test_hessian_block_vs_oracle(wname, l):
     X = I.random_vector(l * w.n, 90 + l).reshape(l, w.n) * np.asarray(w.mask, float)
     ref = sum(Jb.T @ (Jb @ X.T) for Jb in Js).T / sig ** 2
     ctx = f.context_for_workload(w)
+    ctx.set_tuning(waves_per_block=wpb)
     yb = host(ctx.hessian_apply(dev(X, torch.float32), l, sig, prec=f.FP32)).reshape(l, w.n)
     ctx.set_tuning(hess_batched=0)
     try:
@@ -78,8 +84,8 @@ def test_hessian_block_vs_oracle(wname, l):
     ev = max(rel(yv[k], ref[k]) for k in range(l))
     ebv = max(rel(yb[k], yv[k]) for k in range(l))
     e64 = max(rel(y64[k], ref[k]) for k in range(l))
-    say(wname, "l", l, "batched %.2e one-vector %.2e batched vs one-vector %.2e FP64 %.2e"
-        % (eb, ev, ebv, e64))
+    say(wname, "l", l, "wpb", wpb, "batched %.2e one-vector %.2e batched vs one-vector %.2e "
+        "FP64 %.2e" % (eb, ev, ebv, e64))
     assert eb < 1e-5 and ebv < 1e-5 and ev < 1e-5 and e64 < 1e-11
 
 
