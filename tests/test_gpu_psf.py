@@ -108,6 +108,43 @@ def test_psf_batch_ragged_two_bands(ragged_dense, prec_name, wpb):
         "worst rel err vs table oracle %.2e, vs quadrature %.2e (table's own %.2e)" % tuple(worst))
 
 
+def test_psf_batch_mask_holes_stale_output():
+    """A mask with whole 4^3 tiles and single voxels removed inside the
+    cylinder (inactive tiles between active ones on every row), written into
+    an output buffer full of NaN: every voxel outside the active tiles is
+    zeroed by the fill, every voxel inside is written by the contraction, so
+    no stale value survives; active voxels match the oracle's table mode."""
+    f = _fftt()
+    g = I.centred_grid((37, 29, 11), 1.0e-3)
+    nx, ny, nz = g.dims
+    mask = np.asarray(I.cylinder_mask(g, 0.02)).reshape(nz, ny, nx).copy()
+    tx_, ty_, tz_ = np.meshgrid(np.arange(nx) // 4, np.arange(ny) // 4, np.arange(nz) // 4,
+                                indexing="ij")
+    holes = ((tx_ + 2 * ty_ + tz_) % 3 == 0).transpose(2, 1, 0)     # whole tiles
+    mask[holes] = 0
+    rng = np.random.default_rng(12)
+    mask[rng.random(mask.shape) < 0.05] = 0                         # single voxels
+    mask = mask.ravel().astype(np.uint8)
+    w = I.Workload(name="holes", c0=1500.0, tx=I.ring(24, 0.03, 0.0005, phase=0.1),
+                   pairs=I.all_ordered_pairs(24), grid=g, mask=mask,
+                   pulses=[I.sampled_pulse(1e6, 1.0)], r_max=[I.R_MAX[1e6]], n_table=4096)
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    Jt = ot.block()
+    ctx = f.context_for_workload(w)
+    act = np.flatnonzero(mask)
+    vox = rng.choice(act, 40, replace=False)
+    out = torch.full((len(vox) * w.n,), float("nan"), dtype=torch.float32, device="cuda:0")
+    ctx.psf(vox, SIGMA, out=out, prec=f.FP32)
+    got = host(out).reshape(len(vox), w.n)
+    assert not np.isnan(got).any()
+    assert np.all(got[:, mask == 0] == 0.0)
+    ref = (Jt.T @ Jt[:, vox]).T / SIGMA ** 2
+    e = max(rel(got[k], ref[k]) for k in range(len(vox)))
+    say("mask with holes: %d active of %d voxels, worst rel err vs table oracle %.2e"
+        % (act.size, w.n, e))
+    assert e < TOL["FP32"]
+
+
 def test_psf_batch_matches_sequential_fp64(ragged_dense):
     """The batched FP32 PSFs agree with the per-voxel FP64 path (J then J^T)."""
     w, _, ctx = ragged_dense
