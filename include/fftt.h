@@ -110,7 +110,11 @@ fftt_status fftt_set_geometry_2d(fftt_ctx *ctx, double c0, const double *tx_xyz,
  * eq. Kernel_freq (without A).  Between nodes h is interpolated linearly;
  * for R >= r_max the kernel is zero (truncation of Sec. II-C).  All bands
  * must use the same n (2 <= n <= 16384).  With B bands set (0..B-1),
- * apply_J writes B outputs per right-hand side and apply_JT sums over bands. */
+ * apply_J writes B outputs per right-hand side and apply_JT sums over bands.
+ * FP32 operators: when |h[n-1]| <= 1e-6 max|h| in every band (as in the
+ * tables of fftt_build_table_from_pulse), the single-precision node table
+ * stores h[n-1] as 0, so h falls to 0 across the last interval below r_max
+ * instead of to h[n-1]; other tables are used as given. */
 fftt_status fftt_set_kernel_table(fftt_ctx *ctx, int32_t band, const double *h,
                                   int64_t n, double r_max);
 

@@ -65,11 +65,22 @@ fftt_status upload_tables(fftt_ctx* c) {
     std::vector<double> t64((size_t)nb * n * 2);
     std::vector<uint32_t> tbf((size_t)nb * n);
     std::vector<float> tnode((size_t)nb * n + 1, 0.f);   // + h_n = 0 after the last band
+    // When h at r_max is below 1e-6 of max |h| in every band (the tables of
+    // build_table_from_pulse: ~1e-7), the node table stores the top node as 0
+    // and the staged kernels truncate without a select; h then falls to 0
+    // across the last interval instead of to h_{n-1}.  Otherwise the exact
+    // nodes and the select.
+    c->tab_tail_zero = n >= 2;
+    for (int b = 0; b < nb; ++b) {
+        double hmax = 0.0;
+        for (double v : c->h[b]) hmax = std::max(hmax, std::fabs(v));
+        if (!(std::fabs(c->h[b][n - 1]) <= 1e-6 * hmax)) c->tab_tail_zero = false;
+    }
     for (int b = 0; b < nb; ++b) {
         const std::vector<double>& h = c->h[b];
         for (int k = 0; k < n; ++k) {
             const size_t i = (size_t)b * n + k;
-            tnode[i] = (float)h[k];
+            tnode[i] = (c->tab_tail_zero && k == n - 1) ? 0.f : (float)h[k];
             if (k < n - 1) {
                 t64[2 * i] = h[k];
                 t64[2 * i + 1] = h[k + 1] - h[k];
@@ -316,7 +327,8 @@ hipError_t prof_end(fftt_ctx* c, hipEvent_t stop) {
 // Table format of the LDS-staged kernels for an FP32 / BF16-table apply.
 int staged_table(const fftt_ctx* c, fftt_precision prec) {
     if (prec == FFTT_FP32_BF16TABLE) return STAB_BF16;
-    return c->staged_pair_table ? STAB_PAIR32 : STAB_NODE32;
+    if (c->staged_pair_table) return STAB_PAIR32;
+    return c->tab_tail_zero ? STAB_NODE32Z : STAB_NODE32;
 }
 
 // Evaluation of the detour function by the J / J^T kernels: the staged
@@ -353,7 +365,8 @@ int staged_q(fftt_ctx* c, fftt_precision prec) {
 // Device table of a staged launch.
 const void* staged_table_ptr(const fftt_ctx* c, int fmt) {
     switch (fmt) {
-        case STAB_NODE32: return c->d_tab32n.p;
+        case STAB_NODE32:
+        case STAB_NODE32Z: return c->d_tab32n.p;
         case STAB_PAIR32: return c->d_tab32.p;
         case STAB_SERIES: return c->d_series.p;
         default: return c->d_tabbf.p;

@@ -135,6 +135,7 @@ enum StagedTable {
     STAB_PAIR32 = 1,  // FP32 (h_k, h_{k+1} - h_k) (8 bytes per node), cutoff by the clamp
     STAB_BF16 = 2,    // packed BF16 (h_k, slope) (4 bytes per node)
     STAB_SERIES = 3,  // no table: the band's sine series (scalar loads, no LDS)
+    STAB_NODE32Z = 4, // FP32 nodes with the top node stored as 0 (no select)
 };
 hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a);
 // mode 1: out = sum_i |J_ij| (sensitivity coverage), mode 2: out = diag(J^T J),
@@ -293,6 +294,7 @@ struct fftt_ctx {
     int staged = 1;            // use the LDS-staged kernels when they fit
     int unroll_jts = 8, unroll_js = 8;
     int staged_pair_table = 0; // FP32 staged kernels: 0 node table, 1 (h, slope) pairs
+    bool tab_tail_zero = false; // every band's h at r_max negligible: node table top node 0
     int staged_block_max = 0;  // cap on the staged block size (0: LDS decides)
     int psf_fp32_math = 0;     // batched PSFs: 0 split-BF16 matrix cores (1-3 bands), 1 FP32
     int hess_batched = 1;      // Hessian blocks on the matrix cores where possible

@@ -512,6 +512,21 @@ __device__ __forceinline__ float lookup_x(const float* tab, float x, float nm1) 
     return x < nm1 ? v : 0.0f;
 }
 
+// FP32 node table whose top node h_{n-1} is stored as 0 (used when every
+// band's h at r_max is negligible): a coordinate clamped to n-1 reads
+// (0, next) with weight fract(x) = 0, so the truncation needs no select.
+// The float after a band's top node must be finite: the next band's first
+// node, the table's zeroed alignment padding, or the staged distances.
+struct NodeZ {
+    float v;
+};
+
+__device__ __forceinline__ float lookup_x(const NodeZ* tab, float x, float) {
+    const int k = (int)x;
+    const float h0 = tab[k].v, h1 = tab[k + 1].v;
+    return fmaf(__builtin_amdgcn_fractf(x), h1 - h0, h0);
+}
+
 // Sine series instead of a table (the paper's own stored form of eq.
 // Kernel_freq, Sec. II-C):  h = sum_{m=1}^{n} a_m sin(m theta), theta = beta R,
 // h = 0 for R >= r_max.  Per band, kSeriesStride floats in global memory:
@@ -656,6 +671,10 @@ __device__ __forceinline__ const TabT* stage_table(const ApplyArgs& A, int nb) {
     TabT* st = reinterpret_cast<TabT*>(smem);
     const int n = nb * A.ntab;
     for (int i = threadIdx.x; i < n; i += blockDim.x) st[i] = gt[i];
+    // the alignment padding after the table is zeroed (the top node's
+    // neighbour in the node formats, read with weight 0)
+    const int npad = (int)((lds_table_bytes<TabT>(A, nb) - (size_t)n * sizeof(TabT)) / sizeof(TabT));
+    if ((int)threadIdx.x < npad) st[n + threadIdx.x] = TabT{};
     __syncthreads();
     return st;
 }
@@ -1380,6 +1399,9 @@ static hipError_t launch_staged_nbu(hipStream_t s, int tabfmt, bool transpose,
                                     const ApplyArgs& a) {
     switch (tabfmt) {
         case STAB_NODE32: return launch_staged_t<float, NB, U>(s, transpose, a);
+        case STAB_NODE32Z:   // J only (J^T is launched with STAB_NODE32)
+            if (transpose) return hipErrorInvalidValue;
+            return launch_staged(k_j32s<NB, NodeZ, U>, s, a, (size_t)NB * a.ntab * sizeof(NodeZ));
         case STAB_PAIR32: return launch_staged_t<float2, NB, U>(s, transpose, a);
         case STAB_BF16: return launch_staged_t<uint32_t, NB, U>(s, transpose, a);
         // the series' own loop is long: at most four entries per step (no spills)
@@ -1400,6 +1422,9 @@ static hipError_t launch_staged_nb(hipStream_t s, int tabfmt, bool transpose, co
 }
 
 hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a) {
+    // J^T keeps the select on the same zero-topped node table (identical
+    // values): without it the eight-entry J^T kernel exceeds its registers
+    if (transpose && tabfmt == STAB_NODE32Z) tabfmt = STAB_NODE32;
     switch (a.nb) {
         case 1: return launch_staged_nb<1>(s, tabfmt, transpose, a);
         case 2: return launch_staged_nb<2>(s, tabfmt, transpose, a);
@@ -1413,6 +1438,7 @@ hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const 
 // (four entries per step) with per-pair weights from k_coverage_weights.
 template <int NB, int MODE>
 static hipError_t launch_coverage_nb(hipStream_t s, int tabfmt, const ApplyArgs& a) {
+    if (tabfmt == STAB_NODE32Z) tabfmt = STAB_NODE32;   // as J^T
     switch (tabfmt) {
         case STAB_NODE32:
             return launch_staged(k_jt32s<NB, float, 4, MODE>, s, a, (size_t)NB * a.ntab * 4);
@@ -2347,6 +2373,7 @@ static hipError_t launch_hess_nb(hipStream_t s, int tabfmt, const ApplyArgs& a, 
     hipError_t e = hipErrorInvalidValue;
     switch (tabfmt) {
         case STAB_NODE32: e = run(k_jmb3<NB, float>, lj, Q, ldq, l, part); break;
+        case STAB_NODE32Z: e = run(k_jmb3<NB, NodeZ>, lj, Q, ldq, l, part); break;
         case STAB_PAIR32: e = run(k_jmb3<NB, float2>, lj, Q, ldq, l, part); break;
         case STAB_BF16: e = run(k_jmb3<NB, uint32_t>, lj, Q, ldq, l, part); break;
     }
@@ -2368,6 +2395,7 @@ static hipError_t launch_hess_nb(hipStream_t s, int tabfmt, const ApplyArgs& a, 
     const size_t lp = psfb3_lds_bytes(NB, a.ntab, tabfmt, a.n_tx);
     switch (tabfmt) {
         case STAB_NODE32: return run(k_psfb3<NB, float>, lp, (const float*)W, ldw, l, out);
+        case STAB_NODE32Z: return run(k_psfb3<NB, NodeZ>, lp, (const float*)W, ldw, l, out);
         case STAB_PAIR32: return run(k_psfb3<NB, float2>, lp, (const float*)W, ldw, l, out);
         case STAB_BF16: return run(k_psfb3<NB, uint32_t>, lp, (const float*)W, ldw, l, out);
     }
@@ -2444,6 +2472,7 @@ static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
         if (b3) {
             switch (tabfmt) {
                 case STAB_NODE32: return run(k_psfb3<NB, float>);
+                case STAB_NODE32Z: return run(k_psfb3<NB, NodeZ>);
                 case STAB_PAIR32: return run(k_psfb3<NB, float2>);
                 case STAB_BF16: return run(k_psfb3<NB, uint32_t>);
             }
@@ -2452,6 +2481,7 @@ static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
     }
     switch (tabfmt) {
         case STAB_NODE32: return run(k_psf32<NB, float>);
+        case STAB_NODE32Z: return run(k_psf32<NB, NodeZ>);
         case STAB_PAIR32: return run(k_psf32<NB, float2>);
         case STAB_BF16: return run(k_psf32<NB, uint32_t>);
     }
