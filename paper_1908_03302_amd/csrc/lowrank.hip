@@ -16,30 +16,30 @@ namespace fftt {
 
 namespace {
 
-constexpr int kGT = 64;              // Gram tile (vectors per side)
 constexpr int kGJ = 32;              // rows per LDS stage
 constexpr int64_t kGChunk = 4096;    // rows of one partial Gram block
 
-// part[z][a][b] = sum_{j in chunk z} A[a][j] B[b][j] for one 64 x 64 tile of
-// (a, b); grid (ceil(la/64), ceil(lb/64), chunks), 256 threads, each
-// accumulating a 4 x 4 block (a = ta + 16 i, b = tb + 16 j) in registers so
-// that one pair of LDS reads feeds two FMAs.
-template <class T>
+// part[z][a][b] = sum_{j in chunk z} A[a][j] B[b][j] for one GT x GT tile
+// of (a, b), GT = 16 RB; grid (ceil(la/GT), ceil(lb/GT), chunks), 256
+// threads, each accumulating an RB x RB block (a = ta + 16 i, b = tb + 16 j)
+// in registers, so one LDS read feeds RB / 2 FMAs.
+template <int RB, class T>
 __global__ __launch_bounds__(256) void k_gram_part(const T* __restrict__ A, int la,
                                                    const T* __restrict__ B, int lb, int64_t n,
                                                    double* __restrict__ part) {
-    __shared__ double sa[kGT][kGJ + 1], sb[kGT][kGJ + 1];
-    const int a0 = blockIdx.x * kGT, b0 = blockIdx.y * kGT;
+    constexpr int GT = 16 * RB;
+    __shared__ double sa[GT][kGJ + 1], sb[GT][kGJ + 1];
+    const int a0 = blockIdx.x * GT, b0 = blockIdx.y * GT;
     const int64_t j0 = (int64_t)blockIdx.z * kGChunk;
     const int64_t j1 = min(n, j0 + kGChunk);
     const int ta = threadIdx.x / 16, tb = threadIdx.x % 16;
-    double acc[4][4];
+    double acc[RB][RB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < RB; ++j) acc[i][j] = 0.0;
     for (int64_t jb = j0; jb < j1; jb += kGJ) {
-        for (int t = threadIdx.x; t < kGT * kGJ; t += 256) {
+        for (int t = threadIdx.x; t < GT * kGJ; t += 256) {
             const int r = t / kGJ, col = t % kGJ;
             const int64_t j = jb + col;
             sa[r][col] = (a0 + r < la && j < j1) ? (double)A[(int64_t)(a0 + r) * n + j] : 0.0;
@@ -48,23 +48,23 @@ __global__ __launch_bounds__(256) void k_gram_part(const T* __restrict__ A, int 
         __syncthreads();
 #pragma unroll 4
         for (int col = 0; col < kGJ; ++col) {
-            double av[4], bv[4];
+            double av[RB], bv[RB];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < RB; ++i) {
                 av[i] = sa[ta + 16 * i][col];
                 bv[i] = sb[tb + 16 * i][col];
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < RB; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+                for (int j = 0; j < RB; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < RB; ++j) {
             const int a = a0 + ta + 16 * i, b = b0 + tb + 16 * j;
             if (a < la && b < lb) part[((int64_t)blockIdx.z * la + a) * lb + b] = acc[i][j];
         }
@@ -90,8 +90,8 @@ constexpr int kCombCols = 16;   // output vectors per pass over Y
 
 // out[b][j] = sum_a Y[a][j] X[a][b] for b < m (X: [l][m] FP64, wave-uniform
 // scalar loads); grid (ceil(n/256), ceil(m/kCombCols)).  Wider passes (one
-// read of Y for up to 48 outputs) measured slower: fewer waves and a scalar
-// load wait per row of X.
+// read of Y for up to 48 outputs) and requesting the next row of X ahead
+// both measured slower.
 template <class T>
 __global__ __launch_bounds__(256) void k_combine(const T* __restrict__ Y, int l, int64_t n,
                                                  const double* X, int m, T* __restrict__ out) {
@@ -134,13 +134,22 @@ __global__ void k_lowrank_diag(const T* __restrict__ V, int k, int64_t n,
 hipError_t launch_gram(hipStream_t s, bool fp64, const void* A, int la, const void* B, int lb,
                        int64_t n, double* part, double* out) {
     const int64_t chunks = std::max<int64_t>((n + kGChunk - 1) / kGChunk, 1);
-    const dim3 grid((unsigned)((la + kGT - 1) / kGT), (unsigned)((lb + kGT - 1) / kGT),
+    // 48 x 48 tiles when they cover both sides (less padding for up to 48
+    // vectors), else 64 x 64
+    const int gt = std::max(la, lb) <= 48 ? 48 : 64;
+    const dim3 grid((unsigned)((la + gt - 1) / gt), (unsigned)((lb + gt - 1) / gt),
                     (unsigned)chunks);
-    if (fp64)
-        hipLaunchKernelGGL(k_gram_part<double>, grid, dim3(256), 0, s, (const double*)A, la,
-                           (const double*)B, lb, n, part);
+    if (gt == 48 && fp64)
+        hipLaunchKernelGGL((k_gram_part<3, double>), grid, dim3(256), 0, s, (const double*)A,
+                           la, (const double*)B, lb, n, part);
+    else if (gt == 48)
+        hipLaunchKernelGGL((k_gram_part<3, float>), grid, dim3(256), 0, s, (const float*)A, la,
+                           (const float*)B, lb, n, part);
+    else if (fp64)
+        hipLaunchKernelGGL((k_gram_part<4, double>), grid, dim3(256), 0, s, (const double*)A,
+                           la, (const double*)B, lb, n, part);
     else
-        hipLaunchKernelGGL(k_gram_part<float>, grid, dim3(256), 0, s, (const float*)A, la,
+        hipLaunchKernelGGL((k_gram_part<4, float>), grid, dim3(256), 0, s, (const float*)A, la,
                            (const float*)B, lb, n, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
