@@ -1399,9 +1399,13 @@ static hipError_t launch_staged_nbu(hipStream_t s, int tabfmt, bool transpose,
                                     const ApplyArgs& a) {
     switch (tabfmt) {
         case STAB_NODE32: return launch_staged_t<float, NB, U>(s, transpose, a);
-        case STAB_NODE32Z:   // J only (J^T is launched with STAB_NODE32)
-            if (transpose) return hipErrorInvalidValue;
-            return launch_staged(k_j32s<NB, NodeZ, U>, s, a, (size_t)NB * a.ntab * sizeof(NodeZ));
+        case STAB_NODE32Z:   // one-band J^T is launched with STAB_NODE32
+            if constexpr (NB == 1) {
+                if (transpose) return hipErrorInvalidValue;
+                return launch_staged(k_j32s<NB, NodeZ, U>, s, a, (size_t)NB * a.ntab * sizeof(NodeZ));
+            } else {
+                return launch_staged_t<NodeZ, NB, U>(s, transpose, a);
+            }
         case STAB_PAIR32: return launch_staged_t<float2, NB, U>(s, transpose, a);
         case STAB_BF16: return launch_staged_t<uint32_t, NB, U>(s, transpose, a);
         // the series' own loop is long: at most four entries per step (no spills)
@@ -1422,9 +1426,10 @@ static hipError_t launch_staged_nb(hipStream_t s, int tabfmt, bool transpose, co
 }
 
 hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a) {
-    // J^T keeps the select on the same zero-topped node table (identical
-    // values): without it the eight-entry J^T kernel exceeds its registers
-    if (transpose && tabfmt == STAB_NODE32Z) tabfmt = STAB_NODE32;
+    // one-band J^T keeps the select on the same zero-topped node table
+    // (identical values): without it its eight-entry kernel exceeds the 64
+    // registers of two workgroups per CU
+    if (transpose && a.nb == 1 && tabfmt == STAB_NODE32Z) tabfmt = STAB_NODE32;
     switch (a.nb) {
         case 1: return launch_staged_nb<1>(s, tabfmt, transpose, a);
         case 2: return launch_staged_nb<2>(s, tabfmt, transpose, a);
