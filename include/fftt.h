@@ -286,9 +286,12 @@ fftt_status fftt_lowrank_diag(fftt_ctx *ctx, fftt_precision prec, const double *
  * FP32 / BF16-table precision with the staged kernels enabled (and the
  * tables plus n_tx * 512 bytes within LDS): all n in one batch -- the J^T
  * weights of every J e_k, then one launch that contracts the per-tile
- * kernel values with them on the matrix cores (FP32 MFMA).  Otherwise one
- * J and one J^T per voxel.  Library workspace: nb * M * ceil32(n) floats.
- * Asynchronous except for the final wait of the batched path. */
+ * kernel values with them on the matrix cores (BF16 with three-way split
+ * operands for 1 to 3 bands, FP32 otherwise or with FFTT_TUNE_PSF_MATH = 1);
+ * the batch requires (kernel pairs) * ceil32(n) < 2^30 and n < 2^22, else
+ * FFTT_E_INVALID.  Otherwise one J and one J^T per voxel.  Library
+ * workspace: nb * M * ceil32(n) floats.  Asynchronous except for the final
+ * wait of the batched path. */
 fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
                      int32_t n, double noise_sigma, void *out);
 
