@@ -262,8 +262,10 @@ fftt_status fftt_hessian_lowrank(fftt_ctx *ctx, fftt_precision prec, double nois
  * operators with 1 to 3 bands in 3D run as one batch (FFTT_TUNE_HESS_BATCHED):
  * per tile the products with all vectors are contractions on the BF16 matrix
  * cores, every FP32 operand split in two BF16 parts (hi hi + hi lo + lo hi,
- * FP32 accumulation; ~1e-6 relative against the one-vector path), partials
- * summed per pair in FP64 in a fixed order.  Asynchronous. */
+ * FP32 accumulation; within 1e-5, norm-wise per vector, of the one-vector
+ * path), partials summed per pair in FP64 in a fixed order.  Library
+ * workspace: the per-(tile, pair) partials of a column batch, at most about
+ * 8 GB (batches of fewer columns otherwise).  Asynchronous. */
 fftt_status fftt_hessian_apply(fftt_ctx *ctx, fftt_precision prec, double noise_sigma,
                                const void *x, int32_t n_vec, void *y);
 
