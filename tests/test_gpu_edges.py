@@ -163,6 +163,46 @@ def test_shortest_and_longest_table(n_table):
         assert ej <= bar and et <= bar
 
 
+@pytest.mark.parametrize("tail", ["built", "raised"])
+def test_table_tail_forms(tail):
+    """Two bands from the library's table builder (top node ~1e-7 of max|h|:
+    the FP32 node table stores it as 0 and the J / multi-band J^T lookups
+    drop the truncation select), and the same tables with the top node
+    raised to 1e-3 of max|h| (kept as given, truncation by the select).
+    Both match the oracle given the same tables to the FP32 bar."""
+    f = _fftt()
+    tx = I.ring(16, 0.006)
+    g = I.centred_grid((13, 11, 6), 0.5e-3)
+    fcs = (1e6, 2e6)
+    w = I.Workload(name="tail", c0=1500.0, tx=tx, pairs=I.all_ordered_pairs(16), grid=g,
+                   mask=I.cylinder_mask(g, None), pulses=[I.sampled_pulse(fc, 1.0) for fc in fcs],
+                   r_max=[I.R_MAX[fc] for fc in fcs], n_table=4096)
+    tabs = []
+    for p in w.pulses:
+        h, rm = f.build_table_from_pulse(w.c0, p.samples, p.dt, w.n_table, w.r_max[len(tabs)])
+        h = np.array(h, dtype=np.float64)
+        if tail == "raised":
+            h[-1] = 1e-3 * np.abs(h).max()
+        tabs.append((h, rm))
+    o = oracle.Oracle(w.c0, w.tx, w.pairs, w.grid.origin, w.grid.spacing, w.grid.dims, w.mask,
+                      [rm for _, rm in tabs], tables=[h for h, _ in tabs])
+    ctx = f.Context(0)
+    ctx.set_geometry(w.c0, w.tx, w.pairs, w.grid.origin, w.grid.spacing, w.grid.dims, w.mask)
+    for b, (h, rm) in enumerate(tabs):
+        ctx.set_kernel_table(b, h, rm)
+    x = I.random_vector(w.n, 43) * 10.0
+    y = I.random_vector(w.m * 2, 44) * 1e-7
+    yr = np.asarray(o.apply_J(x)).ravel()          # [band][pair]
+    xr = o.apply_JT(y)                              # summed over bands
+    yg = host(ctx.apply_J(dev(x, torch.float32), prec=f.FP32))
+    xg = host(ctx.apply_JT(dev(y, torch.float32), prec=f.FP32))
+    ej, et = rel(yg, yr), rel(xg, xr)
+    say("tail", tail, "J %.2e J^T %.2e" % (ej, et))
+    assert ej <= 1e-5 and et <= 1e-5
+    zero = np.flatnonzero(yr == 0.0)
+    assert np.all(yg[zero] == 0.0)
+
+
 def test_invalid_input_statuses():
     f = _fftt()
     ctx = f.Context(0)
