@@ -293,6 +293,38 @@ def test_ring2d_adjoint_fp32(ring2d):
     assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(Jx) * np.linalg.norm(y)
 
 
+def test_multiband_full_size_sampled_rows_and_columns():
+    """Four bands (0.5, 1, 1.5, 2 MHz) on the full 256x256x64 grid of the
+    128-element ring, in the shape the bench times (the context's default:
+    staged kernels, FP32 node table, J and J^T without the truncation
+    select): sampled rows of J dc for every band and sampled columns of
+    J^T dT summed over the bands, against the oracle's table mode (1e-5) and
+    its quadrature (the tables' own error plus 1e-5)."""
+    w = I.multiband()
+    f = _fftt()
+    say("multiband full size: set-up")
+    ctx = f.context_for_workload(w)
+    ctx.prepare()
+    o = oracle.Oracle.from_workload(w)
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    rng = np.random.default_rng(19)
+    rows = np.sort(rng.choice(w.m, 16, replace=False))
+    x = w.model
+    y = host(ctx.apply_J(dev(x, f.FP32), prec=f.FP32)).reshape(4, w.m)
+    yq, yt_ = o.rows(rows, x), ot.rows(rows, x)
+    act = np.flatnonzero(w.mask)
+    cols = np.sort(rng.choice(act, 1024, replace=False))
+    dT = I.random_vector(4 * w.m, 20) * 1e-7
+    xg = host(ctx.apply_JT(dev(dT, f.FP32), prec=f.FP32))
+    xq, xt = o.cols(cols, dT), ot.cols(cols, dT)
+    ej, ejq, ejtab = rel(y[:, rows], yt_), rel(y[:, rows], yq), rel(yt_, yq)
+    et, etq, ettab = rel(xg[cols], xt), rel(xg[cols], xq), rel(xt, xq)
+    say("multiband rows: vs table %.2e, vs quadrature %.2e (table's own %.2e); cols: vs table "
+        "%.2e, vs quadrature %.2e (table's own %.2e)" % (ej, ejq, ejtab, et, etq, ettab))
+    assert ej < 1e-5 and et < 1e-5
+    assert ejq < ejtab + 1e-5 and etq < ettab + 1e-5
+
+
 # ------------------------------------------------------------ launch shapes
 
 @pytest.mark.parametrize("wpb,unroll,split,staged,stab", [
