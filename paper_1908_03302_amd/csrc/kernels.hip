@@ -466,13 +466,29 @@ __device__ __forceinline__ void dist32(const TxConst& c, double ux, double uy, d
     delta = nf * __builtin_amdgcn_rcpf(Rx + c.D0f);
 }
 
-// FP64 path: plain distances (FP64 leaves no cancellation that matters).
+// FP64 path: plain distances (FP64 leaves no cancellation that matters),
+// returned as delta = R_x - D0f and 1/R_x.  R_x and 1/R_x come together from
+// the hardware reciprocal square root estimate y (relative error below
+// 2^-23) and two steps of Goldschmidt's coupled iteration on g ~ sqrt(s),
+// h ~ 1/(2 sqrt(s)): r = 1/2 - g h, g += g r, h += h r.  Each step squares the
+// relative error, so two reach the precision of a double to a few ulp; no
+// division and no range scaling (s is a squared distance of order 1e-4 m^2,
+// far from the limits of the format).
 __device__ __forceinline__ void dist64(const TxConst& c, double ux, double uy, double uz,
-                                       double uu, double& delta, double& Rx) {
+                                       double uu, double& delta, double& inv_r) {
     const double n = fma(c.d2x, ux, fma(c.d2y, uy, fma(c.d2z, uz, uu + c.cq)));
     const double D = (double)c.D0f;
-    Rx = sqrt(fma(D, D, n));
-    delta = Rx - D;
+    const double s = fma(D, D, n);
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, h = 0.5 * y;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double r = fma(-g, h, 0.5);
+        g = fma(g, r, g);
+        h = fma(h, r, h);
+    }
+    delta = g - D;
+    inv_r = h + h;
 }
 
 // Table coordinate x = R / dR clamped to [0, n-1] (v_med3; a NaN maps into
@@ -735,6 +751,27 @@ __device__ __forceinline__ int64_t wave_tile() {
     return (int64_t)__builtin_amdgcn_readfirstlane(t);
 }
 
+// The entry lists and the per-(tile, transducer) constants are read-only in
+// every kernel that reads them.  Loading them through the constant address
+// space states it, so these wave-uniform loads stay on the scalar path also in
+// the J kernels, whose stores inside the entry loop would otherwise turn them
+// into vector loads followed by readfirstlane.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+using ConstU4 = const __attribute__((address_space(4))) u32x4;
+using ConstU2 = const __attribute__((address_space(4))) u32x2;
+__device__ __forceinline__ Entry entry_at(const Entry* ents, int64_t e) {
+    return __builtin_bit_cast(Entry, ((ConstU4*)(ents + e))[0]);
+}
+__device__ __forceinline__ TxConst tx_at(const TxConst* row, int q) {
+    struct Words { u32x2 w[5]; } v;
+    static_assert(sizeof(Words) == sizeof(TxConst), "TxConst words");
+    ConstU2* p = (ConstU2*)(row + q);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v.w[k] = p[k];
+    return __builtin_bit_cast(TxConst, v);
+}
+
 // Source part of U consecutive entries: recomputed only when the source
 // changes (entries are sorted by source, receiver within a tile).
 template <int U, class F, class Dist>
@@ -746,7 +783,7 @@ __device__ __forceinline__ void source_parts(const Entry (&E)[U], const TxConst*
         const int s = (int)(E[u].sr & 0xffffu);
         if (s != prev) {
             prev = s;
-            dist(row[s], V.ux, V.uy, V.uz, V.uu, ds, as);
+            dist(tx_at(row, s), V.ux, V.uy, V.uz, V.uu, ds, as);
         }
         dsu[u] = ds;
         asu[u] = as;
@@ -763,7 +800,7 @@ __device__ __forceinline__ void jt32_step(const ApplyArgs& A, const TabT* st,
                                           float& acc) {
     Entry E[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) E[u] = ents[e + u];
+    for (int u = 0; u < U; ++u) E[u] = entry_at(ents, e + u);
     float wu[U][NB];
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -772,7 +809,7 @@ __device__ __forceinline__ void jt32_step(const ApplyArgs& A, const TabT* st,
     float dsu[U], rssu[U], dr[U], rsr[U];
     source_parts<U>(E, row, V, prev, ds, rss, dsu, rssu, dist32);
 #pragma unroll
-    for (int u = 0; u < U; ++u) dist32(row[E[u].sr >> 16], V.ux, V.uy, V.uz, V.uu, dr[u], rsr[u]);
+    for (int u = 0; u < U; ++u) dist32(tx_at(row, (int)(E[u].sr >> 16)), V.ux, V.uy, V.uz, V.uu, dr[u], rsr[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const float R = (dsu[u] + dr[u]) + E[u].R0hi;
@@ -813,11 +850,11 @@ __device__ __forceinline__ void j32_step(const ApplyArgs& A, const TabT* st,
                                          int& prev, float& ds, float& rss) {
     Entry E[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) E[u] = ents[e + u];
+    for (int u = 0; u < U; ++u) E[u] = entry_at(ents, e + u);
     float dsu[U], rssu[U], dr[U], rsr[U];
     source_parts<U>(E, row, V, prev, ds, rss, dsu, rssu, dist32);
 #pragma unroll
-    for (int u = 0; u < U; ++u) dist32(row[E[u].sr >> 16], V.ux, V.uy, V.uz, V.uu, dr[u], rsr[u]);
+    for (int u = 0; u < U; ++u) dist32(tx_at(row, (int)(E[u].sr >> 16)), V.ux, V.uy, V.uz, V.uu, dr[u], rsr[u]);
     float R[U], t[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -854,21 +891,21 @@ __global__ __launch_bounds__(1024) void k_j32(ApplyArgs A) {
         j32_step<NB, TabT, 1>(A, st, A.ents, row, part, V, xv, nm1, lane, e, prev, ds, rss);
 }
 
-// FP64 counterparts (Rx carried instead of 1/Rx).
+// FP64 counterparts.
 template <int NB, int U>
 __device__ __forceinline__ void jt64_step(const ApplyArgs& A, const double2* st,
                                           const Entry* __restrict__ ents,
                                           const TxConst* __restrict__ row,
                                           const double* __restrict__ w, const LaneVox& V,
                                           double nm1, int64_t e, int& prev, double& ds,
-                                          double& Rs, double& acc) {
+                                          double& gs, double& acc) {
     Entry E[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) E[u] = ents[e + u];
-    double dsu[U], Rsu[U], dr[U], Rr[U];
-    source_parts<U>(E, row, V, prev, ds, Rs, dsu, Rsu, dist64);
+    for (int u = 0; u < U; ++u) E[u] = entry_at(ents, e + u);
+    double dsu[U], gsu[U], dr[U], gr[U];
+    source_parts<U>(E, row, V, prev, ds, gs, dsu, gsu, dist64);
 #pragma unroll
-    for (int u = 0; u < U; ++u) dist64(row[E[u].sr >> 16], V.ux, V.uy, V.uz, V.uu, dr[u], Rr[u]);
+    for (int u = 0; u < U; ++u) dist64(tx_at(row, (int)(E[u].sr >> 16)), V.ux, V.uy, V.uz, V.uu, dr[u], gr[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const double R = (dsu[u] + dr[u]) + ((double)E[u].R0hi + (double)E[u].R0lo);
@@ -876,7 +913,7 @@ __device__ __forceinline__ void jt64_step(const ApplyArgs& A, const double2* st,
 #pragma unroll
         for (int b = 0; b < NB; ++b)
             hw = fma(lookup(st + b * A.ntab, R, A.inv_dr64[b], nm1), w[b * A.M + E[u].p], hw);
-        acc += hw / (Rsu[u] * Rr[u]);
+        acc = fma(hw, gsu[u] * gr[u], acc);
     }
 }
 
@@ -891,11 +928,11 @@ __global__ __launch_bounds__(1024) void k_jt64(ApplyArgs A) {
     const TxConst* __restrict__ row = A.txc + a * A.n_tx;
     const double* __restrict__ w = static_cast<const double*>(A.w);
     const double nm1 = (double)(A.ntab - 1);
-    double acc = 0.0, ds = 0.0, Rs = 1.0;
+    double acc = 0.0, ds = 0.0, gs = 0.0;
     int prev = -1;
     int64_t e = e0;
-    for (; e + U <= e1; e += U) jt64_step<NB, U>(A, st, A.ents, row, w, V, nm1, e, prev, ds, Rs, acc);
-    for (; e < e1; ++e) jt64_step<NB, 1>(A, st, A.ents, row, w, V, nm1, e, prev, ds, Rs, acc);
+    for (; e + U <= e1; e += U) jt64_step<NB, U>(A, st, A.ents, row, w, V, nm1, e, prev, ds, gs, acc);
+    for (; e < e1; ++e) jt64_step<NB, 1>(A, st, A.ents, row, w, V, nm1, e, prev, ds, gs, acc);
     store_voxel(A, V, acc, s_acc);
 }
 
@@ -905,19 +942,19 @@ __device__ __forceinline__ void j64_step(const ApplyArgs& A, const double2* st,
                                          const TxConst* __restrict__ row,
                                          double* __restrict__ part, const LaneVox& V, double xv,
                                          double nm1, int lane, int64_t e, int& prev, double& ds,
-                                         double& Rs) {
+                                         double& gs) {
     Entry E[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) E[u] = ents[e + u];
-    double dsu[U], Rsu[U], dr[U], Rr[U];
-    source_parts<U>(E, row, V, prev, ds, Rs, dsu, Rsu, dist64);
+    for (int u = 0; u < U; ++u) E[u] = entry_at(ents, e + u);
+    double dsu[U], gsu[U], dr[U], gr[U];
+    source_parts<U>(E, row, V, prev, ds, gs, dsu, gsu, dist64);
 #pragma unroll
-    for (int u = 0; u < U; ++u) dist64(row[E[u].sr >> 16], V.ux, V.uy, V.uz, V.uu, dr[u], Rr[u]);
+    for (int u = 0; u < U; ++u) dist64(tx_at(row, (int)(E[u].sr >> 16)), V.ux, V.uy, V.uz, V.uu, dr[u], gr[u]);
     double R[U], t[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         R[u] = (dsu[u] + dr[u]) + ((double)E[u].R0hi + (double)E[u].R0lo);
-        t[u] = xv / (Rsu[u] * Rr[u]);
+        t[u] = (gsu[u] * xv) * gr[u];
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -940,13 +977,13 @@ __global__ __launch_bounds__(1024) void k_j64(ApplyArgs A) {
     double* __restrict__ part = static_cast<double*>(A.out);
     const double xv = V.act ? static_cast<const double*>(A.x)[A.nxy ? V.vidx % A.nxy : V.vidx] : 0.0;
     const double nm1 = (double)(A.ntab - 1);
-    double ds = 0.0, Rs = 1.0;
+    double ds = 0.0, gs = 0.0;
     int prev = -1;
     int64_t e = e0;
     for (; e + U <= e1; e += U)
-        j64_step<NB, U>(A, st, A.ents, row, part, V, xv, nm1, lane, e, prev, ds, Rs);
+        j64_step<NB, U>(A, st, A.ents, row, part, V, xv, nm1, lane, e, prev, ds, gs);
     for (; e < e1; ++e)
-        j64_step<NB, 1>(A, st, A.ents, row, part, V, xv, nm1, lane, e, prev, ds, Rs);
+        j64_step<NB, 1>(A, st, A.ents, row, part, V, xv, nm1, lane, e, prev, ds, gs);
 }
 
 // One wavefront per tile, waves_per_block tiles per workgroup sharing the
@@ -1063,11 +1100,7 @@ struct StepEntries {
 };
 
 // Transducer indices are returned relative to the staged block's first one.
-// The entry lists are read-only during every kernel that reads them; reading
-// through the constant address space states it, so the compiler keeps these
-// wave-uniform loads on the scalar path even in kernels that store elsewhere.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-using ConstU4 = const __attribute__((address_space(4))) u32x4;
+// The entries are read through the constant address space (see entry_at).
 
 template <int U>
 __device__ __forceinline__ StepEntries<U> load_entries(const Entry* __restrict__ ents, int64_t e,
