@@ -1599,7 +1599,7 @@ hipError_t launch_group_fill(hipStream_t s, const int64_t* tptr, const Entry* en
     return hipGetLastError();
 }
 
-constexpr int kReduceWaves = 16;
+constexpr int kReduceWaves = 8;
 
 // Each 64-pair group is split into S slices of its descriptor list (one
 // workgroup each, so that small pair counts still fill the device); a slice
@@ -1625,18 +1625,33 @@ __global__ __launch_bounds__(64 * kReduceWaves) void k_reduce(
         double acc = 0.0;
         int64_t k = k0;
         // 8 descriptors per step: their gathers are issued together (the
-        // index is always valid, absent pairs add zero), summed in order
+        // index is always valid, absent pairs add zero), summed in order.
+        // The next step's descriptors are requested once this step's gathers
+        // are in flight, so the two latencies overlap.
+        RunDesc dn[8];
+        if (k + 8 <= k1) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) dn[u] = desc[k + u];
+        }
         for (; k + 8 <= k1; k += 8) {
+            RunDesc d[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) d[u] = dn[u];
             T v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const RunDesc d = desc[k + u];
-                const bool on = (d.mask >> lane) & 1ull;
-                const T x = pb[d.start + (on ? __popcll(d.mask & below) : 0)];
-                v[u] = on ? x : (T)0;
+                const bool on = (d[u].mask >> lane) & 1ull;
+                v[u] = pb[d[u].start + (on ? __popcll(d[u].mask & below) : 0)];
+            }
+            if (k + 16 <= k1) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) dn[u] = desc[k + 8 + u];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc += (double)v[u];
+            for (int u = 0; u < 8; ++u) {
+                const bool on = (d[u].mask >> lane) & 1ull;
+                acc += on ? (double)v[u] : 0.0;
+            }
         }
         for (; k < k1; ++k) {
             const RunDesc d = desc[k];
@@ -1668,10 +1683,14 @@ __global__ void k_reduce_final(const double* __restrict__ red, int64_t Mk, int64
     for (int32_t j = kptr[p]; j < kptr[p + 1]; ++j) dT[b * M + kidx[j]] = y;
 }
 
+// As many (group, slice) workgroups as are resident at once on the device
+// (four 512-thread workgroups per CU), rounded down so that they all start
+// in one wave of dispatch: a second, partly filled wave would cost almost a
+// whole latency-bound pass.
 int reduce_slices(int64_t Mk, int n_cu) {
     const int64_t G = (Mk + 63) / 64;
-    const int64_t want = (2 * (int64_t)std::max(n_cu, 1) + G - 1) / std::max<int64_t>(G, 1);
-    return (int)std::min<int64_t>(std::max<int64_t>(want, 1), 16);
+    const int64_t want = 4 * (int64_t)std::max(n_cu, 1) / std::max<int64_t>(G, 1);
+    return (int)std::min<int64_t>(std::max<int64_t>(want, 1), 64);
 }
 
 hipError_t launch_reduce(hipStream_t s, bool fp64, const void* part, int64_t nnz,
