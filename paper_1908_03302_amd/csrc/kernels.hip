@@ -1783,12 +1783,35 @@ __device__ __forceinline__ void store_psf_block(const ApplyArgs& A, int64_t t, c
     }
 }
 
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// bf16(a) | bf16(b) << 16, both rounded to nearest even in one conversion.
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    const f32x2v v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
+}
+
+// Splits a pair of floats x ~ hi + lo (hi = bf16(x), lo = bf16(x - hi)) into
+// packed words: hi and lo of a in the low halves, of b in the high halves.
+__device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t& hi, uint32_t& lo) {
+    hi = pack_bf16x2(a, b);
+    lo = pack_bf16x2(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
+}
+
+// The same split of one float as one word: hi in the low half, lo in the high
+// half (what split_bf16x2 gives for the float in either position).
+__device__ __forceinline__ uint32_t split_word(float x) {
+    const uint32_t hi = pack_bf16x2(x, 0.0f) & 0xffffu;
+    return hi | (pack_bf16x2(x - __uint_as_float(hi << 16), 0.0f) << 16);
+}
+
 template <int NB, class TabT>
 __global__ __launch_bounds__(64) void k_psf_cols(ApplyArgs A, const int32_t* __restrict__ ptile,
                                                  const int32_t* __restrict__ plane,
                                                  const double* __restrict__ C,
                                                  const int32_t* __restrict__ kptr, double s2,
-                                                 float* __restrict__ W, int64_t ldw) {
+                                                 float* __restrict__ W, int64_t ldw, bool packed) {
     const int k = blockIdx.x;
     const int64_t a = ptile[k];
     const int l = plane[k];
@@ -1811,9 +1834,14 @@ __global__ __launch_bounds__(64) void k_psf_cols(ApplyArgs A, const int32_t* __r
         const double m = (double)(kptr[E.p + 1] - kptr[E.p]);
         const float f = (float)(c * c * m * s2) * (gs * gr);
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            W[((int64_t)b * A.M + E.p) * ldw + k] =
-                lookup(tab + b * A.ntab, R, A.inv_dr[b], nm1) * f;
+        for (int b = 0; b < NB; ++b) {
+            const float v = lookup(tab + b * A.ntab, R, A.inv_dr[b], nm1) * f;
+            const int64_t o = ((int64_t)b * A.M + E.p) * ldw + k;
+            if (packed)
+                reinterpret_cast<uint32_t*>(W)[o] = split_word(v);
+            else
+                W[o] = v;
+        }
     }
 }
 
@@ -1851,7 +1879,8 @@ inline int64_t xcd_grid(int64_t n) {
     return (n + round - 1) / round * round;
 }
 
-// Weights of the PSF contractions, W [nb][M][ldw] FP32: wrow is a wave's
+// Weights of the PSF contractions, W [nb][M][ldw] FP32 (split words for the
+// split-BF16 contraction, read through the same path): wrow is a wave's
 // block of columns in one band (uniform), the gather for kernel pair p and
 // the lane's column one 24-bit multiply-add on a 32-bit byte offset (the
 // launches require M ldw < 2^30 and ldw < 2^22).  The chunk producers give
@@ -2015,7 +2044,8 @@ __global__ __launch_bounds__(1024) void k_psf32(ApplyArgs A, const float* __rest
 // FP32 K = 2 steps.  Norm-wise error ~3e-6 on PSF operands.  H is split once,
 // when it is produced (all wavefronts reuse it), and kept voxel-major in LDS
 // as [voxel][entry] BF16 rows of CH + 8 (16-byte aligned, conflict-free
-// 16-byte reads of a lane's 8 K-values); W is split in registers.  Operand
+// 16-byte reads of a lane's 8 K-values); W arrives split by its producers
+// (split_word: one word per value) and is regrouped in registers.  Operand
 // layout (32x32x16): A[m][k] in lane m + 32 (k / 8), element k % 8; B[k][n]
 // in lane n + 32 (k / 8), element k % 8.
 
@@ -2026,22 +2056,6 @@ constexpr int psfb3_chunk(int nb) { return nb == 1 ? 64 : (nb == 2 ? 32 : 16); }
 
 __device__ __forceinline__ uint32_t bf16_bits(__bf16 h) {
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
-}
-
-typedef float f32x2v __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
-
-// bf16(a) | bf16(b) << 16, both rounded to nearest even in one conversion.
-__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-    const f32x2v v = {a, b};
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
-}
-
-// Splits a pair of floats x ~ hi + lo (hi = bf16(x), lo = bf16(x - hi)) into
-// packed words: hi and lo of a in the low halves, of b in the high halves.
-__device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t& hi, uint32_t& lo) {
-    hi = pack_bf16x2(a, b);
-    lo = pack_bf16x2(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
 }
 
 // H of entries c0 .. c0 + CH - 1 split into hi / lo BF16 rows; waves take
@@ -2125,7 +2139,7 @@ __global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __rest
         const int* pb = pbuf + buf * CH;
         // this chunk's weights (requested first), the next chunk's H, then
         // the split and the matrix-core steps
-        float wv[NB][CH / 16][8];
+        uint32_t wv[NB][CH / 16][8];
         if (active) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)
@@ -2133,16 +2147,18 @@ __global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __rest
                 for (int s = 0; s < CH / 16; ++s)
 #pragma unroll
                     for (int i = 0; i < 8; ++i)
-                        wv[b][s][i] = psf_weight(W + ((int64_t)b * A.M) * ldw + k0,
-                                                 pb[16 * s + 8 * up + i], ldw4, col4);
+                        wv[b][s][i] = __float_as_uint(
+                            psf_weight(W + ((int64_t)b * A.M) * ldw + k0,
+                                       pb[16 * s + 8 * up + i], ldw4, col4));
         }
         if (c0 + CH < t1)
             psfb3_chunk_h<NB, CH>(A, st, sx, hbuf + (buf ^ 1) * 2 * HB,
                                   hbuf + (buf ^ 1) * 2 * HB + HB, pbuf + (buf ^ 1) * CH, c0 + CH,
                                   t0, t1, nm1, wave, W_, lane);
         if (active) {
-            // the weights split once they are needed (their loads stay in
-            // flight over the H evaluation above)
+            // the split weights regrouped into hi and lo operands once they
+            // are needed (their loads stay in flight over the H evaluation
+            // above): one byte permutation per two values
             bf16x8 wh[NB][CH / 16], wl[NB][CH / 16];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
@@ -2151,10 +2167,10 @@ __global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __rest
                     u32x4 h, l;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        uint32_t hk, lk;
-                        split_bf16x2(wv[b][s][2 * k], wv[b][s][2 * k + 1], hk, lk);
-                        h[k] = hk;
-                        l[k] = lk;
+                        h[k] = __builtin_amdgcn_perm(wv[b][s][2 * k + 1], wv[b][s][2 * k],
+                                                     0x05040100u);
+                        l[k] = __builtin_amdgcn_perm(wv[b][s][2 * k + 1], wv[b][s][2 * k],
+                                                     0x07060302u);
                     }
                     wh[b][s] = __builtin_bit_cast(bf16x8, h);
                     wl[b][s] = __builtin_bit_cast(bf16x8, l);
@@ -2384,17 +2400,18 @@ int hess_slices(int64_t Mk, int n_cu) {
     return (int)std::min<int64_t>(std::max<int64_t>(want, 1), 64);
 }
 
-// J^T weights of the Hessian product: W[b][p][k] = m_p C_p^2 scale sum_s red.
+// J^T weights of the Hessian product: W[b][p][k] = m_p C_p^2 scale sum_s red,
+// split for the contraction (split_word).
 __global__ void k_hess_weights(const double* __restrict__ red, int S, int64_t Mk, int l, int nb,
                                const double* __restrict__ C, const int32_t* __restrict__ kptr,
-                               double scale, float* __restrict__ W, int64_t ldw) {
+                               double scale, uint32_t* __restrict__ W, int64_t ldw) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)nb * Mk * l) return;
     const int64_t k = i % l, p = (i / l) % Mk, b = i / (l * Mk);
     double t = 0.0;
     for (int s = 0; s < S; ++s) t += red[((b * S + s) * Mk + p) * l + k];
     const double m = (double)(kptr[p + 1] - kptr[p]);
-    W[(b * Mk + p) * ldw + k] = (float)(m * C[p] * C[p] * scale * t);
+    W[(b * Mk + p) * ldw + k] = split_word((float)(m * C[p] * C[p] * scale * t));
 }
 
 size_t jmb3_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
@@ -2446,7 +2463,7 @@ static hipError_t launch_hess_nb(hipStream_t s, int tabfmt, const ApplyArgs& a, 
     if (e != hipSuccess) return e;
     const int64_t nw = (int64_t)NB * a.M * l;
     hipLaunchKernelGGL(k_hess_weights, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, red, S,
-                       a.M, l, NB, C, kptr, scale, W, ldw);
+                       a.M, l, NB, C, kptr, scale, reinterpret_cast<uint32_t*>(W), ldw);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lp = psfb3_lds_bytes(NB, a.ntab, tabfmt, a.n_tx);
@@ -2506,8 +2523,10 @@ static hipError_t launch_psf_nb(hipStream_t s, int tabfmt, const ApplyArgs& a,
     // BF16 table only enters through the contraction
     ApplyArgs ac = a;
     ac.tab = col_tab;
+    // the split-BF16 contraction takes its weights already split
+    const bool packed = b3 && NB <= 3;
     hipLaunchKernelGGL((k_psf_cols<NB, float2>), dim3((unsigned)n), dim3(64), 0, s, ac, ptile,
-                       plane, C, kptr, s2, W, ldw);
+                       plane, C, kptr, s2, W, ldw, packed);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess || a.n_act == 0) return err;
     if (!psf_weights_fit(a.M, ldw)) return hipErrorInvalidValue;
