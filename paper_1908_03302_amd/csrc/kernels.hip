@@ -2058,48 +2058,89 @@ __device__ __forceinline__ uint32_t bf16_bits(__bf16 h) {
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 
-// H of entries c0 .. c0 + CH - 1 split into hi / lo BF16 rows; waves take
-// pairs of entries, each lane (voxel) writes one packed dword per pair.
+// Entry pairs a wave evaluates together in one batch of a chunk (one with
+// several bands, within the registers).
+template <int NB>
+constexpr int psfb3_pb() { return NB == 1 ? kProduceBatch / 2 : 1; }
+
+// Index of slot u of the batch starting at pair j0 of chunk c0, and whether it
+// is a real entry (slots past the chunk or the tile read entry t0 instead).
+template <int CH>
+__device__ __forceinline__ int64_t psfb3_slot(int64_t c0, int j0, int u, int W_, int64_t t0,
+                                              int64_t t1, bool& ok) {
+    const int i2 = j0 + (u / 2) * W_;
+    const int64_t e = c0 + 2 * i2 + (u & 1);
+    ok = i2 < CH / 2 && e < t1;
+    return ok ? e : t0;
+}
+
+// H of one batch of entry pairs split into hi / lo BF16 rows; each lane
+// (voxel) writes one packed dword per pair.
+template <int NB, int CH, class TabT>
+__device__ __forceinline__ void psfb3_batch_h(const ApplyArgs& A, const TabT* st, const float2* sx,
+                                              uint32_t* hh, uint32_t* hl, int* pb,
+                                              const Entry (&E)[2 * psfb3_pb<NB>()],
+                                              const bool (&ok)[2 * psfb3_pb<NB>()], int j0,
+                                              float nm1, int W_, int lane) {
+    constexpr int RS = (CH + 8) / 2;   // row stride in dwords
+    constexpr int PB = psfb3_pb<NB>();
+#pragma unroll
+    for (int v = 0; v < PB; ++v) {
+        const int i2 = j0 + v * W_;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            float h0 = psf_h(A, st, sx, E[2 * v], b, nm1, lane);
+            float h1 = psf_h(A, st, sx, E[2 * v + 1], b, nm1, lane);
+            h0 = ok[2 * v] ? h0 : 0.0f;
+            h1 = ok[2 * v + 1] ? h1 : 0.0f;
+            uint32_t wh, wl;
+            split_bf16x2(h0, h1, wh, wl);
+            const int o = (b * 64 + lane) * RS + i2;
+            if (i2 < CH / 2) {
+                hh[o] = wh;
+                hl[o] = wl;
+            }
+        }
+        if (lane == 0 && i2 < CH / 2) {
+            pb[2 * i2] = ok[2 * v] ? E[2 * v].p : 0;
+            pb[2 * i2 + 1] = ok[2 * v + 1] ? E[2 * v + 1].p : 0;
+        }
+    }
+}
+
+// H of entries c0 .. c0 + CH - 1; waves take batches of entry pairs, their
+// entries read by scalar loads.
 template <int NB, int CH, class TabT>
 __device__ __forceinline__ void psfb3_chunk_h(const ApplyArgs& A, const TabT* st, const float2* sx,
                                               uint32_t* hh, uint32_t* hl, int* pb, int64_t c0,
                                               int64_t t0, int64_t t1, float nm1, int wave,
                                               int W_, int lane) {
-    constexpr int RS = (CH + 8) / 2;   // row stride in dwords
-    // entry pairs per batch (one with several bands, within the registers)
-    constexpr int PB = NB == 1 ? kProduceBatch / 2 : 1;
+    constexpr int PB = psfb3_pb<NB>();
     for (int j0 = wave; j0 < CH / 2; j0 += PB * W_) {
         Entry E[2 * PB];
         bool ok[2 * PB];
 #pragma unroll
-        for (int u = 0; u < 2 * PB; ++u) {
-            const int i2 = j0 + (u / 2) * W_;
-            const int64_t e = c0 + 2 * i2 + (u & 1);
-            ok[u] = i2 < CH / 2 && e < t1;
-            E[u] = A.ents[ok[u] ? e : t0];
-        }
+        for (int u = 0; u < 2 * PB; ++u) E[u] = A.ents[psfb3_slot<CH>(c0, j0, u, W_, t0, t1, ok[u])];
+        psfb3_batch_h<NB, CH>(A, st, sx, hh, hl, pb, E, ok, j0, nm1, W_, lane);
+    }
+}
+
+// When one batch per wave covers a chunk, the wave's entries of a chunk are
+// requested one chunk ahead, through the vector memory path (the byte offset
+// is moved to a VGPR, so the loads are not turned into scalar loads): they
+// are counted by vmcnt, in order with the weight loads, and a scalar load in
+// flight would make every LDS wait in between wait for it as well.
+template <int NB, int CH>
+__device__ __forceinline__ void psfb3_prefetch(const ApplyArgs& A, int64_t c0, int64_t t0,
+                                               int64_t t1, int wave, int W_,
+                                               u32x4 (&ev)[2 * psfb3_pb<NB>()]) {
+    const char* base = reinterpret_cast<const char*>(A.ents + t0);
 #pragma unroll
-        for (int v = 0; v < PB; ++v) {
-            const int i2 = j0 + v * W_;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                float h0 = psf_h(A, st, sx, E[2 * v], b, nm1, lane);
-                float h1 = psf_h(A, st, sx, E[2 * v + 1], b, nm1, lane);
-                h0 = ok[2 * v] ? h0 : 0.0f;
-                h1 = ok[2 * v + 1] ? h1 : 0.0f;
-                uint32_t wh, wl;
-                split_bf16x2(h0, h1, wh, wl);
-                const int o = (b * 64 + lane) * RS + i2;
-                if (i2 < CH / 2) {
-                    hh[o] = wh;
-                    hl[o] = wl;
-                }
-            }
-            if (lane == 0 && i2 < CH / 2) {
-                pb[2 * i2] = ok[2 * v] ? E[2 * v].p : 0;
-                pb[2 * i2 + 1] = ok[2 * v + 1] ? E[2 * v + 1].p : 0;
-            }
-        }
+    for (int u = 0; u < 2 * psfb3_pb<NB>(); ++u) {
+        bool ok;
+        const int64_t e = psfb3_slot<CH>(c0, wave, u, W_, t0, t1, ok);
+        const uint32_t off = to_vgpr((uint32_t)(e - t0) * (uint32_t)sizeof(Entry));
+        ev[u] = *reinterpret_cast<const u32x4*>(base + off);
     }
 }
 
@@ -2129,6 +2170,11 @@ __global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __rest
     const int up = lane >> 5;
     const uint32_t ldw4 = 4u * (uint32_t)ldw, col4 = 4u * (uint32_t)col;
     f32x16v c_lo = {}, c_hi = {};
+    constexpr int PB = psfb3_pb<NB>();
+    // one batch per wave covers a chunk: entries requested a chunk ahead
+    const bool pre = PB * W_ >= CH / 2;
+    u32x4 ev[2 * PB];
+    if (pre && t0 + CH < t1) psfb3_prefetch<NB, CH>(A, t0 + CH, t0, t1, wave, W_, ev);
     if (t0 < t1)
         psfb3_chunk_h<NB, CH>(A, st, sx, hbuf, hbuf + HB, pbuf, t0, t0, t1, nm1, wave, W_, lane);
     __syncthreads();
@@ -2151,10 +2197,24 @@ __global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __rest
                             psf_weight(W + ((int64_t)b * A.M) * ldw + k0,
                                        pb[16 * s + 8 * up + i], ldw4, col4));
         }
-        if (c0 + CH < t1)
-            psfb3_chunk_h<NB, CH>(A, st, sx, hbuf + (buf ^ 1) * 2 * HB,
-                                  hbuf + (buf ^ 1) * 2 * HB + HB, pbuf + (buf ^ 1) * CH, c0 + CH,
-                                  t0, t1, nm1, wave, W_, lane);
+        if (c0 + CH < t1) {
+            uint32_t* nh = hbuf + (buf ^ 1) * 2 * HB;
+            int* np = pbuf + (buf ^ 1) * CH;
+            if (pre) {
+                Entry E[2 * PB];
+                bool ok[2 * PB];
+#pragma unroll
+                for (int u = 0; u < 2 * PB; ++u) {
+                    psfb3_slot<CH>(c0 + CH, wave, u, W_, t0, t1, ok[u]);
+                    E[u] = __builtin_bit_cast(Entry, ev[u]);
+                }
+                if (c0 + 2 * CH < t1) psfb3_prefetch<NB, CH>(A, c0 + 2 * CH, t0, t1, wave, W_, ev);
+                psfb3_batch_h<NB, CH>(A, st, sx, nh, nh + HB, np, E, ok, wave, nm1, W_, lane);
+            } else {
+                psfb3_chunk_h<NB, CH>(A, st, sx, nh, nh + HB, np, c0 + CH, t0, t1, nm1, wave, W_,
+                                      lane);
+            }
+        }
         if (active) {
             // the split weights regrouped into hi and lo operands once they
             // are needed (their loads stay in flight over the H evaluation
