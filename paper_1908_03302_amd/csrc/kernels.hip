@@ -2301,28 +2301,53 @@ __global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restr
     const int wb = min(32, lp - k0);
     float* __restrict__ pblk = part + (int64_t)k0 * A.nnz;
     // H of a chunk: waves split the entries, lane = voxel, BF16 hi / lo
+    auto produce_from = [&](uint16_t* hh, uint16_t* hl, int i0, const Entry (&E)[kProduceBatch],
+                            const bool (&ok)[kProduceBatch]) {
+#pragma unroll
+        for (int u = 0; u < kProduceBatch; ++u) {
+            const int i = i0 + u * W_;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                float h = psf_h(A, st, sx, E[u], b, nm1, lane);
+                h = ok[u] ? h : 0.0f;
+                const __bf16 hi = (__bf16)h;
+                const int o = ((b * CH + i) * RS) * 2 + lane;
+                if (i < CH) {
+                    hh[o] = __builtin_bit_cast(uint16_t, hi);
+                    hl[o] = __builtin_bit_cast(uint16_t, (__bf16)(h - (float)hi));
+                }
+            }
+        }
+    };
     auto produce = [&](uint16_t* hh, uint16_t* hl, int64_t c0) {
         for (int i0 = wave; i0 < CH; i0 += kProduceBatch * W_) {
             Entry E[kProduceBatch];
             bool ok[kProduceBatch];
             produce_batch<CH>(A, c0, i0, W_, t0, t1, E, ok);
-#pragma unroll
-            for (int u = 0; u < kProduceBatch; ++u) {
-                const int i = i0 + u * W_;
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    float h = psf_h(A, st, sx, E[u], b, nm1, lane);
-                    h = ok[u] ? h : 0.0f;
-                    const __bf16 hi = (__bf16)h;
-                    const int o = ((b * CH + i) * RS) * 2 + lane;
-                    if (i < CH) {
-                        hh[o] = __builtin_bit_cast(uint16_t, hi);
-                        hl[o] = __builtin_bit_cast(uint16_t, (__bf16)(h - (float)hi));
-                    }
-                }
-            }
+            produce_from(hh, hl, i0, E, ok);
         }
     };
+    // one batch per wave covers a chunk: the wave's entries of the next chunk
+    // are requested a chunk ahead through the vector memory path (as in
+    // k_psfb3)
+    const bool pre = kProduceBatch * W_ >= CH;
+    const char* ebase = reinterpret_cast<const char*>(A.ents + t0);
+    u32x4 ev[kProduceBatch];
+    auto slot = [&](int64_t c0, int u, bool& ok) -> int64_t {
+        const int i = wave + u * W_;
+        const int64_t e = c0 + i;
+        ok = i < CH && e < t1;
+        return ok ? e : t0;
+    };
+    auto prefetch = [&](int64_t c0) {
+#pragma unroll
+        for (int u = 0; u < kProduceBatch; ++u) {
+            bool ok;
+            const uint32_t off = to_vgpr((uint32_t)(slot(c0, u, ok) - t0) * (uint32_t)sizeof(Entry));
+            ev[u] = *reinterpret_cast<const u32x4*>(ebase + off);
+        }
+    };
+    if (pre && t0 + CH < t1) prefetch(t0 + CH);
     if (t0 < t1) produce(hb16, hb16 + 2 * HB, t0);
     __syncthreads();
     // this wave's columns of Q on the tile's voxels, split once
@@ -2342,8 +2367,22 @@ __global__ __launch_bounds__(1024) void k_jmb3(ApplyArgs A, const float* __restr
     for (int64_t c0 = t0; c0 < t1; c0 += CH, buf ^= 1) {
         const uint32_t* hh = hbuf + buf * 2 * HB;
         const uint32_t* hl = hh + HB;
-        if (c0 + CH < t1)
-            produce(hb16 + (buf ^ 1) * 4 * HB, hb16 + (buf ^ 1) * 4 * HB + 2 * HB, c0 + CH);
+        if (c0 + CH < t1) {
+            uint16_t* nh = hb16 + (buf ^ 1) * 4 * HB;
+            if (pre) {
+                Entry E[kProduceBatch];
+                bool ok[kProduceBatch];
+#pragma unroll
+                for (int u = 0; u < kProduceBatch; ++u) {
+                    slot(c0 + CH, u, ok[u]);
+                    E[u] = __builtin_bit_cast(Entry, ev[u]);
+                }
+                if (c0 + 2 * CH < t1) prefetch(c0 + 2 * CH);
+                produce_from(nh, nh + 2 * HB, wave, E, ok);
+            } else {
+                produce(nh, nh + 2 * HB, c0 + CH);
+            }
+        }
         if (active) {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
