@@ -288,7 +288,7 @@ struct fftt_ctx {
     // launch shape of the operator kernels
     int waves_per_block = 16;
     int n_cu = 0;
-    int unroll_jt = 2;
+    int unroll_jt = 4;
     int unroll_j = 4;
     int split_jt = 0, split_j = 1;
     int staged = 1;            // use the LDS-staged kernels when they fit
