@@ -1749,8 +1749,9 @@ constexpr size_t kPsfOutLds = 16 * kPsfOutSlot * sizeof(float);
 // 8 (q / 4) + 4 (l / 32) + q % 4 of the half in column l % 32.  Each half
 // goes through the wave's LDS slot so that a store covers 32 voxels of two
 // columns (runs of four x-neighbours) rather than one voxel in each of 32
-// columns a whole volume apart.  Every lane of the wave takes part; the
-// workgroup must be done with the LDS.
+// columns a whole volume apart; with an x extent that is a multiple of four
+// a lane stores a row of four x-neighbours as one float4.  Every lane of the
+// wave takes part; the workgroup must be done with the LDS.
 template <class V>
 __device__ __forceinline__ void store_psf_block(const ApplyArgs& A, int64_t t, const V& c_lo,
                                                 const V& c_hi, int k0, int n, int wave,
@@ -1767,14 +1768,38 @@ __device__ __forceinline__ void store_psf_block(const ApplyArgs& A, int64_t t, c
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        bool inside, act;
-        int64_t vidx, v[3];
-        voxel_of_lane(A, t, col + 32 * h, inside, act, vidx, v);
+        if (A.g.dims[0] % 4 == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+            // rows of four x-neighbours stay inside the grid and 16-byte
+            // aligned (x extent a multiple of four, 16-byte aligned output):
+            // lane = (row r of the half, column c % 8), one float4 store per
+            // row and column
+            const int r = lane & 7, cq = lane >> 3;
+            bool inside, act;
+            int64_t vidx, v[3];
+            voxel_of_lane(A, t, 4 * r + 32 * h, inside, act, vidx, v);
+            const uint32_t m = inside ? *reinterpret_cast<const uint32_t*>(A.mask + vidx) : 0u;
 #pragma unroll
-        for (int it = 0; it < 16; ++it) {
-            const int c = 2 * it + up;
-            const float val = slot[c * 33 + col];
-            if (inside && k0 + c < n) out[(int64_t)(k0 + c) * N + vidx] = act ? val : 0.0f;
+            for (int it = 0; it < 4; ++it) {
+                const int c = 8 * it + cq;
+                const float* sv = slot + c * 33 + 4 * r;
+                float4 q;
+                q.x = (m & 0xffu) ? sv[0] : 0.0f;
+                q.y = (m & 0xff00u) ? sv[1] : 0.0f;
+                q.z = (m & 0xff0000u) ? sv[2] : 0.0f;
+                q.w = (m & 0xff000000u) ? sv[3] : 0.0f;
+                if (inside && k0 + c < n)
+                    *reinterpret_cast<float4*>(out + (int64_t)(k0 + c) * N + vidx) = q;
+            }
+        } else {
+            bool inside, act;
+            int64_t vidx, v[3];
+            voxel_of_lane(A, t, col + 32 * h, inside, act, vidx, v);
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const int c = 2 * it + up;
+                const float val = slot[c * 33 + col];
+                if (inside && k0 + c < n) out[(int64_t)(k0 + c) * N + vidx] = act ? val : 0.0f;
+            }
         }
         // the slot's reads complete before the next half overwrites it
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
