@@ -254,12 +254,13 @@ constexpr int kFillCols = 8;   // vectors per wavefront of k_fill_runs
 
 // Zeroes, in each of n vectors of length N, the index ranges [runs[2 r],
 // runs[2 r] + runs[2 r + 1]): one wavefront per (range, kFillCols vectors),
-// 16-byte stores where range and vector starts are multiples of 4.
+// 16-byte stores where range and vector starts are multiples of 4 and the
+// output is 16-byte aligned.
 __global__ __launch_bounds__(64) void k_fill_runs(float* __restrict__ out, int64_t N, int n,
                                                   const int64_t* __restrict__ runs) {
     const int64_t st = runs[2 * (int64_t)blockIdx.x], len = runs[2 * (int64_t)blockIdx.x + 1];
     const int k0 = (int)blockIdx.y * kFillCols, k1 = min(n, k0 + kFillCols);
-    const bool vec = ((st | len | N) & 3) == 0;
+    const bool vec = ((st | len | N) & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
     for (int k = k0; k < k1; ++k) {
         float* __restrict__ o = out + (int64_t)k * N + st;
         if (vec) {

@@ -108,14 +108,18 @@ def test_psf_batch_ragged_two_bands(ragged_dense, prec_name, wpb):
         "worst rel err vs table oracle %.2e, vs quadrature %.2e (table's own %.2e)" % tuple(worst))
 
 
-def test_psf_batch_mask_holes_stale_output():
+@pytest.mark.parametrize("dims,offset", [((37, 29, 11), 0), ((36, 28, 12), 0),
+                                         ((36, 28, 12), 1)])
+def test_psf_batch_mask_holes_stale_output(dims, offset):
     """A mask with whole 4^3 tiles and single voxels removed inside the
     cylinder (inactive tiles between active ones on every row), written into
     an output buffer full of NaN: every voxel outside the active tiles is
     zeroed by the fill, every voxel inside is written by the contraction, so
-    no stale value survives; active voxels match the oracle's table mode."""
+    no stale value survives; active voxels match the oracle's table mode.
+    An x extent of 36 takes the row-of-four result stores, 37 and an output
+    one float past a 16-byte boundary the per-voxel stores."""
     f = _fftt()
-    g = I.centred_grid((37, 29, 11), 1.0e-3)
+    g = I.centred_grid(dims, 1.0e-3)
     nx, ny, nz = g.dims
     mask = np.asarray(I.cylinder_mask(g, 0.02)).reshape(nz, ny, nx).copy()
     tx_, ty_, tz_ = np.meshgrid(np.arange(nx) // 4, np.arange(ny) // 4, np.arange(nz) // 4,
@@ -133,15 +137,17 @@ def test_psf_batch_mask_holes_stale_output():
     ctx = f.context_for_workload(w)
     act = np.flatnonzero(mask)
     vox = rng.choice(act, 40, replace=False)
-    out = torch.full((len(vox) * w.n,), float("nan"), dtype=torch.float32, device="cuda:0")
+    big = torch.full((len(vox) * w.n + offset,), float("nan"), dtype=torch.float32,
+                     device="cuda:0")
+    out = big[offset:]
     ctx.psf(vox, SIGMA, out=out, prec=f.FP32)
     got = host(out).reshape(len(vox), w.n)
     assert not np.isnan(got).any()
     assert np.all(got[:, mask == 0] == 0.0)
     ref = (Jt.T @ Jt[:, vox]).T / SIGMA ** 2
     e = max(rel(got[k], ref[k]) for k in range(len(vox)))
-    say("mask with holes: %d active of %d voxels, worst rel err vs table oracle %.2e"
-        % (act.size, w.n, e))
+    say("mask with holes %s offset %d: %d active of %d voxels, worst rel err vs table "
+        "oracle %.2e" % (dims, offset, act.size, w.n, e))
     assert e < TOL["FP32"]
 
 
