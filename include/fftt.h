@@ -95,7 +95,12 @@ fftt_status fftt_set_geometry(fftt_ctx *ctx, double c0,
  * output, solves, point-spread functions, low-rank analysis) then have N =
  * nx * ny values; fftt_coverage and the Jacobi preconditioner return
  * FFTT_E_UNSUPPORTED (their absolute values and squares do not commute with
- * the layer sum); fftt_work_count counts prism evaluations.
+ * the layer sum); fftt_work_count counts prism evaluations.  BF16 tables
+ * are not offered in this mode: apply_J, apply_JT, solve, psf,
+ * hessian_apply, hessian_lowrank and autotune return FFTT_E_UNSUPPORTED for
+ * FFTT_FP32_BF16TABLE (the layer sum adds Fresnel zones of alternating
+ * sign, so the table's BF16 rounding is not averaged away and J^T would sit
+ * at the 1e-3 bound of that precision).
  *   origin, spacing, dims: in-plane grid (pixel (0,0) centre, x fastest);
  *   active_mask: host [ny][nx] or NULL; 1 <= nz <= 4096.  Otherwise as
  *   fftt_set_geometry, which switches back to 3D. */
@@ -228,7 +233,7 @@ typedef struct {
 fftt_status fftt_solve(fftt_ctx *ctx, const fftt_solve_opts *opts,
                        const void *d_obs, void *x, fftt_solve_report *rep);
 
-/* Sensitivity coverage (Sec. IV: the absolute values of the operator
+/* Sensitivity coverage (Sec. III: the absolute values of the operator
  * summed over its rows) and the diagonal of the Gauss-Newton Hessian:
  *   kind 0: out_j = sum_b sum_i |J^b_ij|;   kind 1: out_j = sum_b sum_i (J^b_ij)^2
  * over every caller pair i (pairs sharing a row of J each count) and band b.
@@ -330,7 +335,7 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *     BF16-table operators with table evaluation, 1 to 3 bands, 3D, LDS),
  *     0 = one J and one J^T per vector.
  *   FFTT_TUNE_RECIPROCITY: 1 (default) = a pair (s, r) and its reverse
- *     (r, s) have the same row of J (source-receiver reciprocity, Sec. II-B;
+ *     (r, s) have the same row of J (source-receiver reciprocity of Sec. II;
  *     the detour and L are symmetric), so each unordered pair is evaluated
  *     once: J writes the row to both, J^T uses the summed data; 0 = every
  *     ordered pair is evaluated (only exact repeats share a row).  Outputs

@@ -547,7 +547,18 @@ fftt_status ensure_ready(fftt_ctx* c) {
     return FFTT_OK;
 }
 
-// ---- randomized eigensolver for H = J^T J / sigma^2 (Sec. II-E) ----
+// BF16 tables are not offered in the 2D approximation (eq. forward_2D): the
+// z integral sums Fresnel zones of alternating sign, so the per-layer
+// rounding of a BF16 table is not averaged away and J^T of sign-random data
+// comes out near the 1e-3 bound of that precision.
+fftt_status check_plane_precision(fftt_ctx* c, fftt_precision prec) {
+    if (c->nxy2 && prec == FFTT_FP32_BF16TABLE)
+        FFTT_FAIL(c, FFTT_E_UNSUPPORTED,
+                  "the 2D approximation takes FFTT_FP64 or FFTT_FP32, not BF16 tables");
+    return FFTT_OK;
+}
+
+// ---- randomized eigensolver for H = J^T J / sigma^2 (Sec. II-D) ----
 
 // y = H x = J^T (J x) / sigma^2; dT: scratch [nb][M].
 fftt_status hess_apply(fftt_ctx* c, fftt_precision prec, double isg2, const void* x, void* dT,
@@ -991,6 +1002,8 @@ fftt_status fftt_hessian_lowrank(fftt_ctx* c, fftt_precision prec, double noise_
     if (!(noise_sigma > 0) || !std::isfinite(noise_sigma)) FFTT_BAD(c, "lowrank: noise_sigma must be > 0");
     fftt_status st = ensure_ready(c);
     if (st != FFTT_OK) return st;
+    st = check_plane_precision(c, prec);
+    if (st != FFTT_OK) return st;
     const bool fp64 = prec == FFTT_FP64;
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
     const int64_t N = c->Nm, D = (int64_t)c->nb * c->M;
@@ -1060,6 +1073,8 @@ fftt_status fftt_hessian_apply(fftt_ctx* c, fftt_precision prec, double noise_si
         FFTT_BAD(c, "hessian_apply: noise_sigma must be > 0");
     fftt_status st = ensure_ready(c);
     if (st != FFTT_OK) return st;
+    st = check_plane_precision(c, prec);
+    if (st != FFTT_OK) return st;
     const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
     FFTT_HIP(c, c->d_solve.alloc((size_t)c->nb * c->M * es));
     return hess_block(c, prec, 1.0 / (noise_sigma * noise_sigma), x, y, n_vec, c->d_solve.p);
@@ -1113,6 +1128,8 @@ fftt_status fftt_apply_J(fftt_ctx* c, fftt_precision prec, const void* dc, void*
     if (!dc || !dT || n_rhs < 1) FFTT_BAD(c, "apply_J: null buffer or n_rhs < 1");
     fftt_status st = ensure_ready(c);
     if (st != FFTT_OK) return st;
+    st = check_plane_precision(c, prec);
+    if (st != FFTT_OK) return st;
     const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
     for (int32_t r = 0; r < n_rhs; ++r) {
         st = apply_J_one(c, prec, static_cast<const char*>(dc) + (size_t)r * c->Nm * es,
@@ -1128,6 +1145,8 @@ fftt_status fftt_apply_JT(fftt_ctx* c, fftt_precision prec, const void* dT, void
     if (prec < FFTT_FP64 || prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "unknown precision");
     if (!dc || !dT || n_rhs < 1) FFTT_BAD(c, "apply_JT: null buffer or n_rhs < 1");
     fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    st = check_plane_precision(c, prec);
     if (st != FFTT_OK) return st;
     const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
     for (int32_t r = 0; r < n_rhs; ++r) {
@@ -1187,6 +1206,8 @@ fftt_status fftt_autotune(fftt_ctx* c, fftt_precision prec, double max_seconds) 
     if (prec < FFTT_FP64 || prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "autotune: unknown precision");
     if (!(max_seconds > 0)) FFTT_BAD(c, "autotune: max_seconds must be > 0");
     fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    st = check_plane_precision(c, prec);
     if (st != FFTT_OK) return st;
     const bool fp64 = prec == FFTT_FP64;
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
@@ -1406,6 +1427,8 @@ static fftt_status solve_impl(fftt_ctx* c, const fftt_solve_opts* o, const void*
     if (o->precond && o->method != 0) FFTT_BAD(c, "solve: the Jacobi preconditioner is for CGLS");
     fftt_status st = ensure_ready(c);
     if (st != FFTT_OK) return st;
+    st = check_plane_precision(c, (fftt_precision)o->prec);
+    if (st != FFTT_OK) return st;
     const fftt_precision prec = (fftt_precision)o->prec;
     const bool fp64 = prec == FFTT_FP64;
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
@@ -1588,6 +1611,8 @@ fftt_status fftt_psf(fftt_ctx* c, fftt_precision prec, const int64_t* voxels, in
     if (!voxels || !out || n < 1) FFTT_BAD(c, "psf: null argument or n < 1");
     if (!(noise_sigma > 0) || !std::isfinite(noise_sigma)) FFTT_BAD(c, "psf: noise_sigma must be > 0");
     fftt_status st = ensure_ready(c);
+    if (st != FFTT_OK) return st;
+    st = check_plane_precision(c, prec);
     if (st != FFTT_OK) return st;
     const std::vector<uint8_t>& mk = c->nxy2 ? c->mask2 : c->mask;
     for (int32_t k = 0; k < n; ++k)

@@ -99,3 +99,68 @@ def test_tv_lbfgs_reduces_objective():
     print("lbfgs objective", hist[0], "->", hist[-1], flush=True)
     assert hist[-1] < 0.05 * hist[0]
     assert torch.isfinite(x).all()
+
+
+@pytest.fixture(scope="module")
+def multiband_subgrid():
+    """The four-band workload (0.5 / 1 / 1.5 / 2 MHz, the 128-element ring)
+    on the central 32x32x16 block of its 256x256x64 grid (the same voxel
+    lattice), a model with structure in every direction, data from the
+    table oracle plus 5 ns noise, and the oracle's objective of eq.
+    leastSquare_misfit1 with the TV term (value and gradient)."""
+    w = I.multiband(dims=(32, 32, 16))
+    print("fixture multiband subgrid: oracle objective", flush=True)
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    x_true = w.model + 8.0 * I.random_vector(w.n, 51)
+    x = 0.5 * x_true + 3.0 * I.random_vector(w.n, 52)
+    B, M = w.n_bands, w.m
+    d = ot.apply_J(x_true).reshape(B, M) + I.noise(B * M, w.noise_sigma, 53).reshape(B, M)
+    cache = {}
+
+    def J_all(v):
+        key = id(v)
+        if key not in cache:
+            cache.clear()
+            cache[key] = ot.apply_J(v).reshape(B, M)
+        return cache[key]
+
+    def JT_band(b):
+        def f(r):
+            y = np.zeros((B, M))
+            y[b] = r
+            return ot.apply_JT(y)
+        return f
+
+    ops = [(lambda v, b=b: J_all(v)[b], JT_band(b)) for b in range(B)]
+    beta = 0.1
+    mis0, _ = solvers.tv_objective(ops, list(d), w.noise_sigma, 0.0, beta, w.grid.dims,
+                                   w.grid.spacing, x)
+    tv0, _ = solvers.tv(x, w.grid.dims, w.grid.spacing, beta)
+    alpha = 0.3 * mis0 / tv0        # both terms of the objective matter
+    chi, grad = solvers.tv_objective(ops, list(d), w.noise_sigma, alpha, beta, w.grid.dims,
+                                     w.grid.spacing, x)
+    return w, x, d, alpha, beta, chi, grad
+
+
+@pytest.mark.parametrize("prec_name,tol", [("FP64", 1e-10), ("FP32", 1e-5)])
+def test_multiband_objective_and_gradient_match_oracle(multiband_subgrid, prec_name, tol):
+    """misfit_tv (four bands in one launch, TV) and its autograd gradient
+    (J^T kernel) against the oracle's tv_objective on the same inputs:
+    relative error of the value and norm-wise error of the gradient within
+    1e-10 (FP64) / 1e-5 (FP32)."""
+    from paper_1908_03302_amd.autograd import misfit_tv
+    w, x, d, alpha, beta, chi, grad = multiband_subgrid
+    f = F()
+    prec = getattr(f, prec_name)
+    dt = torch.float64 if prec == f.FP64 else torch.float32
+    ctx = F().context_for_workload(w)
+    xt = torch.tensor(x, dtype=dt, device="cuda:0", requires_grad=True)
+    dd = torch.tensor(d.ravel(), dtype=dt, device="cuda:0")
+    val = misfit_tv(ctx, xt, dd, w.noise_sigma, alpha, beta, w.grid.dims, w.grid.spacing, prec)
+    val.backward()
+    g = xt.grad.detach().cpu().double().numpy()
+    ev = abs(float(val.detach()) - chi) / abs(chi)
+    eg = np.linalg.norm(g - grad) / np.linalg.norm(grad)
+    print("multiband subgrid", prec_name, "objective rel err %.2e, gradient %.2e" % (ev, eg),
+          flush=True)
+    assert ev < tol and eg < tol

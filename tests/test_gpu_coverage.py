@@ -1,4 +1,4 @@
-"""Sensitivity coverage sum_i |J_ij| (Sec. IV), diag(J^T J) and the
+"""Sensitivity coverage sum_i |J_ij| (Sec. III), diag(J^T J) and the
 Jacobi-preconditioned CGLS built on it, through the C ABI, against the CPU
 FP64 oracle's dense operator.
 

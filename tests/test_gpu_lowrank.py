@@ -1,4 +1,4 @@
-"""Low-rank analysis of the Gauss-Newton Hessian (Sec. II-E) through the C
+"""Low-rank analysis of the Gauss-Newton Hessian (Sec. II-D) through the C
 ABI against the CPU FP64 oracle: the randomized eigensolver
 (fftt_hessian_lowrank) from the same seeded start block as the oracle's
 numpy implementation of the same algorithm, and the low-rank posterior /

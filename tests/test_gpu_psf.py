@@ -236,3 +236,77 @@ def test_psf_split_bf16_matches_fp32_matrix_cores(ragged_dense, prec_name):
     e = max(rel(a[k], b[k]) for k in range(len(vox)))
     say("split BF16 vs FP32 matrix cores", prec_name, "worst rel %.2e" % e)
     assert e < 1e-5
+
+
+def _eight_psf_voxels(w, ot):
+    """Eight of the seed-2 voxels, spread over the batch, among those that
+    some pair sees (a nonzero column of J; voxels far off the ring plane
+    have none)."""
+    vox = w.extra["psf_voxels"]
+    seen = [k for k in range(vox.size) if np.any(ot.block(cols=[int(vox[k])]) != 0)]
+    seen = np.array(seen)
+    return seen[np.linspace(0, seen.size - 1, 8).round().astype(int)]
+
+
+@pytest.fixture(scope="module")
+def psf512_reference():
+    """Whole-grid FP64 reference PSFs of eight seed-2 voxels of the
+    512-PSF workload: J e_v from the table oracle's column v, then J^T of it
+    by an oracle restricted to the pairs with J_iv != 0 (the others add
+    nothing), over every voxel.  Also the quadrature oracle on a sample of
+    each PSF's support, for the table's own error."""
+    w = I.psf512()
+    say("fixture psf512 reference: oracle PSFs over the whole grid")
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    oq = oracle.Oracle.from_workload(w)
+    ks = _eight_psf_voxels(w, ot)
+    refs, samples = [], []
+    rng = np.random.default_rng(31)
+    for k in ks:
+        v = int(w.extra["psf_voxels"][k])
+        col = ot.block(cols=[v])[:, 0]
+        sub = np.flatnonzero(col != 0)
+        o_sub = oracle.Oracle(w.c0, w.tx, w.pairs[sub], w.grid.origin, w.grid.spacing,
+                              w.grid.dims, w.mask, w.r_max, tables=list(ot.tab))
+        ref = o_sub.apply_JT(col[sub]) / SIGMA ** 2
+        supp = np.flatnonzero(ref)
+        cols = np.sort(rng.choice(supp, 256, replace=False))
+        q_sub = oracle.Oracle(w.c0, w.tx, w.pairs[sub], w.grid.origin, w.grid.spacing,
+                              w.grid.dims, w.mask, w.r_max, quads=oq.quads)
+        Jq = q_sub.block(cols=np.concatenate([[v], cols]))
+        refq = Jq[:, 1:].T @ Jq[:, 0] / SIGMA ** 2
+        say("  PSF", int(k), "voxel", v, "pairs", sub.size, "support", supp.size)
+        refs.append(ref)
+        samples.append((cols, refq))
+    return w, ks, refs, samples
+
+
+@pytest.mark.parametrize("prec_name", ["FP32", "FP32_BF16TABLE"])
+def test_psf512_whole_grid_parity(psf512_reference, prec_name):
+    """The 512-PSF batch of the bench (seed-2 voxels, one launch) on the
+    256x256x64 grid: eight PSFs compared with the FP64 oracle over every
+    voxel (eq. resolution_2).  Per PSF: L2 error against the table oracle
+    within 1e-5 (FP32 table) / 1e-3 (BF16 table), the max element error over
+    max |PSF| reported; against quadrature on a 256-voxel sample of the
+    support, the table's own error plus the same bar."""
+    w, ks, refs, samples = psf512_reference
+    f = _fftt()
+    prec = getattr(f, prec_name)
+    ctx = f.context_for_workload(w)
+    vox = w.extra["psf_voxels"]
+    out = ctx.psf(vox, SIGMA, prec=prec).view(len(vox), w.n)
+    worst = 0.0
+    for k, ref, (cols, refq) in zip(ks, refs, samples):
+        got = host(out[int(k)])
+        e2 = rel(got, ref)
+        emax = float(np.abs(got - ref).max() / np.abs(ref).max())
+        e_tab = rel(ref[cols], refq)
+        e_q = rel(got[cols], refq)
+        say("psf512", prec_name, "PSF", int(k), "L2 %.2e max-elem %.2e | sample vs quadrature "
+            "%.2e (table's own %.2e)" % (e2, emax, e_q, e_tab))
+        assert np.all(got[w.mask == 0] == 0.0)
+        assert e2 < TOL[prec_name]
+        assert e_tab < 2.5e-5
+        assert e_q < e_tab + TOL[prec_name]
+        worst = max(worst, e2)
+    say("psf512", prec_name, "worst per-PSF L2 %.2e" % worst)

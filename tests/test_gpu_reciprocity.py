@@ -1,8 +1,9 @@
 """Source-receiver reciprocity in the operators (through the C ABI).
 
 The detour R_xs + R_xr - L and L are symmetric in source and receiver, so
-rows (s, r) and (r, s) of J are equal (Sec. II-B).  The library evaluates
-each unordered pair once by default; these tests check that the outputs
+rows (s, r) and (r, s) of J are equal (Sec. II, the reciprocity of the
+Green's function).  The library evaluates each unordered pair once by
+default; these tests check that the outputs
 match the oracle either way, that reversed rows come out identical, and
 that pair sets with missing reverses or repeated pairs are handled.
 """

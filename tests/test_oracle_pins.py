@@ -434,7 +434,7 @@ def test_tv_gradient_by_finite_differences():
     assert abs(solvers.tv(np.full(60, 3.0), dims, sp, 0.1)[0] - 6.0) < 1e-12
 
 
-# ------------------------------------------------------------- low rank (Sec. II-E)
+# ------------------------------------------------------------- low rank (Sec. II-D)
 def _low_rank_psd(n, r, seed):
     B = np.random.default_rng(seed).standard_normal((n, r))
     return B @ B.T
@@ -513,3 +513,175 @@ def test_midpoint_prism_converges_to_the_z_integral():
     e = np.array(errs).reshape(2, 2).max(axis=1)
     assert 1e-3 < e[0] < 3e-2
     assert e[1] < 5e-8
+
+
+# ------------------------------------------------------------- several bands (Sec. II-C per band)
+def _three_band_setup(table_mode):
+    """A tiny ring with three pulses of different truncation radii (0.5 MHz /
+    50 %, 1 MHz and 2 MHz at 100 %): the B-band oracle and the B one-band
+    oracles of the same pulses.  Each band's kernel is eq. Kernel_freq of
+    its own pulse, so band b of the B-band operator must be the one-band
+    operator of band b's pulse, cut at band b's own R_max."""
+    g = I.centred_grid((10, 9, 6), 1.5e-3)
+    tx = I.ring(8, 0.03)
+    pairs = I.all_ordered_pairs(8)
+    mask = I.cylinder_mask(g, 0.02)
+    pulses = [I.sampled_pulse(0.5e6, 0.5), I.sampled_pulse(1e6, 1.0), I.sampled_pulse(2e6, 1.0)]
+    r_max = [I.R_MAX_HALF_MHZ_BW50, I.R_MAX[1e6], I.R_MAX[2e6]]
+    nw = max(oracle.auto_nodes(p.samples, p.dt, C0, r)[1] for p, r in zip(pulses, r_max))
+    quads = [_quad(p, r, nw=nw) for p, r in zip(pulses, r_max)]
+    tables = ([oracle.table(a, b, r, 512) for (a, b), r in zip(quads, r_max)]
+              if table_mode else None)
+    args = (C0, tx, pairs, g.origin, g.spacing, g.dims, mask)
+    multi = oracle.Oracle(*args, r_max, quads=quads, tables=tables)
+    singles = [oracle.Oracle(*args, [r_max[b]], quads=[quads[b]],
+                             tables=None if tables is None else [tables[b]])
+               for b in range(3)]
+    return g, tx, pairs, mask, r_max, multi, singles
+
+
+@pytest.mark.parametrize("table_mode", [False, True])
+def test_bands_equal_one_band_oracles(table_mode):
+    """Rows ([B][M] layout), columns (sum over bands) and dense blocks of the
+    three-band oracle equal those of the one-band oracles band by band."""
+    g, tx, pairs, mask, r_max, multi, singles = _three_band_setup(table_mode)
+    M, N = pairs.shape[0], g.n
+    x = I.random_vector(N, 40)
+    y = I.random_vector(3 * M, 41).reshape(3, M) * 1e-7
+    rows = np.arange(M)
+    Y = multi.rows(rows, x)
+    assert Y.shape == (3, M)
+    YJ = multi.apply_J(x)
+    for b in range(3):
+        yb = singles[b].rows(rows, x)
+        assert np.linalg.norm(yb) > 0
+        assert np.linalg.norm(Y[b] - yb) <= 1e-13 * np.linalg.norm(yb)
+        assert np.linalg.norm(YJ[b] - yb) <= 1e-13 * np.linalg.norm(yb)
+        Bm = multi.block(band=b)
+        Bs = singles[b].block()
+        assert np.array_equal(Bm, Bs)
+    cols = np.arange(N)
+    ref = sum(singles[b].cols(cols, y[b]) for b in range(3))
+    got = multi.cols(cols, y)
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+    assert np.linalg.norm(multi.apply_JT(y) - ref) <= 1e-13 * np.linalg.norm(ref)
+    # the bands differ, so a transposed [M][B] layout could not pass
+    assert np.linalg.norm(Y[0] - Y[1]) > 0.1 * np.linalg.norm(Y[1])
+
+
+def test_bands_cut_at_their_own_radius():
+    """h = 0 for R >= R_max of the band (truncation of Sec. II-C), decided per
+    band: entries with R_max(2 MHz) <= R < R_max(0.5 MHz) are zero in the
+    2 MHz band and nonzero in the 0.5 MHz band.  R from the geometry."""
+    g, tx, pairs, mask, r_max, multi, singles = _three_band_setup(False)
+    cen = g.centres()
+    xs, xr = tx[pairs[:, 0]], tx[pairs[:, 1]]
+    L = np.linalg.norm(xs - xr, axis=1)
+    R = (np.linalg.norm(cen[None, :, :] - xs[:, None, :], axis=2)
+         + np.linalg.norm(cen[None, :, :] - xr[:, None, :], axis=2) - L[:, None])
+    act = (mask != 0)[None, :]
+    B0, B2 = multi.block(band=0), multi.block(band=2)
+    band = act & (R >= r_max[2] * (1 + 1e-9)) & (R < r_max[0] * (1 - 1e-9))
+    assert band.sum() > 1000
+    assert np.all(B2[band] == 0.0)
+    assert np.count_nonzero(B0[band]) > 0.99 * band.sum()
+    assert np.all(B0[act & (R >= r_max[0] * (1 + 1e-9))] == 0.0)
+    assert np.all(B0[~np.broadcast_to(act, B0.shape)] == 0.0)
+
+
+# ------------------------------------------------------------- TV value (Sec. III regulariser)
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_tv_of_a_linear_ramp(axis):
+    """A ramp x = a i_k along axis k has forward difference a/h_k wherever
+    voxel i_k has an upper neighbour and 0 on the upper face, so
+    TV = (N - N/n_k) sqrt((a/h_k)^2 + beta^2) + (N/n_k) beta.  Unequal
+    spacings pin the 1/h scaling per axis."""
+    dims = (5, 4, 3)
+    sp = (1e-3, 1.3e-3, 0.7e-3)
+    beta, a = 0.1, 0.37e-3
+    N = int(np.prod(dims))
+    idx = np.indices(dims[::-1])[::-1]          # (i, j, k) per voxel, x fastest
+    x = a * idx[axis].ravel().astype(np.float64)
+    face = N // dims[axis]
+    exact = (N - face) * math.hypot(a / sp[axis], beta) + face * beta
+    v, _ = solvers.tv(x, dims, sp, beta)
+    assert abs(v - exact) <= 1e-13 * exact
+
+
+def test_tv_of_a_two_axis_ramp():
+    """x = a i + c k: sqrt((a/h_x)^2 + (c/h_z)^2 + beta^2) where both upper
+    neighbours exist, one term where only one does, beta on the corner edge
+    (isotropic TV)."""
+    dims = (5, 4, 3)
+    sp = (1e-3, 1.3e-3, 0.7e-3)
+    beta, a, c = 0.1, 0.4e-3, -0.9e-3
+    i, j, k = np.indices(dims[::-1])[::-1]
+    x = (a * i + c * k).ravel().astype(np.float64)
+    gx, gz = a / sp[0], c / sp[2]
+    hx = (i < dims[0] - 1).ravel()
+    hz = (k < dims[2] - 1).ravel()
+    mag = np.sqrt(np.where(hx, gx * gx, 0.0) + np.where(hz, gz * gz, 0.0) + beta * beta)
+    exact = float(mag.sum())
+    v, _ = solvers.tv(x, dims, sp, beta)
+    assert abs(v - exact) <= 1e-13 * exact
+    assert np.count_nonzero(hx & hz) == 4 * 4 * 2
+
+
+def test_tv_objective_value_and_gradient():
+    """chi(x) = 1/2 sum_b |J_b x - d_b|^2 / sigma^2 + alpha TV(x) (eq.
+    leastSquare_misfit1 with the TV term): with d_b = J_b x - rho_b the data
+    term is 1/2 sum_b |rho_b|^2 / sigma^2 exactly (ramp x: TV in closed
+    form); the gradient against central differences (the data term is
+    quadratic, so only TV adds O(eps^2))."""
+    rng = np.random.default_rng(12)
+    dims = (5, 4, 3)
+    sp = (1e-3, 1.3e-3, 0.7e-3)
+    N = int(np.prod(dims))
+    beta, sigma, alpha = 0.1, 5e-9, 3e-13
+    Js = [rng.standard_normal((17, N)) * 1e-8, rng.standard_normal((17, N)) * 2e-8]
+    ops = [(lambda v, A=A: A @ v, lambda r, A=A: A.T @ r) for A in Js]
+    idx = np.indices(dims[::-1])[::-1]
+    a = 0.5
+    x = a * idx[1].ravel().astype(np.float64)
+    rho = [rng.standard_normal(17) * 1e-8 for _ in Js]
+    d = [A @ x - r for A, r in zip(Js, rho)]
+    face = N // dims[1]
+    tv_exact = (N - face) * math.hypot(a / sp[1], beta) + face * beta
+    exact = 0.5 * sum(float(r @ r) for r in rho) / sigma ** 2 + alpha * tv_exact
+    chi, grad = solvers.tv_objective(ops, d, sigma, alpha, beta, dims, sp, x)
+    assert abs(chi - exact) <= 1e-12 * exact
+    x1 = rng.standard_normal(N)
+    _, g1 = solvers.tv_objective(ops, d, sigma, alpha, beta, dims, sp, x1)
+    for k in (0, 9, 31, 59):
+        e = np.zeros(N)
+        e[k] = 1e-4
+        fp = solvers.tv_objective(ops, d, sigma, alpha, beta, dims, sp, x1 + e)[0]
+        fm = solvers.tv_objective(ops, d, sigma, alpha, beta, dims, sp, x1 - e)[0]
+        fd = (fp - fm) / 2e-4
+        assert abs(fd - g1[k]) <= 1e-7 * np.abs(g1).max()
+    # both bands enter: dropping the second band's operator changes the gradient
+    _, g0 = solvers.tv_objective(ops[:1], d[:1], sigma, alpha, beta, dims, sp, x1)
+    assert np.linalg.norm(g1 - g0) > 0.1 * np.linalg.norm(g1)
+
+
+def test_tv_of_a_bilinear_field_fixes_the_boundary_side():
+    """x = a i k: the forward difference along x at voxel (i, k) is a k / h_x
+    for i < n_x - 1 and 0 on the upper face, along z a i / h_z for k < n_z - 1
+    (a separable ramp cannot tell forward from backward differences; this
+    field can: with backward differences voxel (0, k) would get a zero
+    x-difference instead of voxel (n_x - 1, k))."""
+    dims = (5, 4, 3)
+    sp = (1e-3, 1.3e-3, 0.7e-3)
+    beta, a = 0.1, 0.3e-3
+    nx, ny, nz = dims
+    x = np.empty(nx * ny * nz)
+    exact = 0.0
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                x[i + nx * (j + ny * k)] = a * i * k
+                gx = a * k / sp[0] if i < nx - 1 else 0.0
+                gz = a * i / sp[2] if k < nz - 1 else 0.0
+                exact += math.sqrt(gx * gx + gz * gz + beta * beta)
+    v, _ = solvers.tv(x, dims, sp, beta)
+    assert abs(v - exact) <= 1e-13 * exact
