@@ -187,6 +187,24 @@ fftt_status fftt_apply_J(fftt_ctx *ctx, fftt_precision prec, const void *dc,
 fftt_status fftt_apply_JT(fftt_ctx *ctx, fftt_precision prec, const void *dT,
                           void *dc, int32_t n_rhs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): J^T
+ * exactly as fftt_apply_JT (same kernels, same results), making no
+ * hipMalloc / hipFree or other allocating call.  Its work memory -- the
+ * per-pair weights, B x (evaluated pairs) values of the precision's type,
+ * and in the 2D mode the prism's output, nx*ny*nz values -- lives in a
+ * file-scope device array of 16 MiB that every device the library runs on
+ * holds until the process ends; a request that needs more returns
+ * FFTT_E_INVALID.  The context must be ready: geometry and tables set and
+ * prepared (fftt_prepare, or any earlier apply after the last change of
+ * geometry, tables or tuning), else FFTT_E_STATE.  The array is shared by
+ * every call on the device, on any context or stream, and keeps the last
+ * call's contents (each call writes all it reads): calls that overlap on
+ * one device race.  Not recorded by fftt_profile.
+ *   dT: device [n_rhs][B][M];  dc: device [n_rhs][N] (overwritten). */
+fftt_status fftt_apply_JT_noalloc(fftt_ctx *ctx, fftt_precision prec, const void *dT,
+                                  void *dc, int32_t n_rhs);
+
 /* Regularised least squares with Gaussian noise Gamma_n = sigma^2 I and
  * Gaussian prior Gamma_pr = I (eq. leastSquare_misfit1 / leastSquare_misfit):
  * minimise |J x - d|^2 / sigma^2 + alpha |x|^2 over all bands.

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "internal.h"
@@ -454,29 +455,27 @@ fftt_status apply_J_one(fftt_ctx* c, fftt_precision prec, const void* x, void* y
     return FFTT_OK;
 }
 
-// dc [N] = J^T dT, one right-hand side; ensure_ready done.
-fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* x) {
+// dc [N] = J^T dT, one right-hand side, with the caller's work buffers:
+// wbuf [nb][Mk] weights in the precision's type and, in the 2D mode, zbuf
+// [N] for the prism's output before the layer sum.  Allocates nothing and,
+// with timed = false, creates no events.  ensure_ready done.
+fftt_status apply_JT_work(fftt_ctx* c, fftt_precision prec, const void* y, void* x, void* wbuf,
+                          void* zbuf, bool timed) {
     const bool fp64 = prec == FFTT_FP64;
-    const size_t es = fp64 ? sizeof(double) : sizeof(float);
-    FFTT_HIP(c, c->d_w.alloc((size_t)c->nb * c->Mk * es));
     ApplyArgs a = base_args(c);
     a.tab = fp64 ? c->d_tab64.p : (prec == FFTT_FP32 ? c->d_tab32.p : c->d_tabbf.p);
-    a.w = c->d_w.p;
+    a.w = wbuf;
     // 2D approximation: the prism's J^T first, then the sum over its layers
-    void* out = x;
-    if (c->nxy2) {
-        FFTT_HIP(c, c->d_z3.alloc((size_t)c->N * es));
-        out = c->d_z3.p;
-    }
+    void* out = c->nxy2 ? zbuf : x;
     a.out = out;
     if (op_table(c, prec) == STAB_SERIES && !c->series_ready)
         FFTT_FAIL(c, FFTT_E_STATE, "series evaluation: a band has no sine series");
     FFTT_HIP(c, launch_weights(c->stream, fp64, y, c->d_kptr.as<int32_t>(),
                                c->d_kidx.as<int32_t>(), c->d_C.as<double>(), c->Mk, c->M, c->nb,
-                               c->d_w.p));
+                               wbuf));
     FFTT_HIP(c, launch_fill(c->stream, fp64, out, c->N));
-    hipEvent_t stop;
-    FFTT_HIP(c, prof_begin(c, 1, &stop));
+    hipEvent_t stop = nullptr;
+    if (timed) FFTT_HIP(c, prof_begin(c, 1, &stop));
     if (const int q = staged_q(c, prec)) {
         a.stage_q = q;
         a.unroll = c->unroll_jts;
@@ -492,6 +491,15 @@ fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* 
     FFTT_HIP(c, prof_end(c, stop));
     if (c->nxy2) FFTT_HIP(c, launch_sum_z(c->stream, fp64, out, c->nxy2, c->nz2, x));
     return FFTT_OK;
+}
+
+// dc [N] = J^T dT, one right-hand side, work buffers owned by the context;
+// ensure_ready done.
+fftt_status apply_JT_one(fftt_ctx* c, fftt_precision prec, const void* y, void* x) {
+    const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
+    FFTT_HIP(c, c->d_w.alloc((size_t)c->nb * c->Mk * es));
+    if (c->nxy2) FFTT_HIP(c, c->d_z3.alloc((size_t)c->N * es));
+    return apply_JT_work(c, prec, y, x, c->d_w.p, c->nxy2 ? c->d_z3.p : nullptr, true);
 }
 
 // out [N] FP32 = coverage (kind 0) or diag(J^T J) (kind 1); ensure_ready done.
@@ -712,6 +720,37 @@ struct IterGraph {
     }
 };
 
+namespace {
+
+// ---- work memory of fftt_apply_JT_noalloc ----
+// A file-scope device array: every device the library runs on holds its own
+// copy (kNoAllocScratch bytes) until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// for the symbol); it uses the device address that hipGetSymbolAddress
+// returns for the current device, looked up once per device when the first
+// context on it is created.
+constexpr size_t kNoAllocScratch = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // by device ordinal; null until looked up
+
+// Device address of this device's scratch array (device c->device current).
+fftt_status init_scratch(fftt_ctx* c) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= c->device) g_scratch_ptr.resize(c->device + 1, nullptr);
+    if (!g_scratch_ptr[c->device]) {
+        void* p = nullptr;
+        FFTT_HIP(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) FFTT_FAIL(c, FFTT_E_DEVICE, "scratch array has no device address");
+        g_scratch_ptr[c->device] = p;
+    }
+    c->scratch = g_scratch_ptr[c->device];
+    return FFTT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 fftt_status fftt_create(fftt_ctx** out, int device, void* hip_stream) {
@@ -730,6 +769,10 @@ fftt_status fftt_create(fftt_ctx** out, int device, void* hip_stream) {
     }
     c->n_cu = prop.multiProcessorCount;
     c->lds_limit = prop.sharedMemPerBlock;
+    if (set_device(c) != FFTT_OK || init_scratch(c) != FFTT_OK) {
+        delete c;
+        return FFTT_E_DEVICE;
+    }
     *out = c;
     return FFTT_OK;
 }
@@ -1152,6 +1195,40 @@ fftt_status fftt_apply_JT(fftt_ctx* c, fftt_precision prec, const void* dT, void
     for (int32_t r = 0; r < n_rhs; ++r) {
         st = apply_JT_one(c, prec, static_cast<const char*>(dT) + (size_t)r * c->nb * c->M * es,
                           static_cast<char*>(dc) + (size_t)r * c->Nm * es);
+        if (st != FFTT_OK) return st;
+    }
+    return FFTT_OK;
+}
+
+fftt_status fftt_apply_JT_noalloc(fftt_ctx* c, fftt_precision prec, const void* dT, void* dc,
+                                  int32_t n_rhs) {
+    if (!c) return FFTT_E_INVALID;
+    if (prec < FFTT_FP64 || prec > FFTT_FP32_BF16TABLE) FFTT_BAD(c, "unknown precision");
+    if (!dc || !dT || n_rhs < 1) FFTT_BAD(c, "apply_JT_noalloc: null buffer or n_rhs < 1");
+    // everything ensure_ready would build must exist already
+    if (!c->has_geom || c->nb == 0 || c->tab_dirty || !c->lists_ok)
+        FFTT_FAIL(c, FFTT_E_STATE,
+                  "apply_JT_noalloc: geometry and tables must be set and prepared "
+                  "(fftt_prepare or an earlier apply)");
+    for (int b = 0; b < c->nb; ++b)
+        if (!c->band_set[b]) FFTT_FAIL(c, FFTT_E_STATE, "apply_JT_noalloc: a band has no table");
+    fftt_status st = check_plane_precision(c, prec);
+    if (st != FFTT_OK) return st;
+    const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
+    const size_t wbytes = ((size_t)c->nb * c->Mk * es + 255) & ~(size_t)255;
+    const size_t need = wbytes + (c->nxy2 ? (size_t)c->N * es : 0);
+    if (need > kNoAllocScratch)
+        FFTT_BAD(c, "apply_JT_noalloc: needs " + std::to_string(need) +
+                        " bytes of work memory, more than the " +
+                        std::to_string(kNoAllocScratch) + "-byte scratch array");
+    if (!c->scratch) FFTT_FAIL(c, FFTT_E_STATE, "apply_JT_noalloc: no scratch address");
+    st = set_device(c);
+    if (st != FFTT_OK) return st;
+    char* w = static_cast<char*>(c->scratch);
+    for (int32_t r = 0; r < n_rhs; ++r) {
+        st = apply_JT_work(c, prec, static_cast<const char*>(dT) + (size_t)r * c->nb * c->M * es,
+                           static_cast<char*>(dc) + (size_t)r * c->Nm * es, w,
+                           c->nxy2 ? w + wbytes : nullptr, false);
         if (st != FFTT_OK) return st;
     }
     return FFTT_OK;

@@ -231,6 +231,7 @@ int build_series_from_pulse(double c0, const double* f, int64_t nt, double dt, d
 struct fftt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    void* scratch = nullptr;    // device address of this device's scratch array
     std::string err;
 
     // geometry (host)

@@ -26,7 +26,7 @@ EXPORTS = ["fftt_create", "fftt_destroy", "fftt_last_error", "fftt_set_stream",
            "fftt_psf", "fftt_profile", "fftt_kernel_time", "fftt_set_tuning", "fftt_get_tuning",
            "fftt_autotune", "fftt_set_kernel_series", "fftt_build_series_from_pulse",
            "fftt_coverage", "fftt_hessian_lowrank", "fftt_lowrank_diag",
-           "fftt_set_geometry_2d", "fftt_hessian_apply"]
+           "fftt_set_geometry_2d", "fftt_hessian_apply", "fftt_apply_JT_noalloc"]
 TUNE_WAVES_PER_BLOCK, TUNE_UNROLL_JT, TUNE_UNROLL_J, TUNE_SPLIT_JT, TUNE_SPLIT_J = 0, 1, 2, 3, 4
 TUNE_STAGED, TUNE_UNROLL_JT_STAGED, TUNE_UNROLL_J_STAGED = 5, 6, 7
 TUNE_STAGED_TABLE = 8
@@ -91,6 +91,7 @@ def load():
                                   C.POINTER(C.c_int64)]
     L.fftt_apply_J.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
     L.fftt_apply_JT.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
+    L.fftt_apply_JT_noalloc.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
     L.fftt_solve.argtypes = [vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveReport)]
     L.fftt_psf.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.c_int32, C.c_double, vp]
     L.fftt_coverage.argtypes = [vp, C.c_int, C.c_int32, vp]
@@ -323,6 +324,15 @@ class Context:
         self._check(self.L.fftt_apply_JT(
             self.h, int(prec), self._tensor(dT, prec, n_rhs * self.n_bands * self.M, "dT"),
             self._tensor(dc, prec, n_rhs * self.N, "dc"), int(n_rhs)), "apply_JT")
+        return dc
+
+    def apply_JT_noalloc(self, dT, dc, prec=FP32, n_rhs=1):
+        """J^T through the entry point that allocates nothing (its work
+        memory is the library's fixed scratch array); dc must be given."""
+        self._bind_stream()
+        self._check(self.L.fftt_apply_JT_noalloc(
+            self.h, int(prec), self._tensor(dT, prec, n_rhs * self.n_bands * self.M, "dT"),
+            self._tensor(dc, prec, n_rhs * self.N, "dc"), int(n_rhs)), "apply_JT_noalloc")
         return dc
 
     def solve(self, d_obs, x, method=0, prec=FP32, alpha=1e-3, noise_sigma=1.0, max_iter=20,
