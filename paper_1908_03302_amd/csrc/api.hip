@@ -197,6 +197,7 @@ fftt_status build_pairs(fftt_ctx* c) {
 ApplyArgs base_args(const fftt_ctx* c) {
     ApplyArgs a{};
     a.tiles = c->d_tiles.as<int32_t>();
+    a.tile_ijk = c->d_tile_ijk.as<uint64_t>();
     a.n_act = (int64_t)c->act_tiles.size();
     a.tptr = c->d_tptr.as<int64_t>();
     a.ents = c->d_ents.as<Entry>();
@@ -914,6 +915,20 @@ fftt_status fftt_set_geometry(fftt_ctx* c, double c0, const double* tx_xyz, int6
     if (!c->act_tiles.empty())
         FFTT_HIP(c, hipMemcpy(c->d_tiles.p, c->act_tiles.data(),
                               c->act_tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    {
+        // tile coordinates packed 21 bits each, read by the kernels instead
+        // of dividing tile ids by the tile counts
+        std::vector<uint64_t> ijk(std::max<size_t>(c->act_tiles.size(), 1), 0);
+        const int64_t n0 = c->g.ntile[0], n1 = c->g.ntile[1];
+        for (size_t k = 0; k < c->act_tiles.size(); ++k) {
+            const int64_t t = c->act_tiles[k];
+            ijk[k] = (uint64_t)(t % n0) | ((uint64_t)((t / n0) % n1) << 21) |
+                     ((uint64_t)(t / (n0 * n1)) << 42);
+        }
+        FFTT_HIP(c, c->d_tile_ijk.alloc(ijk.size() * sizeof(uint64_t)));
+        FFTT_HIP(c, hipMemcpy(c->d_tile_ijk.p, ijk.data(), ijk.size() * sizeof(uint64_t),
+                              hipMemcpyHostToDevice));
+    }
     FFTT_HIP(c, c->d_fill_runs.alloc(std::max<size_t>(runs.size(), 2) * sizeof(int64_t)));
     if (!runs.empty())
         FFTT_HIP(c, hipMemcpy(c->d_fill_runs.p, runs.data(), runs.size() * sizeof(int64_t),

@@ -50,9 +50,13 @@ struct GridGeom {
     double spacing[3];
 };
 
+// Packed coordinates of an active tile: tx | ty << 21 | tz << 42.
+constexpr uint64_t kTileCoordMask = (1ull << 21) - 1;
+
 // Arguments of the apply kernels.
 struct ApplyArgs {
     const int32_t* tiles;     // active tile ids [n_act]
+    const uint64_t* tile_ijk; // packed tile coordinates [n_act]
     int64_t n_act;
     const int64_t* tptr;      // [n_act + 1]
     const Entry* ents;        // [nnz]
@@ -261,7 +265,8 @@ struct fftt_ctx {
     int64_t n_fill_runs = 0;              // voxel ranges outside every active tile
 
     // geometry (device)
-    fftt::DevBuf d_tx, d_ps, d_pr, d_kptr, d_kidx, d_L, d_C, d_mask, d_tiles, d_fill_runs;
+    fftt::DevBuf d_tx, d_ps, d_pr, d_kptr, d_kidx, d_L, d_C, d_mask, d_tiles, d_tile_ijk,
+        d_fill_runs;
 
     // kernel tables
     int nb = 0;

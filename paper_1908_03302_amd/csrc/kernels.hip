@@ -99,6 +99,68 @@ __device__ __forceinline__ double dpp_f(double v) {
     return dpp_d<CTRL>(v);
 }
 
+// Eight wavefront sums at once by halving the set of registers with every
+// exchange.  permlane32_swap of registers a, b followed by one add leaves
+// a's two 32-lane halves summed in lanes 0-31 and b's in lanes 32-63;
+// permlane16_swap does the same for pairs of 16-lane rows.  The two
+// remaining registers (four rows of partial sums each) are merged into one
+// by summing each row's two halves (rotation by 8) and moving one register
+// into the upper half of every row (DPP bank mask).  Every group of 8 lanes then
+// holds partial sums of one value; two quad permutations and the row
+// half-mirror (all symmetric, so no lane direction matters) leave the
+// group's total in each of its lanes.  18 VALU instructions for 8 sums, no
+// lane selects.  Group g (lanes 8g .. 8g + 7) ends with the total of value
+// sum8_value_of_lane(8g).  Fixed order: deterministic.
+__device__ __forceinline__ float swap32_add(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap16_add(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <int CTRL, int BANK_MASK>
+__device__ __forceinline__ float dpp_move(float old, float src) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src),
+                                                      CTRL, 0xf, BANK_MASK, false));
+}
+
+// Full-mask DPP move (zero "old": the compiler folds it into the consumer's
+// add as one v_add_f32_dpp).
+template <int CTRL>
+__device__ __forceinline__ float dpp_all(float src) {
+    return dpp_move<CTRL, 0xf>(0.f, src);
+}
+
+__device__ __forceinline__ float sum8_groups(const float (&v)[8]) {
+    // s[k]: value 2k in lanes 0-31, 2k + 1 in lanes 32-63
+    const float s0 = swap32_add(v[0], v[1]), s1 = swap32_add(v[2], v[3]);
+    const float s2 = swap32_add(v[4], v[5]), s3 = swap32_add(v[6], v[7]);
+    // t[j], rows 0..3: values 4j, 4j + 2, 4j + 1, 4j + 3
+    const float t0 = swap16_add(s0, s1), t1 = swap16_add(s2, s3);
+    // row halves summed: lanes 0-7 of row r then hold t0's row r, lanes 8-15
+    // (banks 2 and 3, copied in by an identity move) t1's
+    const float x0 = t0 + dpp_all<0x128>(t0);       // row_ror:8
+    const float y0 = t1 + dpp_all<0x128>(t1);
+    float x = dpp_move<0xe4, 0xc>(x0, y0);          // quad_perm 0,1,2,3
+    x += dpp_all<0xb1>(x);                          // quad_perm 1,0,3,2
+    x += dpp_all<0x4e>(x);                          // quad_perm 2,3,0,1
+    x += dpp_all<0x141>(x);                         // row_half_mirror
+    return x;
+}
+
+// Value held by the lanes of group g (lanes 8g .. 8g + 7) after
+// sum8_groups: the group's half of its row picks t0 or t1, the row picks
+// the value within it.
+__device__ __forceinline__ int sum8_value_of_lane(int lane) {
+    const int row = lane >> 4, half = (lane >> 3) & 1;
+    return 4 * half + ((row & 1) << 1) + (row >> 1);
+}
+
 // U simultaneous wavefront sums: afterwards lane l holds sum_lanes v[l % U]
 // (U = 1, 2 or 4).  Lanes are first paired so each lane carries one of the
 // U sums, then the 64 / U lanes of each class are combined (row rotations by
@@ -128,25 +190,9 @@ __device__ __forceinline__ T multi_sum(const T (&v)[U], int lane) {
         const T y = two ? a : c;
         x += dpp_f<0x4e>(y);
     } else {
+        static_assert(U != 8 || !std::is_same<T, double>::value, "multi_sum<8>: FP32 only");
         static_assert(U == 8, "multi_sum: U in {1, 2, 4, 8}");
-        const bool odd = lane & 1, two = lane & 2, four = lane & 4;
-        T a[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {   // a[k]: value 2k + bit 0 of the lane
-            a[k] = odd ? v[2 * k + 1] : v[2 * k];
-            a[k] += dpp_f<0xb1>(odd ? v[2 * k] : v[2 * k + 1]);
-        }
-        T c[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {   // c[k]: value 4k + (lane & 3)
-            c[k] = two ? a[2 * k + 1] : a[2 * k];
-            c[k] += dpp_f<0x4e>(two ? a[2 * k] : a[2 * k + 1]);
-        }
-        // the partner 4 lanes away in the row has bit 2 flipped: value lane & 7
-        x = four ? c[1] : c[0];
-        x += dpp_f<0x124>(four ? c[0] : c[1]);
-        x += dpp_f<0x128>(x);                 // row_ror:8
-        return add_halves(x);
+        return sum8_groups(v);
     }
     x += dpp_f<0x124>(x);                     // row_ror:4
     x += dpp_f<0x128>(x);                     // row_ror:8
@@ -301,14 +347,15 @@ hipError_t launch_chunk_scan(hipStream_t s, int32_t* cnt, int64_t n_chunks, int6
 
 // --------------------------------------------------------------- work count
 
-__device__ __forceinline__ void voxel_of_lane(const ApplyArgs& A, int64_t t, int lane,
+// Voxel of `lane` in active tile a: the tile's coordinates come packed from
+// the host (21 bits each), so no kernel divides by the tile counts.
+__device__ __forceinline__ void voxel_of_lane(const ApplyArgs& A, int64_t a, int lane,
                                               bool& inside, bool& act, int64_t& vidx,
                                               int64_t v[3]) {
-    int64_t tix, tiy, tiz;
-    tile_xyz(t, A.g, tix, tiy, tiz);
-    v[0] = kTile * tix + (lane & 3);
-    v[1] = kTile * tiy + ((lane >> 2) & 3);
-    v[2] = kTile * tiz + (lane >> 4);
+    const uint64_t ijk = A.tile_ijk[a];
+    v[0] = kTile * (int64_t)(ijk & kTileCoordMask) + (lane & 3);
+    v[1] = kTile * (int64_t)((ijk >> 21) & kTileCoordMask) + ((lane >> 2) & 3);
+    v[2] = kTile * (int64_t)(ijk >> 42) + (lane >> 4);
     inside = v[0] < A.g.dims[0] && v[1] < A.g.dims[1] && v[2] < A.g.dims[2];
     vidx = inside ? v[0] + A.g.dims[0] * (v[1] + A.g.dims[1] * v[2]) : 0;
     act = inside && A.mask[vidx] != 0;
@@ -331,7 +378,7 @@ __global__ __launch_bounds__(256) void k_count_pv(ApplyArgs A, double rmax,
     if (a >= A.n_act) return;
     bool inside, act;
     int64_t vidx, v[3];
-    voxel_of_lane(A, A.tiles[a], lane, inside, act, vidx, v);
+    voxel_of_lane(A, a, lane, inside, act, vidx, v);
     const double x = A.g.origin[0] + (double)v[0] * A.g.spacing[0];
     const double y = A.g.origin[1] + (double)v[1] * A.g.spacing[1];
     const double z = A.g.origin[2] + (double)v[2] * A.g.spacing[2];
@@ -665,7 +712,7 @@ struct LaneVox {
 __device__ __forceinline__ LaneVox lane_vox(const ApplyArgs& A, int64_t a, int lane) {
     LaneVox L;
     int64_t v[3];
-    voxel_of_lane(A, A.tiles[a], lane, L.inside, L.act, L.vidx, v);
+    voxel_of_lane(A, a, lane, L.inside, L.act, L.vidx, v);
     L.ux = ((double)(lane & 3) - 1.5) * A.g.spacing[0];
     L.uy = ((double)((lane >> 2) & 3) - 1.5) * A.g.spacing[1];
     L.uz = ((double)(lane >> 4) - 1.5) * A.g.spacing[2];
@@ -1186,6 +1233,56 @@ template <int U, bool SCALE, class F>
 __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const float2* sx, int lane,
                                              int& prev, float& cd, float& cg, float factor,
                                              F&& body) {
+    if constexpr (U == 8 && !SCALE) {
+        // Runs of one source in a tile average fewer than eight entries, so
+        // a step of eight usually holds two sources: each half of the step
+        // reuses the source it starts with (the cached one for the first
+        // half, entry 3's for the second) when all four of its entries share
+        // it, and reads its four sources otherwise.  The arithmetic is
+        // instantiated in all four combinations so that reused values are
+        // used in place.  (J^T only: in J, whose source factor carries the
+        // model value, the larger code was no faster.)
+        bool lo = true, hi = true;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) lo = lo && (E.s[u] == prev);
+#pragma unroll
+        for (int u = 4; u < 8; ++u) hi = hi && (E.s[u] == E.s[3]);
+        auto read = [&](int u, float& d, float& g) {
+            const float2 v = sx[E.s[u] * 64 + lane];
+            d = v.x;
+            g = SCALE ? v.y * factor : v.y;
+        };
+        auto second = [&](float (&d)[8], float (&g)[8]) {
+            if (hi) {
+#pragma unroll
+                for (int u = 4; u < 8; ++u) {
+                    d[u] = d[3];
+                    g[u] = g[3];
+                }
+            } else {
+#pragma unroll
+                for (int u = 4; u < 8; ++u) read(u, d[u], g[u]);
+            }
+            body(d, g);
+            prev = E.s[7];
+            cd = d[7];
+            cg = g[7];
+        };
+        float d[8], g[8];
+        if (lo) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                d[u] = cd;
+                g[u] = cg;
+            }
+            second(d, g);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) read(u, d[u], g[u]);
+            second(d, g);
+        }
+        return;
+    }
     bool same = true;
 #pragma unroll
     for (int u = 0; u < U; ++u) same = same && (E.s[u] == prev);
@@ -1326,7 +1423,7 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_jt32s(ApplyArgs A) {
     for (int k = 1; k < W; ++k) t += s_acc[k * 64 + lane];
     bool inside, act;
     int64_t vidx, v[3];
-    voxel_of_lane(A, A.tiles[a], lane, inside, act, vidx, v);
+    voxel_of_lane(A, a, lane, inside, act, vidx, v);
     if (inside) static_cast<float*>(A.out)[vidx] = act ? t : 0.f;
 }
 
@@ -1360,7 +1457,11 @@ __device__ __forceinline__ void j32s_body(const ApplyArgs& A, const TabT* st, co
 #pragma unroll
             for (int u = 0; u < U; ++u) v[u] *= t[u];
             const float sum = multi_sum<U>(v, lane);
-            if (lane < U) part[b * A.nnz + e + lane] = sum;
+            if constexpr (U == 8) {
+                if ((lane & 7) == 0) part[b * A.nnz + e + sum8_value_of_lane(lane)] = sum;
+            } else {
+                if (lane < U) part[b * A.nnz + e + lane] = sum;
+            }
         }
     });
 }
@@ -1377,7 +1478,7 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_j32s(ApplyArgs A) {
     {
         bool inside, act;
         int64_t vidx, v[3];
-        voxel_of_lane(A, A.tiles[a], lane, inside, act, vidx, v);
+        voxel_of_lane(A, a, lane, inside, act, vidx, v);
         xv = act ? static_cast<const float*>(A.x)[A.nxy ? v[0] + A.g.dims[0] * v[1] : vidx] : 0.f;
     }
     const float nm1 = (float)(A.ntab - 1);
@@ -1432,13 +1533,7 @@ static hipError_t launch_staged_nbu(hipStream_t s, int tabfmt, bool transpose,
                                     const ApplyArgs& a) {
     switch (tabfmt) {
         case STAB_NODE32: return launch_staged_t<float, NB, U>(s, transpose, a);
-        case STAB_NODE32Z:   // one-band J^T is launched with STAB_NODE32
-            if constexpr (NB == 1) {
-                if (transpose) return hipErrorInvalidValue;
-                return launch_staged(k_j32s<NB, NodeZ, U>, s, a, (size_t)NB * a.ntab * sizeof(NodeZ));
-            } else {
-                return launch_staged_t<NodeZ, NB, U>(s, transpose, a);
-            }
+        case STAB_NODE32Z: return launch_staged_t<NodeZ, NB, U>(s, transpose, a);
         case STAB_PAIR32: return launch_staged_t<float2, NB, U>(s, transpose, a);
         case STAB_BF16: return launch_staged_t<uint32_t, NB, U>(s, transpose, a);
         // the series' own loop is long: at most four entries per step (no spills)
@@ -1744,7 +1839,7 @@ constexpr int kPsfOutSlot = 32 * 33;
 constexpr size_t kPsfOutLds = 16 * kPsfOutSlot * sizeof(float);
 
 // Writes a wave's 64-voxel x 32-column block of PSFs (columns k0 .. k0 + 31
-// below n) of tile t.  The block is two 32 x 32 matrix-core results, lo for
+// below n) of active tile a.  The block is two 32 x 32 matrix-core results, lo for
 // voxels 0-31 and hi for 32-63, where register q of lane l holds voxel
 // 8 (q / 4) + 4 (l / 32) + q % 4 of the half in column l % 32.  Each half
 // goes through the wave's LDS slot so that a store covers 32 voxels of two
@@ -1753,7 +1848,7 @@ constexpr size_t kPsfOutLds = 16 * kPsfOutSlot * sizeof(float);
 // a lane stores a row of four x-neighbours as one float4.  Every lane of the
 // wave takes part; the workgroup must be done with the LDS.
 template <class V>
-__device__ __forceinline__ void store_psf_block(const ApplyArgs& A, int64_t t, const V& c_lo,
+__device__ __forceinline__ void store_psf_block(const ApplyArgs& A, int64_t a, const V& c_lo,
                                                 const V& c_hi, int k0, int n, int wave,
                                                 int lane, float* __restrict__ out) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -1776,7 +1871,7 @@ __device__ __forceinline__ void store_psf_block(const ApplyArgs& A, int64_t t, c
             const int r = lane & 7, cq = lane >> 3;
             bool inside, act;
             int64_t vidx, v[3];
-            voxel_of_lane(A, t, 4 * r + 32 * h, inside, act, vidx, v);
+            voxel_of_lane(A, a, 4 * r + 32 * h, inside, act, vidx, v);
             const uint32_t m = inside ? *reinterpret_cast<const uint32_t*>(A.mask + vidx) : 0u;
 #pragma unroll
             for (int it = 0; it < 4; ++it) {
@@ -1793,7 +1888,7 @@ __device__ __forceinline__ void store_psf_block(const ApplyArgs& A, int64_t t, c
         } else {
             bool inside, act;
             int64_t vidx, v[3];
-            voxel_of_lane(A, t, col + 32 * h, inside, act, vidx, v);
+            voxel_of_lane(A, a, col + 32 * h, inside, act, vidx, v);
 #pragma unroll
             for (int it = 0; it < 16; ++it) {
                 const int c = 2 * it + up;
@@ -2057,7 +2152,7 @@ __global__ __launch_bounds__(1024) void k_psf32(ApplyArgs A, const float* __rest
         __syncthreads();
     }
     if (!active) return;
-    store_psf_block(A, A.tiles[a], c_lo, c_hi, k0, n, wave, lane, out);
+    store_psf_block(A, a, c_lo, c_hi, k0, n, wave, lane, out);
 }
 
 // ---- the same contraction with BF16 matrix-core steps, split three ways
@@ -2282,7 +2377,7 @@ __global__ __launch_bounds__(1024) void k_psfb3(ApplyArgs A, const float* __rest
         __syncthreads();
     }
     if (!active) return;
-    store_psf_block(A, A.tiles[a], c_lo, c_hi, k0, n, wave, lane, out);
+    store_psf_block(A, a, c_lo, c_hi, k0, n, wave, lane, out);
 }
 
 // ---- batched J for dense right-hand sides (Gauss-Newton Hessian blocks)
