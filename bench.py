@@ -13,9 +13,14 @@ ordered pair evaluated under reciprocity_off.
 Prints one JSON line.  Extra fields: roofline of the dominant kernel (from
 HIP events recorded on the launch stream; HBM traffic from the committed
 counter summary while the kernel source is unchanged), CPU-oracle baseline
-on a bounded sample, and the other workloads on the same GPU: CG time to a
-fixed misfit for the mixed and FP64 paths (128-ring and 32-ring), the
-four-band operators, and 512 batched point-spread functions.
+on bounded samples (with the CPU model), the errors of the GPU results
+against those oracle samples (sampled rows of J and columns of J^T in FP32
+and with the BF16 table, two whole-grid PSFs of the 512-PSF batch), and the
+other workloads on the same GPU: CG time to a fixed misfit for the mixed and
+FP64 paths (128-ring and 32-ring, the latter with its J / J^T rates), the
+four-band operators, TV + L-BFGS on the four-band workload (FP32 and FP64,
+objective decrease, finite-difference gradient check), and 512 batched
+point-spread functions.
 """
 from __future__ import annotations
 
@@ -67,11 +72,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, budget_s=30.0):
-    """FP64 oracle on a bounded sample of rows of J (whole grid per row)."""
+def cpu_model():
+    """Host CPU model name and logical CPU count (from /proc/cpuinfo)."""
+    name, n = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    n += 1
+                    if name == "unknown":
+                        name = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return name, n or (os.cpu_count() or 1)
+
+
+def cpu_baseline(w, gpu, budget_s=20.0):
+    """The FP64 oracle timed on the host cores on bounded samples of the
+    workload: random rows of J dc (whole grid per row, frequency
+    quadrature), random columns of J^T dT, and two whole-grid PSFs (table
+    mode, restricted to the pairs that see the voxel).  The sampled outputs
+    are also the references of the bench's error report: `gpu` holds the
+    GPU results of the same products (FP32 and BF16 table)."""
     import numpy as np
     import oracle
     o = oracle.Oracle.from_workload(w)
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
     x = w.model
     rng = np.random.default_rng(123)
     rows_all = rng.permutation(w.m)
@@ -95,12 +121,47 @@ def cpu_baseline(w, budget_s=30.0):
     n = max(cores, min(4096, int(budget_s / max(t1, 1e-3)) * cores))
     rows = rows_all[:n]
     t0 = time.perf_counter()
-    o.rows(rows, x)
+    y_ref = o.rows(rows, x)
     dt = time.perf_counter() - t0
     pv = sum(pv_of(r) for r in rows)
-    return {"value": pv / dt, "unit": "pair-voxel evals/s", "cores": cores, "kind": "oracle",
+    model, ncpu = cpu_model()
+    base = {"value": pv / dt, "unit": "pair-voxel evals/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "host_logical_cpus": ncpu,
             "sample": "%d random rows of J dc (whole 256x256x64 grid each, %d pv), FP64 "
                       "quadrature, %.1f s" % (n, pv, dt)}
+    # columns of J^T dT
+    act = np.flatnonzero(w.mask)
+    cols = np.sort(rng.choice(act, 1024, replace=False))
+    t0 = time.perf_counter()
+    x_ref = o.cols(cols, gpu["dT"])
+    base["JT_columns"] = {"columns": int(cols.size), "s": time.perf_counter() - t0}
+    # two whole-grid PSFs of the 512-PSF batch
+    psf_ref = []
+    t0 = time.perf_counter()
+    for k in gpu["psf_k"]:
+        v = int(gpu["psf_voxels"][k])
+        col = ot.block(cols=[v])[:, 0]
+        sub = np.flatnonzero(col != 0)
+        o_sub = oracle.Oracle(w.c0, w.tx, w.pairs[sub], w.grid.origin, w.grid.spacing,
+                              w.grid.dims, w.mask, w.r_max, tables=list(ot.tab))
+        psf_ref.append(o_sub.apply_JT(col[sub]) / w.noise_sigma ** 2)
+    base["psf_whole_grid"] = {"n": len(psf_ref), "s": time.perf_counter() - t0,
+                              "mode": "table oracle, pairs restricted to those seeing the voxel"}
+    # errors of the GPU results against these references
+    def errs(g, r):
+        g = np.asarray(g, dtype=np.float64).ravel()
+        r = np.asarray(r, dtype=np.float64).ravel()
+        return {"l2_rel": float(np.linalg.norm(g - r) / np.linalg.norm(r)),
+                "max_elem_over_max_ref": float(np.abs(g - r).max() / np.abs(r).max())}
+    err = {"reference": "FP64 oracle (quadrature for J / J^T, table mode for PSFs)"}
+    for name in ("fp32", "bf16_table"):
+        err["J_rows_" + name] = errs(gpu["y_" + name][rows], y_ref)
+        err["JT_columns_" + name] = errs(gpu["x_" + name][cols], x_ref)
+    for name in gpu["psf"]:
+        e = [errs(g, r) for g, r in zip(gpu["psf"][name], psf_ref)]
+        err["psf_" + name] = {"per_psf_l2_rel": [d["l2_rel"] for d in e],
+                              "per_psf_max_elem": [d["max_elem_over_max_ref"] for d in e]}
+    return base, err
 
 
 def main():
@@ -118,6 +179,8 @@ def main():
                     help="skip the low-rank Hessian eigen-decomposition leg")
     ap.add_argument("--no-series", action="store_true",
                     help="skip the sine-series evaluation leg")
+    ap.add_argument("--no-tv", action="store_true",
+                    help="skip the four-band TV + L-BFGS leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of the autotuner's")
     ap.add_argument("--cg-iters", type=int, default=20)
@@ -251,9 +314,18 @@ def main():
         out["cg_small"] = cg_time_to_misfit(cs, ws, fftt, torch, ws.extra["cg_iters"],
                                             eager_too=True)
         out["cg_small"]["workload"] = ws.name
+        out["cg_small"]["operators"] = small_operator_rates(cs, ws, fftt, torch)
         del cs
+    # GPU results kept for the error report (against the CPU oracle's
+    # samples in the cpu_baseline leg)
+    gpu = {"dT": I.random_vector(w.m, 10) * 1e-7, "psf": {}}
+    dTr = torch.tensor(gpu["dT"], dtype=torch.float32, device=dev)
+    for name, prec in (("fp32", fftt.FP32), ("bf16_table", fftt.FP32_BF16TABLE)):
+        gpu["y_" + name] = ctx.apply_J(dc, prec=prec).double().cpu().numpy()
+        gpu["x_" + name] = ctx.apply_JT(dTr, prec=prec).double().cpu().numpy()
+    del dTr
     if not args.no_psf:
-        out["psf"] = psf_leg(ctx, w, fftt, torch, pv)
+        out["psf"], gpu["psf"], gpu["psf_voxels"], gpu["psf_k"] = psf_leg(ctx, w, fftt, torch, pv)
     out["coverage"] = coverage_leg(ctx, w, torch)
     if not args.no_lowrank:
         out["lowrank"] = lowrank_leg(ctx, w, fftt, torch)
@@ -266,9 +338,14 @@ def main():
         out["plane2d"] = plane_leg(fftt, torch)
     if not args.no_slices:
         out["slices"] = slices_leg(fftt, torch)
+    if not args.no_tv:
+        out["multiband_tv_lbfgs"] = tv_leg(fftt, torch)
     if not args.no_cpu:
         log("bench: CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(w)
+        if "psf_k" not in gpu:
+            gpu["psf_k"] = []
+        out["cpu_baseline"], out["errors"] = cpu_baseline(w, gpu)
+        log("bench: errors vs the oracle: %s" % json.dumps(out["errors"]))
     print(json.dumps(out), flush=True)
 
 
@@ -279,10 +356,17 @@ def psf_leg(ctx, w, fftt, torch, pv, reps=3):
     cores with each FP32 product taken as three BF16 products, so its peak
     for this FP32 work is the dense BF16 peak / 3; the FP32 matrix-core
     variant is timed beside it against the FP32 peak."""
+    import numpy as np
     from paper_1908_03302_amd import inputs as I
     vox = I.pick_voxels(w.mask, 512, seed=2)
     out = torch.empty(len(vox) * w.n, dtype=torch.float32, device="cuda:0")
     res = {"n_psf": len(vox), "voxels_seed": 2, "noise_sigma": w.noise_sigma}
+    # two PSFs of the batch kept for the error report: the first voxels
+    # within 5 mm of the ring plane and 60 mm of its axis (pairs see them)
+    cen = w.grid.centres()[vox]
+    near = np.flatnonzero((np.abs(cen[:, 2]) < 5e-3) & (np.hypot(cen[:, 0], cen[:, 1]) < 0.06))
+    keep = [int(near[0]), int(near[len(near) // 2])]
+    samples = {}
     fpv = flops_per_pv(1, len(vox))
     for name, prec, math in (("fp32", fftt.FP32, 0), ("bf16_table", fftt.FP32_BF16TABLE, 0),
                              ("fp32_fp32_matrix_cores", fftt.FP32, 1)):
@@ -307,9 +391,11 @@ def psf_leg(ctx, w, fftt, torch, pv, reps=3):
                                   "matrix_math": "bf16 x3 split" if math == 0 else "fp32"}}
         log("bench: 512 PSFs %s: %.1f ms (kernels %.1f ms), %.1f TFLOP/s"
             % (name, wall, kms, tf))
+        ov = out.view(len(vox), w.n)
+        samples[name] = [ov[k].double().cpu().numpy() for k in keep]
     ctx.set_tuning(psf_math=0)
     del out
-    return res
+    return res, samples, vox, keep
 
 
 def lowrank_leg(ctx, w, fftt, torch, k=32, l=40, q=2):
@@ -514,6 +600,99 @@ def slices_leg(fftt, torch, reps=3, lsqr_iters=50):
     del ctx, dc, dT, dc2, d64, d, x
     torch.cuda.empty_cache()
     return out
+
+
+def small_operator_rates(ctx, w, fftt, torch, reps=50):
+    """J and J^T of the small ring (32 elements, 24x24x12 grid, FP64 table)
+    in FP64 and FP32: kernel times and pair-voxel evaluations per second
+    (operator pv over every ordered pair)."""
+    pv_op, pv, _ = ctx.work_count()
+    dev = torch.device("cuda:0")
+    res = {"pv_per_apply": pv_op, "pv_evaluated_per_apply": pv}
+    for name, prec, dt in (("fp64", fftt.FP64, torch.float64), ("fp32", fftt.FP32, torch.float32)):
+        dc = torch.tensor(w.model, dtype=dt, device=dev)
+        dT = torch.empty(w.m, dtype=dt, device=dev)
+        dc2 = torch.empty(w.n, dtype=dt, device=dev)
+        for _ in range(3):
+            ctx.apply_J(dc, dT, prec=prec)
+            ctx.apply_JT(dT, dc2, prec=prec)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(reps):
+            ctx.apply_J(dc, dT, prec=prec)
+            ctx.apply_JT(dT, dc2, prec=prec)
+        j, jt, rd = ctx.kernel_time(0), ctx.kernel_time(1), ctx.kernel_time(2)
+        ctx.profile(False)
+        ms = (j[0] + jt[0] + rd[0]) / reps
+        res[name] = {"J_ms": j[0] / j[1], "JT_ms": jt[0] / jt[1], "J_reduce_ms": rd[0] / rd[1],
+                     "pv_per_s": 2 * pv_op / (ms * 1e-3)}
+    res["note"] = ("FP64 operators are the per-wavefront kernels (no LDS staging of the "
+                   "transducer distances); FP32 the staged ones")
+    log("bench: small ring operators: FP64 J %.4f / J^T %.4f ms, FP32 J %.4f / J^T %.4f ms"
+        % (res["fp64"]["J_ms"], res["fp64"]["JT_ms"], res["fp32"]["J_ms"], res["fp32"]["JT_ms"]))
+    return res
+
+
+def tv_leg(fftt, torch, iters=10, n_fd=8):
+    """The differentiable four-band workload at its own scale (128-element
+    ring, 256x256x64 grid, 0.5 / 1 / 1.5 / 2 MHz in one launch): data from
+    the FP64 operator plus 5 ns noise, then the TV-regularised misfit of
+    eq. leastSquare_misfit1 minimised by L-BFGS (strong Wolfe) through the
+    autograd wrapper (backward = the J^T kernel), in FP32 and in FP64.
+    Reported: wall time, objective evaluations, objective decrease, and the
+    gradient against central differences along seeded directions on the
+    central 32x32x16 block."""
+    import numpy as np
+    from paper_1908_03302_amd import inputs as I
+    from paper_1908_03302_amd.autograd import invert_tv, misfit_tv
+    w = I.multiband()
+    ctx = fftt.context_for_workload(w, device=0)
+    ctx.prepare()
+    dev = torch.device("cuda:0")
+    d64 = ctx.apply_J(torch.tensor(w.model, dtype=torch.float64, device=dev), prec=fftt.FP64)
+    d64 = d64 + torch.tensor(I.noise(d64.numel(), w.noise_sigma, w.noise_seed),
+                             dtype=torch.float64, device=dev)
+    sig, beta, alpha = w.noise_sigma, 0.1, 2e-12
+    dims, sp = w.grid.dims, w.grid.spacing
+    res = {"workload": w.name, "bands": 4, "alpha_tv": alpha, "beta": beta,
+           "lbfgs_iterations": iters}
+    for name, prec, dt in (("fp32", fftt.FP32, torch.float32), ("fp64", fftt.FP64, torch.float64)):
+        d = d64.to(dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, hist = invert_tv(ctx, d, sig, alpha, beta, dims, sp, iters=iters, prec=prec)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[name] = {"s": wall, "evaluations": len(hist), "objective_first": hist[0],
+                     "objective_last": hist[-1], "decrease": hist[-1] / hist[0]}
+        # gradient check at the L-BFGS end point
+        xg = x.clone().requires_grad_(True)
+        misfit_tv(ctx, xg, d, sig, alpha, beta, dims, sp, prec).backward()
+        g = xg.grad.detach()
+        nx, ny, nz = dims
+        sub = np.zeros((nz, ny, nx), dtype=bool)
+        sub[nz // 2 - 8:nz // 2 + 8, ny // 2 - 16:ny // 2 + 16, nx // 2 - 16:nx // 2 + 16] = True
+        sub = torch.tensor(sub.ravel(), device=dev)
+        gen = torch.Generator(device="cuda:0")
+        gen.manual_seed(17)
+        worst = 0.0
+        eps = 1e-2 if prec == fftt.FP64 else 1.0
+        for _ in range(n_fd):
+            dirn = torch.randn(w.n, dtype=dt, device=dev, generator=gen) * sub
+            with torch.no_grad():
+                fp = misfit_tv(ctx, x + eps * dirn, d, sig, alpha, beta, dims, sp, prec)
+                fm = misfit_tv(ctx, x - eps * dirn, d, sig, alpha, beta, dims, sp, prec)
+            fd = float(fp - fm) / (2 * eps)
+            an = float((g * dirn).sum())
+            worst = max(worst, abs(fd - an) / max(abs(an), 1e-300))
+        res[name]["fd_gradient_worst_rel"] = worst
+        res[name]["fd_directions"] = n_fd
+        res[name]["fd_eps"] = eps
+        log("bench: four-band TV + L-BFGS %s: %.2f s, %d evaluations, objective %.4g -> %.4g, "
+            "FD gradient worst %.2e" % (name, wall, len(hist), hist[0], hist[-1], worst))
+    del ctx
+    torch.cuda.empty_cache()
+    return res
 
 
 def cg_time_to_misfit(ctx, w, fftt, torch, iters, eager_too=False):
