@@ -177,7 +177,17 @@ fftt_status fftt_work_count(fftt_ctx *ctx, int64_t *pv, int64_t *pv_evaluated,
                             int64_t *lanes);
 
 /* dT = J dc (eq. forward_compact) for n_rhs right-hand sides.
- *   dc: device [n_rhs][N];  dT: device [n_rhs][B][M] (overwritten). */
+ *   dc: device [n_rhs][N];  dT: device [n_rhs][B][M] (overwritten).
+ * With n_rhs >= 8 and FFTT_TUNE_RHS_BATCHED = 1 (default), FP32 / BF16-table
+ * operators with table evaluation, 1 to 3 bands, in 3D, the right-hand
+ * sides run as batches on the matrix cores (per tile the products with
+ * all of them are split-BF16 contractions, as in fftt_hessian_apply;
+ * within 1e-5, norm-wise per vector, of the one-vector path; library
+ * workspace: nb * (evaluated entries) floats per column, batches kept
+ * under about 8 GB).  Otherwise, and for fewer right-hand sides, one
+ * launch per right-hand side.  The same holds for fftt_apply_JT, whose
+ * batch is the point-spread-function contraction of fftt_psf applied to
+ * the data vectors (workspace nb * (kernel pairs) * ceil32(n_rhs) words). */
 fftt_status fftt_apply_J(fftt_ctx *ctx, fftt_precision prec, const void *dc,
                          void *dT, int32_t n_rhs);
 
@@ -352,6 +362,9 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *     eigensolver) run batched on the matrix cores where they can (FP32 /
  *     BF16-table operators with table evaluation, 1 to 3 bands, 3D, LDS),
  *     0 = one J and one J^T per vector.
+ *   FFTT_TUNE_RHS_BATCHED: 1 (default) = fftt_apply_J / fftt_apply_JT with
+ *     n_rhs >= 8 run batched on the matrix cores where they can (as
+ *     FFTT_TUNE_HESS_BATCHED), 0 = one launch per right-hand side.
  *   FFTT_TUNE_RECIPROCITY: 1 (default) = a pair (s, r) and its reverse
  *     (r, s) have the same row of J (source-receiver reciprocity of Sec. II;
  *     the detour and L are symmetric), so each unordered pair is evaluated
@@ -364,7 +377,7 @@ enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_
        FFTT_TUNE_UNROLL_JT_STAGED = 6, FFTT_TUNE_UNROLL_J_STAGED = 7,
        FFTT_TUNE_STAGED_TABLE = 8, FFTT_TUNE_RECIPROCITY = 9,
        FFTT_TUNE_STAGED_BLOCK = 10, FFTT_TUNE_KERNEL_EVAL = 11, FFTT_TUNE_PSF_MATH = 12,
-       FFTT_TUNE_HESS_BATCHED = 13 };
+       FFTT_TUNE_HESS_BATCHED = 13, FFTT_TUNE_RHS_BATCHED = 14 };
 fftt_status fftt_set_tuning(fftt_ctx *ctx, int32_t key, int32_t value);
 
 /* Current value of a tuning key (FFTT_E_INVALID for an unknown key). */

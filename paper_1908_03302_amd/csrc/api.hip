@@ -570,6 +570,73 @@ fftt_status check_plane_precision(fftt_ctx* c, fftt_precision prec) {
 // ---- randomized eigensolver for H = J^T J / sigma^2 (Sec. II-D) ----
 
 // y = H x = J^T (J x) / sigma^2; dT: scratch [nb][M].
+// Columns per batch of the multi-vector J (transpose = false) or J^T on the
+// matrix cores for r right-hand sides, or 0 where the batched kernels do
+// not apply (FP64, series evaluation, four bands, the 2D mode, no staged
+// kernels, LDS, fewer than kRhsBatchMin vectors): the partials of J take
+// nb * nnz floats per column, kept under 8 GB per batch.
+constexpr int kRhsBatchMin = 8;
+
+int rhs_batch_cols(fftt_ctx* c, fftt_precision prec, bool transpose, int r) {
+    if (!c->rhs_batched || r < kRhsBatchMin || prec == FFTT_FP64 || c->nb > 3 || c->nxy2 ||
+        !c->staged || op_table(c, prec) == STAB_SERIES || c->nnz == 0)
+        return 0;
+    const int fmt = staged_table(c, prec);
+    if (psf_lds_bytes(c->nb, c->ntab, fmt, c->n_tx, true) > c->lds_limit) return 0;
+    if (!transpose && jmb3_lds_bytes(c->nb, c->ntab, fmt, c->n_tx) > c->lds_limit) return 0;
+    int cb = r;
+    if (!transpose) {
+        const double per_col = (double)c->nb * (double)c->nnz * sizeof(float);
+        cb = (int)std::min<double>(r, std::floor(8e9 / per_col));
+        if (cb < r) cb &= ~7;
+    }
+    while (cb >= kRhsBatchMin && !psf_weights_fit(c->Mk, ((int64_t)cb + 31) / 32 * 32)) cb /= 2;
+    return cb >= kRhsBatchMin ? cb : 0;
+}
+
+// dT [r][nb][M] = J dc or dc [r][N] = J^T dT for r right-hand sides in
+// batches of cb columns on the matrix cores; ensure_ready done.
+fftt_status apply_rhs_batched(fftt_ctx* c, fftt_precision prec, bool transpose, const void* in,
+                              void* out, int r, int cb) {
+    const int fmt = staged_table(c, prec);
+    const int64_t N = c->Nm, D = (int64_t)c->nb * c->M;
+    const int S = hess_slices(c->Mk, c->n_cu);
+    ApplyArgs a = base_args(c);
+    a.tab = staged_table_ptr(c, fmt);
+    a.stage_q = (int)c->n_tx;
+    hipEvent_t stop;
+    FFTT_HIP(c, prof_begin(c, transpose ? 1 : 0, &stop));
+    for (int c0 = 0; c0 < r; c0 += cb) {
+        const int n = std::min(cb, r - c0);
+        const int64_t ldw = ((int64_t)n + 31) / 32 * 32;
+        if (transpose) {
+            FFTT_HIP(c, c->d_hb_w.alloc((size_t)c->nb * c->Mk * ldw * sizeof(uint32_t)));
+            FFTT_HIP(c, launch_fill(c->stream, false, c->d_hb_w.p, (int64_t)c->nb * c->Mk * ldw));
+            float* o = static_cast<float*>(out) + (size_t)c0 * N;
+            FFTT_HIP(c, fill_runs(c->stream, o, c->N, n, c->d_fill_runs.as<int64_t>(),
+                                  c->n_fill_runs));
+            FFTT_HIP(c, launch_rhs_batch(c->stream, fmt, true, a,
+                                         static_cast<const float*>(in) + (size_t)c0 * D, 0, n,
+                                         nullptr, c->d_gptr.as<int64_t>(), c->d_desc.p, S,
+                                         nullptr, c->d_C.as<double>(), c->d_kptr.as<int32_t>(),
+                                         c->d_kidx.as<int32_t>(), c->M,
+                                         c->d_hb_w.as<uint32_t>(), ldw, o));
+        } else {
+            FFTT_HIP(c, c->d_hb_part.alloc((size_t)c->nb * c->nnz * hess_part_ld(n) * sizeof(float)));
+            FFTT_HIP(c, c->d_hb_red.alloc((size_t)c->nb * S * c->Mk * n * sizeof(double)));
+            FFTT_HIP(c, launch_rhs_batch(c->stream, fmt, false, a,
+                                         static_cast<const float*>(in) + (size_t)c0 * N, N, n,
+                                         c->d_hb_part.as<float>(), c->d_gptr.as<int64_t>(),
+                                         c->d_desc.p, S, c->d_hb_red.as<double>(),
+                                         c->d_C.as<double>(), c->d_kptr.as<int32_t>(),
+                                         c->d_kidx.as<int32_t>(), c->M, nullptr, 0,
+                                         static_cast<float*>(out) + (size_t)c0 * D));
+        }
+    }
+    FFTT_HIP(c, prof_end(c, stop));
+    return FFTT_OK;
+}
+
 fftt_status hess_apply(fftt_ctx* c, fftt_precision prec, double isg2, const void* x, void* dT,
                        void* y) {
     fftt_status st = apply_J_one(c, prec, x, dT);
@@ -1188,6 +1255,8 @@ fftt_status fftt_apply_J(fftt_ctx* c, fftt_precision prec, const void* dc, void*
     if (st != FFTT_OK) return st;
     st = check_plane_precision(c, prec);
     if (st != FFTT_OK) return st;
+    if (const int cb = rhs_batch_cols(c, prec, false, n_rhs))
+        return apply_rhs_batched(c, prec, false, dc, dT, n_rhs, cb);
     const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
     for (int32_t r = 0; r < n_rhs; ++r) {
         st = apply_J_one(c, prec, static_cast<const char*>(dc) + (size_t)r * c->Nm * es,
@@ -1206,6 +1275,8 @@ fftt_status fftt_apply_JT(fftt_ctx* c, fftt_precision prec, const void* dT, void
     if (st != FFTT_OK) return st;
     st = check_plane_precision(c, prec);
     if (st != FFTT_OK) return st;
+    if (const int cb = rhs_batch_cols(c, prec, true, n_rhs))
+        return apply_rhs_batched(c, prec, true, dT, dc, n_rhs, cb);
     const size_t es = prec == FFTT_FP64 ? sizeof(double) : sizeof(float);
     for (int32_t r = 0; r < n_rhs; ++r) {
         st = apply_JT_one(c, prec, static_cast<const char*>(dT) + (size_t)r * c->nb * c->M * es,
@@ -1266,6 +1337,7 @@ fftt_status fftt_get_tuning(fftt_ctx* c, int32_t key, int32_t* value) {
         case FFTT_TUNE_KERNEL_EVAL: *value = c->eval_series; return FFTT_OK;
         case FFTT_TUNE_PSF_MATH: *value = c->psf_fp32_math; return FFTT_OK;
         case FFTT_TUNE_HESS_BATCHED: *value = c->hess_batched; return FFTT_OK;
+        case FFTT_TUNE_RHS_BATCHED: *value = c->rhs_batched; return FFTT_OK;
     }
     FFTT_BAD(c, "unknown tuning key");
 }
@@ -1443,6 +1515,10 @@ fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
         case FFTT_TUNE_HESS_BATCHED:
             if (value != 0 && value != 1) FFTT_BAD(c, "batched Hessian must be 0 or 1");
             c->hess_batched = value;
+            return FFTT_OK;
+        case FFTT_TUNE_RHS_BATCHED:
+            if (value != 0 && value != 1) FFTT_BAD(c, "batched right-hand sides must be 0 or 1");
+            c->rhs_batched = value;
             return FFTT_OK;
         case FFTT_TUNE_SPLIT_JT:
         case FFTT_TUNE_SPLIT_J:

@@ -181,6 +181,16 @@ hipError_t launch_hess_block(hipStream_t s, int tabfmt, const ApplyArgs& a, cons
                              const int32_t* kptr, double scale, float* W, int64_t ldw,
                              float* out);
 size_t jmb3_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx);
+// Several right-hand sides at once (1 to 3 bands, split-BF16 matrix cores).
+// transpose = false: out [l][nb][M] = J Q for Q [l][ldq] model vectors, with
+// part, red, S as for launch_hess_block (W unused).  transpose = true:
+// out [l][N] = J^T dT for dT [l][nb][M] (in), W [nb][Mk][ldw] scratch (ldw a
+// multiple of 32 >= l); out must be zeroed outside the active tiles.
+hipError_t launch_rhs_batch(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a,
+                            const float* in, int64_t ldq, int l, float* part, const int64_t* gptr,
+                            const void* desc, int S, double* red, const double* C,
+                            const int32_t* kptr, const int32_t* kidx, int64_t M, uint32_t* W,
+                            int64_t ldw, float* out);
 // J per-pair sum: S slices per 64-pair group (reduce_slices), FP64 scratch
 // red [nb][S][Mk], then the rows of every caller pair of a group.
 int reduce_slices(int64_t Mk, int n_cu);
@@ -304,6 +314,7 @@ struct fftt_ctx {
     int staged_block_max = 0;  // cap on the staged block size (0: LDS decides)
     int psf_fp32_math = 0;     // batched PSFs: 0 split-BF16 matrix cores (1-3 bands), 1 FP32
     int hess_batched = 1;      // Hessian blocks on the matrix cores where possible
+    int rhs_batched = 1;       // apply_J / apply_JT of n_rhs >= 8 batched likewise
     size_t lds_limit = 65536;
 
     // work buffers

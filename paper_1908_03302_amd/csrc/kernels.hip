@@ -2714,6 +2714,120 @@ hipError_t launch_hess_block(hipStream_t s, int tabfmt, const ApplyArgs& a, cons
     return hipErrorInvalidValue;
 }
 
+// ---- several right-hand sides at once (apply_J / apply_JT, n_rhs > 1)
+//
+// J Q for l model vectors: the Hessian's batched J (k_jmb3 partials, then
+// k_reduce_cols' per-pair FP64 sums over the tiles), then every caller pair
+// of kernel pair p gets C_p times its sum: out [l][nb][M].
+__global__ void k_jbatch_out(const double* __restrict__ red, int S, int64_t Mk, int64_t M, int l,
+                             int nb, const double* __restrict__ C,
+                             const int32_t* __restrict__ kptr, const int32_t* __restrict__ kidx,
+                             float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nb * Mk * l) return;
+    const int64_t k = i % l, p = (i / l) % Mk, b = i / (l * Mk);
+    double t = 0.0;
+    for (int s = 0; s < S; ++s) t += red[((b * S + s) * Mk + p) * l + k];
+    const float v = (float)(C[p] * t);
+    for (int32_t j = kptr[p]; j < kptr[p + 1]; ++j) out[(k * nb + b) * M + kidx[j]] = v;
+}
+
+// J^T of l data vectors dT [l][nb][M]: the weight of kernel pair p for
+// vector k is C_p times the sum of its caller pairs' data (FP64 sum, as the
+// one-vector J^T), stored split for the BF16 matrix-core contraction.
+__global__ void k_jtbatch_weights(const float* __restrict__ dT, int64_t Mk, int64_t M, int l,
+                                  int nb, const double* __restrict__ C,
+                                  const int32_t* __restrict__ kptr,
+                                  const int32_t* __restrict__ kidx, uint32_t* __restrict__ W,
+                                  int64_t ldw) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nb * Mk * l) return;
+    const int64_t k = i % l, p = (i / l) % Mk, b = i / (l * Mk);
+    double t = 0.0;
+    for (int32_t j = kptr[p]; j < kptr[p + 1]; ++j) t += (double)dT[(k * nb + b) * M + kidx[j]];
+    W[(b * Mk + p) * ldw + k] = split_word((float)(C[p] * t));
+}
+
+template <int NB>
+static hipError_t launch_rhs_nb(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a,
+                                const float* in, int64_t ldq, int l, float* part,
+                                const int64_t* gptr, const void* desc, int S, double* red,
+                                const double* C, const int32_t* kptr, const int32_t* kidx,
+                                int64_t M, uint32_t* W, int64_t ldw, float* out) {
+    const int wpb = a.waves_per_block;
+    const unsigned nbat = (unsigned)((l + 32 * wpb - 1) / (32 * wpb));
+    const unsigned grid = (unsigned)xcd_grid(a.n_act);
+    auto run = [&](auto kern, size_t lds, auto... args) -> hipError_t {
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kern, dim3(grid, nbat), dim3(64 * wpb), lds, s, a, args...);
+        return hipGetLastError();
+    };
+    const int64_t nw = (int64_t)NB * a.M * l;
+    if (transpose) {
+        if (!psf_weights_fit(a.M, ldw)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_jtbatch_weights, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s,
+                           in, a.M, M, l, NB, C, kptr, kidx, W, ldw);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || a.n_act == 0) return e;
+        const size_t lp = psfb3_lds_bytes(NB, a.ntab, tabfmt, a.n_tx);
+        switch (tabfmt) {
+            case STAB_NODE32: return run(k_psfb3<NB, float>, lp, (const float*)W, ldw, l, out);
+            case STAB_NODE32Z: return run(k_psfb3<NB, NodeZ>, lp, (const float*)W, ldw, l, out);
+            case STAB_PAIR32: return run(k_psfb3<NB, float2>, lp, (const float*)W, ldw, l, out);
+            case STAB_BF16: return run(k_psfb3<NB, uint32_t>, lp, (const float*)W, ldw, l, out);
+        }
+        return hipErrorInvalidValue;
+    }
+    hipError_t e = hipSuccess;
+    if (a.n_act > 0) {
+        const size_t lj = jmb3_lds_bytes(NB, a.ntab, tabfmt, a.n_tx);
+        e = hipErrorInvalidValue;
+        switch (tabfmt) {
+            case STAB_NODE32: e = run(k_jmb3<NB, float>, lj, in, ldq, l, part); break;
+            case STAB_NODE32Z: e = run(k_jmb3<NB, NodeZ>, lj, in, ldq, l, part); break;
+            case STAB_PAIR32: e = run(k_jmb3<NB, float2>, lj, in, ldq, l, part); break;
+            case STAB_BF16: e = run(k_jmb3<NB, uint32_t>, lj, in, ldq, l, part); break;
+        }
+        if (e != hipSuccess) return e;
+        const int64_t G = (a.M + 63) / 64;
+        const int nz = (l + kRedCols - 1) / kRedCols;
+        hipLaunchKernelGGL(k_reduce_cols,
+                           dim3((unsigned)G, (unsigned)S,
+                                (unsigned)((nz + kRedColWaves - 1) / kRedColWaves)),
+                           dim3(64 * std::min(nz, kRedColWaves)), 0, s, part, a.nnz, l, gptr,
+                           static_cast<const RunDesc*>(desc), a.M, NB, S, red);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_jbatch_out, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, red, S,
+                       a.M, M, l, NB, C, kptr, kidx, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_batch(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a,
+                            const float* in, int64_t ldq, int l, float* part, const int64_t* gptr,
+                            const void* desc, int S, double* red, const double* C,
+                            const int32_t* kptr, const int32_t* kidx, int64_t M, uint32_t* W,
+                            int64_t ldw, float* out) {
+    switch (a.nb) {
+        case 1:
+            return launch_rhs_nb<1>(s, tabfmt, transpose, a, in, ldq, l, part, gptr, desc, S, red,
+                                    C, kptr, kidx, M, W, ldw, out);
+        case 2:
+            return launch_rhs_nb<2>(s, tabfmt, transpose, a, in, ldq, l, part, gptr, desc, S, red,
+                                    C, kptr, kidx, M, W, ldw, out);
+        case 3:
+            return launch_rhs_nb<3>(s, tabfmt, transpose, a, in, ldq, l, part, gptr, desc, S, red,
+                                    C, kptr, kidx, M, W, ldw, out);
+    }
+    return hipErrorInvalidValue;
+}
+
 size_t psfb3_lds_bytes(int nb, int ntab, int tabfmt, int64_t n_tx) {
     const size_t tbytes = (size_t)nb * ntab * staged_entry_bytes(tabfmt);
     const int ch = psfb3_chunk(nb);
