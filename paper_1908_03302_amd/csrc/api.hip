@@ -299,9 +299,38 @@ fftt_status build_lists(fftt_ctx* c) {
     c->pv = (int64_t)pv[0];
     c->pv_eval = (int64_t)pv[1];
     c->lanes = nnz * kTileVox;
+
+    // the source-grouped copy for the staged J^T
+    c->grouped_ok = false;
+    c->d_gents.release();
+    c->d_gtptr.release();
+    if (n_tx <= kGroupMaxTx && c->entry_order) {
+        std::vector<int64_t> gt(n_act + 1, 0);
+        for (int64_t a = 0; a < n_act; ++a) gt[a + 1] = gt[a] + (cnt[a] + 7) / 8 * 8;
+        c->g_nnz = gt[n_act];
+        FFTT_HIP(c, c->d_gtptr.alloc((n_act + 1) * sizeof(int64_t)));
+        FFTT_HIP(c, hipMemcpyAsync(c->d_gtptr.p, gt.data(), (n_act + 1) * sizeof(int64_t),
+                                   hipMemcpyHostToDevice, s));
+        FFTT_HIP(c, c->d_gents.alloc((size_t)(c->g_nnz + kEntryPad) * sizeof(Entry)));
+        FFTT_HIP(c, hipMemsetAsync(c->d_gents.as<Entry>() + c->g_nnz, 0,
+                                   kEntryPad * sizeof(Entry), s));
+        FFTT_HIP(c, launch_group_order(s, c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(), n_act,
+                                       (int)n_tx, c->d_gtptr.as<int64_t>(),
+                                       c->d_gents.as<Entry>()));
+        // the host offsets must outlive the asynchronous copy
+        FFTT_HIP(c, hipStreamSynchronize(s));
+        c->grouped_ok = true;
+    }
     c->lists_rcut = r_cut;
     c->lists_ok = true;
     return FFTT_OK;
+}
+
+// A staged J^T over every transducer at once takes the source-grouped lists.
+void use_grouped(const fftt_ctx* c, ApplyArgs& a, int q) {
+    if (!c->entry_order || !c->grouped_ok || q < c->n_tx) return;
+    a.ents = c->d_gents.as<Entry>();
+    a.tptr = c->d_gtptr.as<int64_t>();
 }
 
 // Event pair for one timed launch of kernel family k (or nulls when off).
@@ -482,6 +511,7 @@ fftt_status apply_JT_work(fftt_ctx* c, fftt_precision prec, const void* y, void*
         a.unroll = c->unroll_jts;
         const int fmt = op_table(c, prec);
         a.tab = staged_table_ptr(c, fmt);
+        use_grouped(c, a, q);
         FFTT_HIP(c, launch_apply_staged(c->stream, fmt, true, a));
     } else {
         if (op_table(c, prec) == STAB_SERIES)
@@ -1338,6 +1368,7 @@ fftt_status fftt_get_tuning(fftt_ctx* c, int32_t key, int32_t* value) {
         case FFTT_TUNE_PSF_MATH: *value = c->psf_fp32_math; return FFTT_OK;
         case FFTT_TUNE_HESS_BATCHED: *value = c->hess_batched; return FFTT_OK;
         case FFTT_TUNE_RHS_BATCHED: *value = c->rhs_batched; return FFTT_OK;
+        case FFTT_TUNE_ENTRY_ORDER: *value = c->entry_order; return FFTT_OK;
     }
     FFTT_BAD(c, "unknown tuning key");
 }
@@ -1519,6 +1550,12 @@ fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
         case FFTT_TUNE_RHS_BATCHED:
             if (value != 0 && value != 1) FFTT_BAD(c, "batched right-hand sides must be 0 or 1");
             c->rhs_batched = value;
+            return FFTT_OK;
+        case FFTT_TUNE_ENTRY_ORDER:
+            if (value != 0 && value != 1) FFTT_BAD(c, "entry order must be 0 or 1");
+            // the grouped copy is built with the lists: turning it on rebuilds them
+            if (value && !c->entry_order) c->lists_ok = false;
+            c->entry_order = value;
             return FFTT_OK;
         case FFTT_TUNE_SPLIT_JT:
         case FFTT_TUNE_SPLIT_J:

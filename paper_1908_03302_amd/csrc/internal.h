@@ -191,6 +191,19 @@ hipError_t launch_rhs_batch(hipStream_t s, int tabfmt, bool transpose, const App
                             const void* desc, int S, double* red, const double* C,
                             const int32_t* kptr, const int32_t* kidx, int64_t M, uint32_t* W,
                             int64_t ldw, float* out);
+// Source-grouped copy of the entry lists for the staged J^T.  Per tile,
+// each kernel pair is oriented towards its endpoint with more entries in the
+// tile (ties: the lower index; the kernel value is symmetric in source and
+// receiver), the entries are grouped by that source, and every source's
+// entries are split into whole groups of four (the grouped part, a multiple
+// of eight entries) and the rest; steps of eight are interleaved evenly
+// between the two kinds.  The tile's list is padded to a multiple of eight
+// with entries of zero kernel value (pair 0, R0hi = R0lo = 3e38).  gtptr:
+// [n_act + 1] offsets with every tile's length rounded up to a multiple of
+// eight.  Requires n_tx <= kGroupMaxTx.
+constexpr int kGroupMaxTx = 1024;
+hipError_t launch_group_order(hipStream_t s, const int64_t* tptr, const Entry* ents,
+                              int64_t n_act, int n_tx, const int64_t* gtptr, Entry* gents);
 // J per-pair sum: S slices per 64-pair group (reduce_slices), FP64 scratch
 // red [nb][S][Mk], then the rows of every caller pair of a group.
 int reduce_slices(int64_t Mk, int n_cu);
@@ -300,6 +313,14 @@ struct fftt_ctx {
     int64_t pv = 0, pv_eval = 0, lanes = 0;
     fftt::DevBuf d_txc, d_tptr, d_ents, d_gptr, d_desc;
     int64_t n_desc = 0;
+    // the same entries grouped by source for the staged J^T (one staged
+    // block only): every tile's list oriented and reordered so that groups of
+    // four consecutive entries share their source where possible, padded to
+    // a multiple of eight (launch_group_order)
+    bool grouped_ok = false;
+    int64_t g_nnz = 0;
+    fftt::DevBuf d_gtptr, d_gents;
+    int entry_order = 1;       // the staged J^T uses the grouped list when it applies
 
     // launch shape of the operator kernels
     int waves_per_block = 16;

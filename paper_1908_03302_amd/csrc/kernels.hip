@@ -1224,70 +1224,99 @@ __device__ __forceinline__ void for_each_block(const ApplyArgs& A, int64_t a, fl
 }
 
 // Source terms of a step: the scaled detour part and 1/R_xs times a per-lane
-// factor (J: the model value of the voxel, J^T: 1).  Entries are sorted by
-// source within runs, so usually all U entries of a step share the cached
-// source (no LDS read, no multiply); otherwise every entry's source is read
-// in one batch.  The arithmetic of the step is instantiated in both arms so
-// that the cached values are used in place (no register copies).
+// factor (J: the model value of the voxel, J^T: 1).  The last source read is
+// cached (prev, cd, cg); a step whose entries share one source needs one LDS
+// read at most (none when it is the cached one), any other step reads every
+// entry's source.  J^T takes a step of eight as two halves of four that are
+// handled so, and walks source-grouped lists on which almost every half
+// shares its source.  (J, whose source factor carries the model value, keeps
+// whole steps: the larger code was slower there.)  The arithmetic of the
+// step is instantiated per case so that shared values are used in place (no
+// register copies).
 template <int U, bool SCALE, class F>
 __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const float2* sx, int lane,
                                              int& prev, float& cd, float& cg, float factor,
                                              F&& body) {
+    auto fetch = [&](int q, float& d, float& g) {
+        const float2 v = sx[q * 64 + lane];
+        d = v.x;
+        g = SCALE ? v.y * factor : v.y;
+    };
+    auto refresh = [&](int q) {
+        if (q != prev) {
+            fetch(q, cd, cg);
+            prev = q;
+        }
+    };
     if constexpr (U == 8 && !SCALE) {
-        // Runs of one source in a tile average fewer than eight entries, so
-        // a step of eight usually holds two sources: each half of the step
-        // reuses the source it starts with (the cached one for the first
-        // half, entry 3's for the second) when all four of its entries share
-        // it, and reads its four sources otherwise.  The arithmetic is
-        // instantiated in all four combinations so that reused values are
-        // used in place.  (J^T only: in J, whose source factor carries the
-        // model value, the larger code was no faster.)
         bool lo = true, hi = true;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) lo = lo && (E.s[u] == prev);
+        for (int u = 1; u < 4; ++u) lo = lo && (E.s[u] == E.s[0]);
 #pragma unroll
-        for (int u = 4; u < 8; ++u) hi = hi && (E.s[u] == E.s[3]);
-        auto read = [&](int u, float& d, float& g) {
-            const float2 v = sx[E.s[u] * 64 + lane];
-            d = v.x;
-            g = SCALE ? v.y * factor : v.y;
-        };
-        auto second = [&](float (&d)[8], float (&g)[8]) {
-            if (hi) {
+        for (int u = 5; u < 8; ++u) hi = hi && (E.s[u] == E.s[4]);
+        float d[8], g[8];
+        if (lo && hi) {
+            refresh(E.s[0]);
+            if (E.s[4] == E.s[0]) {
 #pragma unroll
-                for (int u = 4; u < 8; ++u) {
-                    d[u] = d[3];
-                    g[u] = g[3];
+                for (int u = 0; u < 8; ++u) {
+                    d[u] = cd;
+                    g[u] = cg;
                 }
+                body(d, g);
             } else {
+                float hd, hg;
+                fetch(E.s[4], hd, hg);
 #pragma unroll
-                for (int u = 4; u < 8; ++u) read(u, d[u], g[u]);
+                for (int u = 0; u < 4; ++u) {
+                    d[u] = cd;
+                    g[u] = cg;
+                    d[u + 4] = hd;
+                    g[u + 4] = hg;
+                }
+                body(d, g);
+                prev = E.s[4];
+                cd = hd;
+                cg = hg;
+            }
+        } else if (lo) {
+            refresh(E.s[0]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                d[u] = cd;
+                g[u] = cg;
+                fetch(E.s[u + 4], d[u + 4], g[u + 4]);
             }
             body(d, g);
             prev = E.s[7];
             cd = d[7];
             cg = g[7];
-        };
-        float d[8], g[8];
-        if (lo) {
+        } else if (hi) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 4; ++u) fetch(E.s[u], d[u], g[u]);
+            refresh(E.s[4]);
+#pragma unroll
+            for (int u = 4; u < 8; ++u) {
                 d[u] = cd;
                 g[u] = cg;
             }
-            second(d, g);
+            body(d, g);
         } else {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) read(u, d[u], g[u]);
-            second(d, g);
+            for (int u = 0; u < 8; ++u) fetch(E.s[u], d[u], g[u]);
+            body(d, g);
+            prev = E.s[7];
+            cd = d[7];
+            cg = g[7];
         }
         return;
     }
     bool same = true;
 #pragma unroll
-    for (int u = 0; u < U; ++u) same = same && (E.s[u] == prev);
+    for (int u = 1; u < U; ++u) same = same && (E.s[u] == E.s[0]);
+    float d[U], g[U];
     if (same) {
-        float d[U], g[U];
+        refresh(E.s[0]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             d[u] = cd;
@@ -1295,13 +1324,8 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
         }
         body(d, g);
     } else {
-        float d[U], g[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const float2 v = sx[E.s[u] * 64 + lane];
-            d[u] = v.x;
-            g[u] = SCALE ? v.y * factor : v.y;
-        }
+        for (int u = 0; u < U; ++u) fetch(E.s[u], d[u], g[u]);
         body(d, g);
         prev = E.s[U - 1];
         cd = d[U - 1];
@@ -1691,6 +1715,141 @@ hipError_t launch_group_fill(hipStream_t s, const int64_t* tptr, const Entry* en
     if (nc == 0) return hipSuccess;
     hipLaunchKernelGGL(k_group_fill, dim3((unsigned)nc), dim3(256), 0, s, tptr, ents, n_act,
                        chunk, G, cnt, gptr, static_cast<RunDesc*>(desc));
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ source-grouped entry lists
+//
+// One workgroup per tile.  deg[q]: entries of the tile with endpoint q;
+// each entry's source is its endpoint of larger degree (ties: the lower
+// index), cnt[q] the entries with source q; gcnt[q] of them (whole fours)
+// go to the grouped part, the rest to the other part.  Ranks within a source
+// follow the pair order (deterministic).  Steps of eight: the grouped part's
+// and the rest's are interleaved evenly (Bresenham) when the step map fits
+// in LDS, else the grouped steps come first.
+
+constexpr int kGroupThreads = 256;
+constexpr int kGroupMaxSteps = 4096;
+
+__device__ __forceinline__ int group_source(const int* deg, uint32_t sr) {
+    const int s = (int)(sr & 0xffffu), r = (int)(sr >> 16);
+    return (deg[s] > deg[r] || (deg[s] == deg[r] && s <= r)) ? s : r;
+}
+
+__global__ __launch_bounds__(kGroupThreads) void k_group_order(
+    const int64_t* __restrict__ tptr, const Entry* __restrict__ ents, int n_tx,
+    const int64_t* __restrict__ gtptr, Entry* __restrict__ gents) {
+    __shared__ int deg[kGroupMaxTx], cnt[kGroupMaxTx], gcnt[kGroupMaxTx];
+    __shared__ int gstart[kGroupMaxTx], rstart[kGroupMaxTx], run[kGroupMaxTx];
+    __shared__ int smap[kGroupMaxSteps];
+    __shared__ int s_src[kGroupThreads];
+    __shared__ int s_n[3];   // grouped entries, grouped steps, 1 if smap is used
+    const int64_t a = blockIdx.x;
+    const int64_t t0 = tptr[a];
+    const int n = (int)(tptr[a + 1] - t0);
+    const int64_t o0 = gtptr[a];
+    const int nout = (int)(gtptr[a + 1] - o0);
+    const int tid = (int)threadIdx.x;
+    for (int q = tid; q < n_tx; q += kGroupThreads) {
+        deg[q] = 0;
+        cnt[q] = 0;
+        run[q] = 0;
+    }
+    __syncthreads();
+    for (int e = tid; e < n; e += kGroupThreads) {
+        const uint32_t sr = ents[t0 + e].sr;
+        atomicAdd(&deg[sr & 0xffffu], 1);
+        atomicAdd(&deg[sr >> 16], 1);
+    }
+    __syncthreads();
+    for (int e = tid; e < n; e += kGroupThreads)
+        atomicAdd(&cnt[group_source(deg, ents[t0 + e].sr)], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int P = 0, last = -1;
+        for (int q = 0; q < n_tx; ++q) {
+            if (cnt[q] >= 4) last = q;
+            P += cnt[q] & ~3;
+        }
+        // an odd number of grouped fours: the last one joins the rest
+        const int drop = (P & 4) ? last : -1;
+        int gp = 0, rp = 0;
+        for (int q = 0; q < n_tx; ++q) {
+            const int gq = (cnt[q] & ~3) - (q == drop ? 4 : 0);
+            gcnt[q] = gq;
+            gstart[q] = gp;
+            rstart[q] = rp;
+            gp += gq;
+            rp += cnt[q] - gq;
+        }
+        const int H = nout / 8, Hg = gp / 8, Hr = H - Hg;
+        s_n[0] = gp;
+        s_n[1] = Hg;
+        s_n[2] = H <= kGroupMaxSteps;
+        if (H <= kGroupMaxSteps) {
+            int kg = 0, kr = 0;
+            for (int i = 0; i < H; ++i) {
+                const bool rest = (int64_t)(i + 1) * Hr / H > (int64_t)i * Hr / H;
+                if (rest)
+                    smap[Hg + kr++] = i;
+                else
+                    smap[kg++] = i;
+            }
+        }
+    }
+    __syncthreads();
+    const int P = s_n[0], Hg = s_n[1];
+    const bool mapped = s_n[2] != 0;
+    // output position of grouped (rest = false) or rest position i
+    auto place = [&](bool rest, int i) {
+        const int st = (rest ? Hg : 0) + (i >> 3);
+        return (mapped ? smap[st] : st) * 8 + (i & 7);
+    };
+    for (int base = 0; base < n; base += kGroupThreads) {
+        const int e = base + tid;
+        int q = -1;
+        Entry E;
+        if (e < n) {
+            E = ents[t0 + e];
+            q = group_source(deg, E.sr);
+        }
+        s_src[tid] = q;
+        __syncthreads();
+        int rank = 0;
+        if (q >= 0) {
+            for (int k = 0; k < tid; ++k) rank += s_src[k] == q;
+            rank += run[q];
+        }
+        __syncthreads();
+        if (q >= 0) {
+            atomicAdd(&run[q], 1);
+            const bool rest = rank >= gcnt[q];
+            const int pos = place(rest, rest ? rstart[q] + rank - gcnt[q] : gstart[q] + rank);
+            const int s = (int)(E.sr & 0xffffu), r = (int)(E.sr >> 16);
+            Entry O = E;
+            O.sr = (uint32_t)q | ((uint32_t)(q == s ? r : s) << 16);
+            gents[o0 + pos] = O;
+        }
+        __syncthreads();
+    }
+    // padding: zero kernel value (the detour is far beyond any table), pair 0
+    const int X = n - P;
+    if (tid < nout - n) {
+        Entry O;
+        O.p = 0;
+        O.sr = 0;
+        O.R0hi = 3.0e38f;
+        O.R0lo = 3.0e38f;
+        gents[o0 + place(true, X + tid)] = O;
+    }
+}
+
+hipError_t launch_group_order(hipStream_t s, const int64_t* tptr, const Entry* ents,
+                              int64_t n_act, int n_tx, const int64_t* gtptr, Entry* gents) {
+    if (n_act == 0) return hipSuccess;
+    if (n_tx > kGroupMaxTx) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_group_order, dim3((unsigned)n_act), dim3(kGroupThreads), 0, s, tptr,
+                       ents, n_tx, gtptr, gents);
     return hipGetLastError();
 }
 

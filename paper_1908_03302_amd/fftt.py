@@ -36,6 +36,7 @@ TUNE_KERNEL_EVAL = 11
 TUNE_PSF_MATH = 12
 TUNE_HESS_BATCHED = 13
 TUNE_RHS_BATCHED = 14
+TUNE_ENTRY_ORDER = 15
 
 
 class SolveOpts(C.Structure):
@@ -249,7 +250,7 @@ class Context:
     def set_tuning(self, waves_per_block=None, unroll_jt=None, unroll_j=None, split_jt=None,
                    split_j=None, staged=None, unroll_jt_staged=None, unroll_j_staged=None,
                    staged_table=None, reciprocity=None, staged_block=None, kernel_eval=None,
-                   psf_math=None, hess_batched=None, rhs_batched=None):
+                   psf_math=None, hess_batched=None, rhs_batched=None, entry_order=None):
         for key, v in ((TUNE_WAVES_PER_BLOCK, waves_per_block), (TUNE_UNROLL_JT, unroll_jt),
                        (TUNE_UNROLL_J, unroll_j), (TUNE_SPLIT_JT, split_jt),
                        (TUNE_SPLIT_J, split_j), (TUNE_STAGED, staged),
@@ -259,7 +260,7 @@ class Context:
                        (TUNE_RECIPROCITY, reciprocity),
                        (TUNE_STAGED_BLOCK, staged_block), (TUNE_KERNEL_EVAL, kernel_eval),
                        (TUNE_PSF_MATH, psf_math), (TUNE_HESS_BATCHED, hess_batched),
-                       (TUNE_RHS_BATCHED, rhs_batched)):
+                       (TUNE_RHS_BATCHED, rhs_batched), (TUNE_ENTRY_ORDER, entry_order)):
             if v is not None:
                 self._check(self.L.fftt_set_tuning(self.h, key, int(v)), "set_tuning")
 
@@ -269,7 +270,8 @@ class Context:
                    "unroll_j_staged": TUNE_UNROLL_J_STAGED, "staged_table": TUNE_STAGED_TABLE,
                    "reciprocity": TUNE_RECIPROCITY, "staged_block": TUNE_STAGED_BLOCK,
                    "kernel_eval": TUNE_KERNEL_EVAL, "psf_math": TUNE_PSF_MATH,
-                   "hess_batched": TUNE_HESS_BATCHED, "rhs_batched": TUNE_RHS_BATCHED}
+                   "hess_batched": TUNE_HESS_BATCHED, "rhs_batched": TUNE_RHS_BATCHED,
+                   "entry_order": TUNE_ENTRY_ORDER}
 
     def get_tuning(self):
         """All tuning keys and their current values."""
