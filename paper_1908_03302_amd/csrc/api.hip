@@ -201,6 +201,7 @@ ApplyArgs base_args(const fftt_ctx* c) {
     a.n_act = (int64_t)c->act_tiles.size();
     a.tptr = c->d_tptr.as<int64_t>();
     a.ents = c->d_ents.as<Entry>();
+    a.ents8 = c->d_ents8.as<uint32_t>();
     a.txc = c->d_txc.as<TxConst>();
     a.n_tx = c->n_tx;
     a.nnz = c->nnz;
@@ -256,6 +257,12 @@ fftt_status build_lists(fftt_ctx* c) {
                             n_tx, c->d_ps.as<int32_t>(), c->d_pr.as<int32_t>(),
                             c->d_L.as<double>(), M, c->g, r_cut, nullptr,
                             c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>()));
+
+    // the staged J's eight-byte copy (with the same look-ahead padding)
+    FFTT_HIP(c, c->d_ents8.alloc((size_t)(nnz + kEntryPad) * 2 * sizeof(uint32_t)));
+    FFTT_HIP(c, hipMemsetAsync(c->d_ents8.as<uint32_t>() + 2 * nnz, 0,
+                               kEntryPad * 2 * sizeof(uint32_t), s));
+    FFTT_HIP(c, launch_pack_j_entries(s, c->d_ents.as<Entry>(), nnz, c->d_ents8.as<uint32_t>()));
 
     // run descriptors of 64-pair groups (for the deterministic J reduction)
     const int64_t chunk = 256;

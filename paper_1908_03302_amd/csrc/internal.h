@@ -60,6 +60,7 @@ struct ApplyArgs {
     int64_t n_act;
     const int64_t* tptr;      // [n_act + 1]
     const Entry* ents;        // [nnz]
+    const uint32_t* ents8;    // the staged J's copy: [nnz] (sr, R0hi bits) word pairs
     const TxConst* txc;       // [n_act][n_tx]
     int64_t n_tx;
     int64_t nnz;
@@ -202,6 +203,9 @@ hipError_t launch_rhs_batch(hipStream_t s, int tabfmt, bool transpose, const App
 // [n_act + 1] offsets with every tile's length rounded up to a multiple of
 // eight.  Requires n_tx <= kGroupMaxTx.
 constexpr int kGroupMaxTx = 1024;
+// The staged J reads only sr and R0hi of an entry: out [n][2] words, the
+// same order as ents.
+hipError_t launch_pack_j_entries(hipStream_t s, const Entry* ents, int64_t n, uint32_t* out);
 hipError_t launch_group_order(hipStream_t s, const int64_t* tptr, const Entry* ents,
                               int64_t n_act, int n_tx, const int64_t* gtptr, Entry* gents);
 // J per-pair sum: S slices per 64-pair group (reduce_slices), FP64 scratch
@@ -317,6 +321,7 @@ struct fftt_ctx {
     // block only): every tile's list oriented and reordered so that groups of
     // four consecutive entries share their source where possible, padded to
     // a multiple of eight (launch_group_order)
+    fftt::DevBuf d_ents8;      // (sr, R0hi) of every entry, the staged J's stream
     bool grouped_ok = false;
     int64_t g_nnz = 0;
     fftt::DevBuf d_gtptr, d_gents;

@@ -1167,6 +1167,26 @@ __device__ __forceinline__ StepEntries<U> load_entries(const Entry* __restrict__
     return E;
 }
 
+// The staged J's entries: (sr, R0hi) word pairs, eight bytes each (the pair
+// index is not needed there); StepEntries.p is left unset.
+template <int U>
+__device__ __forceinline__ StepEntries<U> load_entries(const uint32_t* __restrict__ ents8,
+                                                       int64_t e, int base) {
+    StepEntries<U> E;
+    ConstU2* raw = (ConstU2*)(ents8 + 2 * e);
+    u32x2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = raw[u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        E.p[u] = 0;
+        E.s[u] = (int)(v[u].x & 0xffffu) - base;
+        E.r[u] = (int)(v[u].x >> 16) - base;
+        E.R0[u] = __uint_as_float(v[u].y);
+    }
+    return E;
+}
+
 __device__ __forceinline__ int64_t uniform64(int64_t x) {
     const uint64_t u = (uint64_t)x;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
@@ -1179,12 +1199,19 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
 // and a tile's entries are sorted by source, so they form one run per block;
 // the workgroup stages one block at a time.  First entry in [e, t1) whose
 // source is at least q (uniform binary search).
-__device__ __forceinline__ int64_t first_source_at_least(const Entry* __restrict__ ents,
+__device__ __forceinline__ int source_at(const Entry* __restrict__ ents, int64_t e) {
+    return (int)(ents[e].sr & 0xffffu);
+}
+__device__ __forceinline__ int source_at(const uint32_t* __restrict__ ents8, int64_t e) {
+    return (int)(ents8[2 * e] & 0xffffu);
+}
+template <class EntT>
+__device__ __forceinline__ int64_t first_source_at_least(const EntT* __restrict__ ents,
                                                         int64_t e, int64_t t1, int q) {
     int64_t lo = e, hi = t1;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if ((int)(ents[mid].sr & 0xffffu) < q)
+        if (source_at(ents, mid) < q)
             lo = mid + 1;
         else
             hi = mid;
@@ -1195,19 +1222,19 @@ __device__ __forceinline__ int64_t first_source_at_least(const Entry* __restrict
 // Runs body(q0, e0, e1) for each transducer block of tile a after staging
 // it; e0 .. e1 is this wavefront's share of the block's entries (multiples of
 // U).  The staged values are valid inside body only.
-template <int U, class F>
-__device__ __forceinline__ void for_each_block(const ApplyArgs& A, int64_t a, float2* sx,
-                                               int lane, F&& body) {
+template <int U, class EntT, class F>
+__device__ __forceinline__ void for_each_block(const ApplyArgs& A, const EntT* ents, int64_t a,
+                                               float2* sx, int lane, F&& body) {
     const int Q = A.stage_q;
     const int W = (int)(blockDim.x >> 6);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
     for (int64_t b0 = t0; b0 < t1;) {
-        const int q0 = (int)(A.ents[b0].sr & 0xffffu) / Q * Q;
+        const int q0 = source_at(ents, b0) / Q * Q;
         // usually one block holds all of the tile's remaining entries
-        const int64_t b1 = (int)(A.ents[t1 - 1].sr & 0xffffu) < q0 + Q
+        const int64_t b1 = source_at(ents, t1 - 1) < q0 + Q
                                ? t1
-                               : first_source_at_least(A.ents, b0, t1, q0 + Q);
+                               : first_source_at_least(ents, b0, t1, q0 + Q);
         // the lane's voxel offsets are recomputed per block rather than kept
         // live through the entry loop
         stage_distances(A, a, lane_vox(A, a, lane), sx, lane, q0, min(Q, (int)A.n_tx - q0));
@@ -1420,7 +1447,7 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_jt32s(ApplyArgs A) {
     const float* __restrict__ w = static_cast<const float*>(A.w);
     const float nm1 = (float)(A.ntab - 1);
     float acc = 0.f;
-    for_each_block<U>(A, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
+    for_each_block<U>(A, A.ents, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
         float cd = 0.f, cg = 0.f;
         int prev = -1;
         int64_t e = e0;
@@ -1506,16 +1533,16 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_j32s(ApplyArgs A) {
         xv = act ? static_cast<const float*>(A.x)[A.nxy ? v[0] + A.g.dims[0] * v[1] : vidx] : 0.f;
     }
     const float nm1 = (float)(A.ntab - 1);
-    for_each_block<U>(A, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
+    for_each_block<U>(A, A.ents8, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
         float cd = 0.f, cg = 0.f;
         int prev = -1;
         int64_t e = e0;
         for (; e + U <= e1; e += U)
-            j32s_body<NB, TabT, U>(A, st, sx, load_entries<U>(A.ents, e, q0), part, xv, nm1, lane,
-                                   e, prev, cd, cg);
+            j32s_body<NB, TabT, U>(A, st, sx, load_entries<U>(A.ents8, e, q0), part, xv, nm1,
+                                   lane, e, prev, cd, cg);
         for (; e < e1; ++e)
-            j32s_body<NB, TabT, 1>(A, st, sx, load_entries<1>(A.ents, e, q0), part, xv, nm1, lane,
-                                   e, prev, cd, cg);
+            j32s_body<NB, TabT, 1>(A, st, sx, load_entries<1>(A.ents8, e, q0), part, xv, nm1,
+                                   lane, e, prev, cd, cg);
     });
 }
 
@@ -1842,6 +1869,19 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_order(
         O.R0lo = 3.0e38f;
         gents[o0 + place(true, X + tid)] = O;
     }
+}
+
+__global__ void k_pack_j_entries(const Entry* __restrict__ in, int64_t n,
+                                 uint2* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = make_uint2(in[i].sr, __float_as_uint(in[i].R0hi));
+}
+
+hipError_t launch_pack_j_entries(hipStream_t s, const Entry* ents, int64_t n, uint32_t* out) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_j_entries, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ents,
+                       n, reinterpret_cast<uint2*>(out));
+    return hipGetLastError();
 }
 
 hipError_t launch_group_order(hipStream_t s, const int64_t* tptr, const Entry* ents,
