@@ -371,14 +371,14 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *     once: J writes the row to both, J^T uses the summed data; 0 = every
  *     ordered pair is evaluated (only exact repeats share a row).  Outputs
  *     agree within rounding; changing it re-runs the set-up on next use.
- *   FFTT_TUNE_ENTRY_ORDER: 1 (default) = the staged J^T, when it stages
- *     every transducer at once (up to 1024), walks a copy of each tile's
- *     (tile, pair) list in which every pair is oriented towards its endpoint
- *     with more pairs in the tile and the list is grouped by that endpoint
- *     in fours, so that most half-steps share one staged source (the row of
- *     J is symmetric in source and receiver); 0 = the pair-ordered list (and
- *     no copy is kept; turning it on again rebuilds the lists on next use).
- *     J^T agrees within rounding (summation order).
+ *   FFTT_TUNE_ENTRY_ORDER: 1 (default) = when every staged launch can stage
+ *     all transducers at once (up to 1024), the staged J^T walks a copy of
+ *     each tile's (tile, pair) list in which every pair is oriented towards
+ *     its endpoint with more pairs in the tile and the list is grouped by
+ *     that endpoint in fours, so that most half-steps share one staged
+ *     source (the row of J is symmetric in source and receiver); 0 = a copy
+ *     in pair order.  A change rebuilds the lists on next use.  J^T agrees
+ *     within rounding (summation order).
  * FFTT_E_INVALID for other keys or values. */
 enum { FFTT_TUNE_WAVES_PER_BLOCK = 0, FFTT_TUNE_UNROLL_JT = 1, FFTT_TUNE_UNROLL_J = 2,
        FFTT_TUNE_SPLIT_JT = 3, FFTT_TUNE_SPLIT_J = 4, FFTT_TUNE_STAGED = 5,

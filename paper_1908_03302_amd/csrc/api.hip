@@ -202,6 +202,8 @@ ApplyArgs base_args(const fftt_ctx* c) {
     a.tptr = c->d_tptr.as<int64_t>();
     a.ents = c->d_ents.as<Entry>();
     a.ents8 = c->d_ents8.as<uint32_t>();
+    a.ents3 = c->d_ents3.as<Entry3>();
+    a.tptr3 = c->jt_grouped ? c->d_gtptr.as<int64_t>() : c->d_tptr.as<int64_t>();
     a.txc = c->d_txc.as<TxConst>();
     a.n_tx = c->n_tx;
     a.nnz = c->nnz;
@@ -307,38 +309,43 @@ fftt_status build_lists(fftt_ctx* c) {
     c->pv_eval = (int64_t)pv[1];
     c->lanes = nnz * kTileVox;
 
-    // the source-grouped copy for the staged J^T
-    c->grouped_ok = false;
-    c->d_gents.release();
+    // the staged J^T's twelve-byte copy: grouped by source when every staged
+    // launch stages all transducers at once (the tables in their largest
+    // layout plus 512 bytes per transducer fit in LDS), else in pair order
+    c->jt_grouped = false;
     c->d_gtptr.release();
-    if (n_tx <= kGroupMaxTx && c->entry_order) {
+    const bool one_block = n_tx <= kGroupMaxTx &&
+                           staged_lds_bytes(c->nb, c->ntab, STAB_PAIR32, n_tx,
+                                            c->waves_per_block) <= c->lds_limit;
+    if (c->entry_order && one_block) {
         std::vector<int64_t> gt(n_act + 1, 0);
         for (int64_t a = 0; a < n_act; ++a) gt[a + 1] = gt[a] + (cnt[a] + 7) / 8 * 8;
         c->g_nnz = gt[n_act];
         FFTT_HIP(c, c->d_gtptr.alloc((n_act + 1) * sizeof(int64_t)));
         FFTT_HIP(c, hipMemcpyAsync(c->d_gtptr.p, gt.data(), (n_act + 1) * sizeof(int64_t),
                                    hipMemcpyHostToDevice, s));
-        FFTT_HIP(c, c->d_gents.alloc((size_t)(c->g_nnz + kEntryPad) * sizeof(Entry)));
-        FFTT_HIP(c, hipMemsetAsync(c->d_gents.as<Entry>() + c->g_nnz, 0,
-                                   kEntryPad * sizeof(Entry), s));
+        FFTT_HIP(c, c->d_ents3.alloc((size_t)(c->g_nnz + kEntryPad) * sizeof(Entry3)));
+        FFTT_HIP(c, hipMemsetAsync(c->d_ents3.as<Entry3>() + c->g_nnz, 0,
+                                   kEntryPad * sizeof(Entry3), s));
         FFTT_HIP(c, launch_group_order(s, c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(), n_act,
                                        (int)n_tx, c->d_gtptr.as<int64_t>(),
-                                       c->d_gents.as<Entry>()));
+                                       c->d_ents3.as<Entry3>()));
         // the host offsets must outlive the asynchronous copy
         FFTT_HIP(c, hipStreamSynchronize(s));
-        c->grouped_ok = true;
+        c->jt_grouped = true;
+    } else {
+        FFTT_HIP(c, c->d_ents3.alloc((size_t)(nnz + kEntryPad) * sizeof(Entry3)));
+        FFTT_HIP(c, hipMemsetAsync(c->d_ents3.as<Entry3>() + nnz, 0, kEntryPad * sizeof(Entry3),
+                                   s));
+        FFTT_HIP(c, launch_pack_jt_entries(s, c->d_ents.as<Entry>(), nnz,
+                                           c->d_ents3.as<Entry3>()));
     }
     c->lists_rcut = r_cut;
     c->lists_ok = true;
     return FFTT_OK;
 }
 
-// A staged J^T over every transducer at once takes the source-grouped lists.
-void use_grouped(const fftt_ctx* c, ApplyArgs& a, int q) {
-    if (!c->entry_order || !c->grouped_ok || q < c->n_tx) return;
-    a.ents = c->d_gents.as<Entry>();
-    a.tptr = c->d_gtptr.as<int64_t>();
-}
+
 
 // Event pair for one timed launch of kernel family k (or nulls when off).
 hipError_t prof_begin(fftt_ctx* c, int k, hipEvent_t* stop) {
@@ -513,12 +520,14 @@ fftt_status apply_JT_work(fftt_ctx* c, fftt_precision prec, const void* y, void*
     FFTT_HIP(c, launch_fill(c->stream, fp64, out, c->N));
     hipEvent_t stop = nullptr;
     if (timed) FFTT_HIP(c, prof_begin(c, 1, &stop));
-    if (const int q = staged_q(c, prec)) {
+    // the grouped copy serves launches that stage every transducer at once
+    int q = staged_q(c, prec);
+    if (c->jt_grouped && q < c->n_tx) q = 0;
+    if (q) {
         a.stage_q = q;
         a.unroll = c->unroll_jts;
         const int fmt = op_table(c, prec);
         a.tab = staged_table_ptr(c, fmt);
-        use_grouped(c, a, q);
         FFTT_HIP(c, launch_apply_staged(c->stream, fmt, true, a));
     } else {
         if (op_table(c, prec) == STAB_SERIES)
@@ -1560,8 +1569,8 @@ fftt_status fftt_set_tuning(fftt_ctx* c, int32_t key, int32_t value) {
             return FFTT_OK;
         case FFTT_TUNE_ENTRY_ORDER:
             if (value != 0 && value != 1) FFTT_BAD(c, "entry order must be 0 or 1");
-            // the grouped copy is built with the lists: turning it on rebuilds them
-            if (value && !c->entry_order) c->lists_ok = false;
+            // the J^T copy is built with the lists: a change rebuilds them
+            if (value != c->entry_order) c->lists_ok = false;
             c->entry_order = value;
             return FFTT_OK;
         case FFTT_TUNE_SPLIT_JT:

@@ -43,6 +43,14 @@ struct Entry {
 };
 static_assert(sizeof(Entry) == 16, "Entry layout");
 
+// The staged J^T's copy of an entry (no low word of the detour).
+struct Entry3 {
+    int32_t p;
+    uint32_t sr;
+    float R0hi;
+};
+static_assert(sizeof(Entry3) == 12, "Entry3 layout");
+
 struct GridGeom {
     int64_t dims[3];
     int64_t ntile[3];
@@ -61,6 +69,8 @@ struct ApplyArgs {
     const int64_t* tptr;      // [n_act + 1]
     const Entry* ents;        // [nnz]
     const uint32_t* ents8;    // the staged J's copy: [nnz] (sr, R0hi bits) word pairs
+    const Entry3* ents3;      // the staged J^T's copy (source-grouped or pair order)
+    const int64_t* tptr3;     // its tile offsets [n_act + 1]
     const TxConst* txc;       // [n_act][n_tx]
     int64_t n_tx;
     int64_t nnz;
@@ -192,14 +202,15 @@ hipError_t launch_rhs_batch(hipStream_t s, int tabfmt, bool transpose, const App
                             const void* desc, int S, double* red, const double* C,
                             const int32_t* kptr, const int32_t* kidx, int64_t M, uint32_t* W,
                             int64_t ldw, float* out);
-// Source-grouped copy of the entry lists for the staged J^T.  Per tile,
+// Copies of the entry lists for the staged J^T (Entry3 records).
+// launch_pack_jt_entries: the same order.  launch_group_order: per tile,
 // each kernel pair is oriented towards its endpoint with more entries in the
 // tile (ties: the lower index; the kernel value is symmetric in source and
 // receiver), the entries are grouped by that source, and every source's
 // entries are split into whole groups of four (the grouped part, a multiple
 // of eight entries) and the rest; steps of eight are interleaved evenly
 // between the two kinds.  The tile's list is padded to a multiple of eight
-// with entries of zero kernel value (pair 0, R0hi = R0lo = 3e38).  gtptr:
+// with entries of zero kernel value (pair 0, R0hi = 3e38).  gtptr:
 // [n_act + 1] offsets with every tile's length rounded up to a multiple of
 // eight.  Requires n_tx <= kGroupMaxTx.
 constexpr int kGroupMaxTx = 1024;
@@ -207,7 +218,8 @@ constexpr int kGroupMaxTx = 1024;
 // same order as ents.
 hipError_t launch_pack_j_entries(hipStream_t s, const Entry* ents, int64_t n, uint32_t* out);
 hipError_t launch_group_order(hipStream_t s, const int64_t* tptr, const Entry* ents,
-                              int64_t n_act, int n_tx, const int64_t* gtptr, Entry* gents);
+                              int64_t n_act, int n_tx, const int64_t* gtptr, Entry3* gents);
+hipError_t launch_pack_jt_entries(hipStream_t s, const Entry* ents, int64_t n, Entry3* out);
 // J per-pair sum: S slices per 64-pair group (reduce_slices), FP64 scratch
 // red [nb][S][Mk], then the rows of every caller pair of a group.
 int reduce_slices(int64_t Mk, int n_cu);
@@ -317,15 +329,14 @@ struct fftt_ctx {
     int64_t pv = 0, pv_eval = 0, lanes = 0;
     fftt::DevBuf d_txc, d_tptr, d_ents, d_gptr, d_desc;
     int64_t n_desc = 0;
-    // the same entries grouped by source for the staged J^T (one staged
-    // block only): every tile's list oriented and reordered so that groups of
-    // four consecutive entries share their source where possible, padded to
-    // a multiple of eight (launch_group_order)
     fftt::DevBuf d_ents8;      // (sr, R0hi) of every entry, the staged J's stream
-    bool grouped_ok = false;
+    // the staged J^T's copy of the entries: grouped by source (when every
+    // staged launch covers all transducers at once, see launch_group_order;
+    // tile offsets d_gtptr) or in pair order (offsets d_tptr)
+    bool jt_grouped = false;
     int64_t g_nnz = 0;
-    fftt::DevBuf d_gtptr, d_gents;
-    int entry_order = 1;       // the staged J^T uses the grouped list when it applies
+    fftt::DevBuf d_gtptr, d_ents3;
+    int entry_order = 1;       // build the grouped copy when it applies
 
     // launch shape of the operator kernels
     int waves_per_block = 16;

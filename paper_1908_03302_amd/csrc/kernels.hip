@@ -1187,6 +1187,26 @@ __device__ __forceinline__ StepEntries<U> load_entries(const uint32_t* __restric
     return E;
 }
 
+// The staged J^T's entries: (p, sr, R0hi), twelve bytes each.
+using ConstU1 = const __attribute__((address_space(4))) uint32_t;
+template <int U>
+__device__ __forceinline__ StepEntries<U> load_entries(const Entry3* __restrict__ ents3,
+                                                       int64_t e, int base) {
+    StepEntries<U> E;
+    ConstU1* raw = (ConstU1*)(ents3 + e);
+    uint32_t v[3 * U];
+#pragma unroll
+    for (int i = 0; i < 3 * U; ++i) v[i] = raw[i];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        E.p[u] = (int)v[3 * u];
+        E.s[u] = (int)(v[3 * u + 1] & 0xffffu) - base;
+        E.r[u] = (int)(v[3 * u + 1] >> 16) - base;
+        E.R0[u] = __uint_as_float(v[3 * u + 2]);
+    }
+    return E;
+}
+
 __device__ __forceinline__ int64_t uniform64(int64_t x) {
     const uint64_t u = (uint64_t)x;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
@@ -1204,6 +1224,9 @@ __device__ __forceinline__ int source_at(const Entry* __restrict__ ents, int64_t
 }
 __device__ __forceinline__ int source_at(const uint32_t* __restrict__ ents8, int64_t e) {
     return (int)(ents8[2 * e] & 0xffffu);
+}
+__device__ __forceinline__ int source_at(const Entry3* __restrict__ ents3, int64_t e) {
+    return (int)(ents3[e].sr & 0xffffu);
 }
 template <class EntT>
 __device__ __forceinline__ int64_t first_source_at_least(const EntT* __restrict__ ents,
@@ -1223,12 +1246,13 @@ __device__ __forceinline__ int64_t first_source_at_least(const EntT* __restrict_
 // it; e0 .. e1 is this wavefront's share of the block's entries (multiples of
 // U).  The staged values are valid inside body only.
 template <int U, class EntT, class F>
-__device__ __forceinline__ void for_each_block(const ApplyArgs& A, const EntT* ents, int64_t a,
-                                               float2* sx, int lane, F&& body) {
+__device__ __forceinline__ void for_each_block(const ApplyArgs& A, const EntT* ents,
+                                               const int64_t* tptr, int64_t a, float2* sx,
+                                               int lane, F&& body) {
     const int Q = A.stage_q;
     const int W = (int)(blockDim.x >> 6);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t t0 = A.tptr[a], t1 = A.tptr[a + 1];
+    const int64_t t0 = tptr[a], t1 = tptr[a + 1];
     for (int64_t b0 = t0; b0 < t1;) {
         const int q0 = source_at(ents, b0) / Q * Q;
         // usually one block holds all of the tile's remaining entries
@@ -1447,17 +1471,22 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_jt32s(ApplyArgs A) {
     const float* __restrict__ w = static_cast<const float*>(A.w);
     const float nm1 = (float)(A.ntab - 1);
     float acc = 0.f;
-    for_each_block<U>(A, A.ents, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
+    // J^T walks its own copy of the lists; the coverage passes the originals
+    const auto* ents = MODE == 0 ? (const void*)A.ents3 : (const void*)A.ents;
+    using EntT = std::conditional_t<MODE == 0, Entry3, Entry>;
+    const EntT* el = static_cast<const EntT*>(ents);
+    for_each_block<U>(A, el, MODE == 0 ? A.tptr3 : A.tptr, a, sx, lane,
+                      [&](int q0, int64_t e0, int64_t e1) {
         float cd = 0.f, cg = 0.f;
         int prev = -1;
         int64_t e = e0;
         for (; e + U <= e1; e += U) {
-            const StepEntries<U> E = load_entries<U>(A.ents, e, q0);
+            const StepEntries<U> E = load_entries<U>(el, e, q0);
             jt32s_body<NB, TabT, U, MODE>(A, st, sx, E, load_weights<NB, U>(A, w, E), nm1, lane,
                                           prev, cd, cg, acc);
         }
         for (; e < e1; ++e) {
-            const StepEntries<1> E = load_entries<1>(A.ents, e, q0);
+            const StepEntries<1> E = load_entries<1>(el, e, q0);
             jt32s_body<NB, TabT, 1, MODE>(A, st, sx, E, load_weights<NB, 1>(A, w, E), nm1, lane,
                                           prev, cd, cg, acc);
         }
@@ -1533,7 +1562,7 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_j32s(ApplyArgs A) {
         xv = act ? static_cast<const float*>(A.x)[A.nxy ? v[0] + A.g.dims[0] * v[1] : vidx] : 0.f;
     }
     const float nm1 = (float)(A.ntab - 1);
-    for_each_block<U>(A, A.ents8, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
+    for_each_block<U>(A, A.ents8, A.tptr, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
         float cd = 0.f, cg = 0.f;
         int prev = -1;
         int64_t e = e0;
@@ -1765,7 +1794,7 @@ __device__ __forceinline__ int group_source(const int* deg, uint32_t sr) {
 
 __global__ __launch_bounds__(kGroupThreads) void k_group_order(
     const int64_t* __restrict__ tptr, const Entry* __restrict__ ents, int n_tx,
-    const int64_t* __restrict__ gtptr, Entry* __restrict__ gents) {
+    const int64_t* __restrict__ gtptr, Entry3* __restrict__ gents) {
     __shared__ int deg[kGroupMaxTx], cnt[kGroupMaxTx], gcnt[kGroupMaxTx];
     __shared__ int gstart[kGroupMaxTx], rstart[kGroupMaxTx], run[kGroupMaxTx];
     __shared__ int smap[kGroupMaxSteps];
@@ -1853,8 +1882,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_order(
             const bool rest = rank >= gcnt[q];
             const int pos = place(rest, rest ? rstart[q] + rank - gcnt[q] : gstart[q] + rank);
             const int s = (int)(E.sr & 0xffffu), r = (int)(E.sr >> 16);
-            Entry O = E;
+            Entry3 O;
+            O.p = E.p;
             O.sr = (uint32_t)q | ((uint32_t)(q == s ? r : s) << 16);
+            O.R0hi = E.R0hi;
             gents[o0 + pos] = O;
         }
         __syncthreads();
@@ -1862,11 +1893,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_order(
     // padding: zero kernel value (the detour is far beyond any table), pair 0
     const int X = n - P;
     if (tid < nout - n) {
-        Entry O;
+        Entry3 O;
         O.p = 0;
         O.sr = 0;
         O.R0hi = 3.0e38f;
-        O.R0lo = 3.0e38f;
         gents[o0 + place(true, X + tid)] = O;
     }
 }
@@ -1884,8 +1914,27 @@ hipError_t launch_pack_j_entries(hipStream_t s, const Entry* ents, int64_t n, ui
     return hipGetLastError();
 }
 
+__global__ void k_pack_jt_entries(const Entry* __restrict__ in, int64_t n,
+                                  Entry3* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        Entry3 o;
+        o.p = in[i].p;
+        o.sr = in[i].sr;
+        o.R0hi = in[i].R0hi;
+        out[i] = o;
+    }
+}
+
+hipError_t launch_pack_jt_entries(hipStream_t s, const Entry* ents, int64_t n, Entry3* out) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_jt_entries, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       ents, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_group_order(hipStream_t s, const int64_t* tptr, const Entry* ents,
-                              int64_t n_act, int n_tx, const int64_t* gtptr, Entry* gents) {
+                              int64_t n_act, int n_tx, const int64_t* gtptr, Entry3* gents) {
     if (n_act == 0) return hipSuccess;
     if (n_tx > kGroupMaxTx) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_group_order, dim3((unsigned)n_act), dim3(kGroupThreads), 0, s, tptr,
