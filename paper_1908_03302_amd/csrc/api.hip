@@ -205,6 +205,7 @@ ApplyArgs base_args(const fftt_ctx* c) {
     a.ents3 = c->d_ents3.as<Entry3>();
     a.tptr3 = c->jt_grouped ? c->d_gtptr.as<int64_t>() : c->d_tptr.as<int64_t>();
     a.txc = c->d_txc.as<TxConst>();
+    a.txc32 = c->d_txc32.as<TxConst32>();
     a.n_tx = c->n_tx;
     a.nnz = c->nnz;
     a.M = c->Mk;
@@ -234,6 +235,9 @@ fftt_status build_lists(fftt_ctx* c) {
     FFTT_HIP(c, c->d_txc.alloc((size_t)n_act * n_tx * sizeof(TxConst)));
     FFTT_HIP(c, launch_txc(s, c->d_tiles.as<int32_t>(), n_act, c->d_tx.as<double>(), n_tx, c->g,
                            c->d_txc.as<TxConst>()));
+    FFTT_HIP(c, c->d_txc32.alloc((size_t)n_act * n_tx * sizeof(TxConst32)));
+    FFTT_HIP(c, launch_pack_txc32(s, c->d_txc.as<TxConst>(), n_act * n_tx,
+                                  c->d_txc32.as<TxConst32>()));
 
     DevBuf counts;
     FFTT_HIP(c, counts.alloc((size_t)std::max<int64_t>(n_act, 1) * sizeof(int64_t)));

@@ -35,6 +35,16 @@ struct TxConst {
 };
 static_assert(sizeof(TxConst) == 40, "TxConst layout");
 
+// The same constants in FP32 for the staged kernels' distances.  With
+// millimetre tile offsets u, the terms of n = 2 (c - x_q).u + |u|^2 + cq are
+// below ~1e-3 m^2, so FP32 rounding leaves an error of ~1e-10 m^2 in n and
+// ~1e-9 m in delta = n / (R_x + D0f), a thousandth of a micrometre-sized
+// table step; the cancelling detour R0 stays FP64-derived.
+struct TxConst32 {
+    float d2x, d2y, d2z, cq, D0f, Q0f;
+};
+static_assert(sizeof(TxConst32) == 24, "TxConst32 layout");
+
 // One (tile, pair) incidence that survived culling.
 struct Entry {
     int32_t p;              // internal pair index
@@ -72,6 +82,7 @@ struct ApplyArgs {
     const Entry3* ents3;      // the staged J^T's copy (source-grouped or pair order)
     const int64_t* tptr3;     // its tile offsets [n_act + 1]
     const TxConst* txc;       // [n_act][n_tx]
+    const TxConst32* txc32;   // the same in FP32 for the staged kernels
     int64_t n_tx;
     int64_t nnz;
     int64_t M;
@@ -214,6 +225,8 @@ hipError_t launch_rhs_batch(hipStream_t s, int tabfmt, bool transpose, const App
 // [n_act + 1] offsets with every tile's length rounded up to a multiple of
 // eight.  Requires n_tx <= kGroupMaxTx.
 constexpr int kGroupMaxTx = 1024;
+// FP32 copy of the per-(tile, transducer) constants for the staged kernels.
+hipError_t launch_pack_txc32(hipStream_t s, const TxConst* txc, int64_t n, TxConst32* out);
 // The staged J reads only sr and R0hi of an entry: out [n][2] words, the
 // same order as ents.
 hipError_t launch_pack_j_entries(hipStream_t s, const Entry* ents, int64_t n, uint32_t* out);
@@ -328,6 +341,7 @@ struct fftt_ctx {
     int64_t nnz = 0;
     int64_t pv = 0, pv_eval = 0, lanes = 0;
     fftt::DevBuf d_txc, d_tptr, d_ents, d_gptr, d_desc;
+    fftt::DevBuf d_txc32;      // FP32 copy of d_txc (staged kernels)
     int64_t n_desc = 0;
     fftt::DevBuf d_ents8;      // (sr, R0hi) of every entry, the staged J's stream
     // the staged J^T's copy of the entries: grouped by source (when every

@@ -1111,27 +1111,42 @@ __device__ __forceinline__ float2* staged_tx(const ApplyArgs& A, int nb) {
 }
 
 // Stages transducers q0 .. q0 + n - 1 into sx[q - q0][lane].
+// With the FP32 constants (A.txc32) n is formed in FP32 (see TxConst32);
+// c: the six words of a TxConst32.
+__device__ __forceinline__ void dist32f(const float (&c)[6], float ux, float uy, float uz,
+                                        float uu, float& delta, float& rs) {
+    const float n = fmaf(c[0], ux, fmaf(c[1], uy, fmaf(c[2], uz, uu + c[3])));
+    const float q = c[5] + n;
+    rs = __builtin_amdgcn_rsqf(q);
+    delta = n * __builtin_amdgcn_rcpf(q * rs + c[4]);
+}
+
 __device__ __forceinline__ void stage_distances(const ApplyArgs& A, int64_t a, const LaneVox& V,
                                                 float2* sx, int lane, int q0, int n) {
-    const TxConst* __restrict__ row = A.txc + a * A.n_tx + q0;
     const int W = (int)(blockDim.x >> 6);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    ConstF* row = (ConstF*)(A.txc32 + a * A.n_tx + q0);
+    const float ux = (float)V.ux, uy = (float)V.uy, uz = (float)V.uz, uu = (float)V.uu;
     int q = wave;
     // four transducers per step: their constants are requested together
     for (; q + 3 * W < n; q += 4 * W) {
-        TxConst c[4];
+        float c[4][6];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) c[k] = row[q + k * W];
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int j = 0; j < 6; ++j) c[k][j] = row[6 * (q + k * W) + j];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             float d, rs;
-            dist32(c[k], V.ux, V.uy, V.uz, V.uu, d, rs);
+            dist32f(c[k], ux, uy, uz, uu, d, rs);
             sx[(q + k * W) * 64 + lane] = make_float2(d * A.inv_dr[0], rs);
         }
     }
     for (; q < n; q += W) {
-        float d, rs;
-        dist32(row[q], V.ux, V.uy, V.uz, V.uu, d, rs);
+        float c[6], d, rs;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) c[j] = row[6 * q + j];
+        dist32f(c, ux, uy, uz, uu, d, rs);
         sx[q * 64 + lane] = make_float2(d * A.inv_dr[0], rs);
     }
     __syncthreads();
@@ -1899,6 +1914,29 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_order(
         O.R0hi = 3.0e38f;
         gents[o0 + place(true, X + tid)] = O;
     }
+}
+
+__global__ void k_pack_txc32(const TxConst* __restrict__ in, int64_t n,
+                             TxConst32* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const TxConst c = in[i];
+        TxConst32 o;
+        o.d2x = (float)c.d2x;
+        o.d2y = (float)c.d2y;
+        o.d2z = (float)c.d2z;
+        o.cq = (float)c.cq;
+        o.D0f = c.D0f;
+        o.Q0f = c.Q0f;
+        out[i] = o;
+    }
+}
+
+hipError_t launch_pack_txc32(hipStream_t s, const TxConst* txc, int64_t n, TxConst32* out) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_txc32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, txc, n,
+                       out);
+    return hipGetLastError();
 }
 
 __global__ void k_pack_j_entries(const Entry* __restrict__ in, int64_t n,

@@ -146,21 +146,38 @@ def solve_case(small):
     return w, Jt, ctx, d, sig, minv
 
 
+# Relative accuracy of the FP32 coverage pass's diag(J^T J) on the small
+# ring: the table-oracle comparison above measures ~1.2e-7 norm-wise.
+DIAG_FP32 = 3e-7
+
+
 def test_pcgls_fp64_tracks_oracle_pcgls(solve_case):
     """FP64 operators and vectors; the diagonal comes from the FP32 coverage
-    pass, the oracle's from its dense table-mode matrix."""
+    pass, the oracle's from its dense table-mode matrix.  Twenty iterations
+    are far from convergence, where the iterate amplifies a change of the
+    Jacobi diagonal several hundred times: the bar is 1e-5 plus what the
+    oracle's own PCGLS moves when its diagonal is perturbed at the FP32
+    pass's accuracy (random relative perturbations of size DIAG_FP32, the
+    largest of four draws); likewise for the final misfit."""
     w, Jt, ctx, d, sig, minv = solve_case
     f = _fftt()
     x = dev(np.zeros(w.n), torch.float64)
     rep = ctx.solve(dev(d, torch.float64), x, method=0, prec=f.FP64, alpha=ALPHA,
                     noise_sigma=sig, max_iter=20, precond=True)
-    xr, hist = solvers.pcgls(lambda v: Jt @ v, lambda v: Jt.T @ v, d, sig, ALPHA, minv, 20)
+    A, At = (lambda v: Jt @ v), (lambda v: Jt.T @ v)
+    xr, hist = solvers.pcgls(A, At, d, sig, ALPHA, minv, 20)
+    dg = (Jt ** 2).sum(axis=0) / sig ** 2
+    dx = dm = 0.0
+    for k in range(4):
+        z = np.random.default_rng(100 + k).standard_normal(dg.size)
+        xk, hk = solvers.pcgls(A, At, d, sig, ALPHA, 1.0 / (dg * (1 + DIAG_FP32 * z) + ALPHA), 20)
+        dx, dm = max(dx, rel(xk, xr)), max(dm, abs(hk[-1] / hist[-1] - 1))
     e = rel(host(x), xr)
-    say("PCGLS fp64 20 its rel err vs oracle %.2e, misfit %.6e vs %.6e" % (e, rep["misfit"],
-                                                                             hist[-1]))
+    say("PCGLS fp64 20 its rel err vs oracle %.2e (oracle's own spread %.2e), misfit %.6e vs "
+        "%.6e (spread %.2e)" % (e, dx, rep["misfit"], hist[-1], dm))
     assert rep["iters"] == 20
-    assert e < 1e-5
-    assert abs(rep["misfit"] / hist[-1] - 1) < 1e-6
+    assert e < 1e-5 + dx
+    assert abs(rep["misfit"] / hist[-1] - 1) < 1e-6 + dm
 
 
 def test_pcgls_converges_to_direct_solution(solve_case):
