@@ -658,6 +658,9 @@ def tv_leg(fftt, torch, iters=10, n_fd=8):
            "lbfgs_iterations": iters}
     for name, prec, dt in (("fp32", fftt.FP32, torch.float32), ("fp64", fftt.FP64, torch.float64)):
         d = d64.to(dt)
+        # one untimed objective and gradient (first-use buffers of this precision)
+        xw = torch.zeros(w.n, dtype=dt, device=dev, requires_grad=True)
+        misfit_tv(ctx, xw, d, sig, alpha, beta, dims, sp, prec).backward()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x, hist = invert_tv(ctx, d, sig, alpha, beta, dims, sp, iters=iters, prec=prec)
