@@ -1298,7 +1298,9 @@ __device__ __forceinline__ void for_each_block(const ApplyArgs& A, const EntT* e
 // shares its source.  (J, whose source factor carries the model value, keeps
 // whole steps: the larger code was slower there.)  The arithmetic of the
 // step is instantiated per case so that shared values are used in place (no
-// register copies).
+// register copies); an empty asm statement, distinct per case, ends each
+// case so that the compiler does not merge their arithmetic into one block
+// (which brings the copies back: up to 14 v_mov per step).
 template <int U, bool SCALE, class F>
 __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const float2* sx, int lane,
                                              int& prev, float& cd, float& cg, float factor,
@@ -1330,6 +1332,7 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
                     g[u] = cg;
                 }
                 body(d, g);
+                asm volatile("; source case 1");
             } else {
                 float hd, hg;
                 fetch(E.s[4], hd, hg);
@@ -1341,6 +1344,7 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
                     g[u + 4] = hg;
                 }
                 body(d, g);
+                asm volatile("; source case 2");
                 prev = E.s[4];
                 cd = hd;
                 cg = hg;
@@ -1354,6 +1358,7 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
                 fetch(E.s[u + 4], d[u + 4], g[u + 4]);
             }
             body(d, g);
+            asm volatile("; source case 3");
             prev = E.s[7];
             cd = d[7];
             cg = g[7];
@@ -1367,10 +1372,12 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
                 g[u] = cg;
             }
             body(d, g);
+            asm volatile("; source case 4");
         } else {
 #pragma unroll
             for (int u = 0; u < 8; ++u) fetch(E.s[u], d[u], g[u]);
             body(d, g);
+            asm volatile("; source case 5");
             prev = E.s[7];
             cd = d[7];
             cg = g[7];
@@ -1389,10 +1396,12 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
             g[u] = cg;
         }
         body(d, g);
+        asm volatile("; source case 6");
     } else {
 #pragma unroll
         for (int u = 0; u < U; ++u) fetch(E.s[u], d[u], g[u]);
         body(d, g);
+        asm volatile("; source case 7");
         prev = E.s[U - 1];
         cd = d[U - 1];
         cg = g[U - 1];
@@ -2273,7 +2282,7 @@ constexpr int psf_chunk() { return NB == 1 ? 64 : (NB == 2 ? 32 : (NB == 3 ? 16 
 // the distance from the transducers).  The grid is padded to whole rounds;
 // blocks past the last tile return at once.
 constexpr int kXcds = 8;
-constexpr int kXcdRun = 64;
+constexpr int kXcdRun = 128;
 
 __device__ __forceinline__ int64_t xcd_tile(int64_t b) {
     const int64_t x = b % kXcds, i = b / kXcds;
