@@ -264,11 +264,24 @@ fftt_status build_lists(fftt_ctx* c) {
                             c->d_L.as<double>(), M, c->g, r_cut, nullptr,
                             c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>()));
 
+    // per entry, the bands whose kernel can be nonzero in the tile (carried
+    // by the staged copies below)
+    DevBuf bmask;
+    FFTT_HIP(c, bmask.alloc((size_t)std::max<int64_t>(nnz, 1)));
+    {
+        double cuts[kMaxBands];
+        for (int b = 0; b < c->nb; ++b) cuts[b] = c->r_max[b] + 1e-7;
+        FFTT_HIP(c, launch_band_masks(s, c->d_tiles.as<int32_t>(), n_act, c->d_txc.as<TxConst>(),
+                                      n_tx, c->d_L.as<double>(), c->g, cuts, c->nb,
+                                      c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(),
+                                      bmask.as<uint8_t>()));
+    }
     // the staged J's eight-byte copy (with the same look-ahead padding)
     FFTT_HIP(c, c->d_ents8.alloc((size_t)(nnz + kEntryPad) * 2 * sizeof(uint32_t)));
     FFTT_HIP(c, hipMemsetAsync(c->d_ents8.as<uint32_t>() + 2 * nnz, 0,
                                kEntryPad * 2 * sizeof(uint32_t), s));
-    FFTT_HIP(c, launch_pack_j_entries(s, c->d_ents.as<Entry>(), nnz, c->d_ents8.as<uint32_t>()));
+    FFTT_HIP(c, launch_pack_j_entries(s, c->d_ents.as<Entry>(), bmask.as<uint8_t>(), nnz,
+                                      c->d_ents8.as<uint32_t>()));
 
     // run descriptors of 64-pair groups (for the deterministic J reduction)
     const int64_t chunk = 256;
@@ -331,9 +344,9 @@ fftt_status build_lists(fftt_ctx* c) {
         FFTT_HIP(c, c->d_ents3.alloc((size_t)(c->g_nnz + kEntryPad) * sizeof(Entry3)));
         FFTT_HIP(c, hipMemsetAsync(c->d_ents3.as<Entry3>() + c->g_nnz, 0,
                                    kEntryPad * sizeof(Entry3), s));
-        FFTT_HIP(c, launch_group_order(s, c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(), n_act,
-                                       (int)n_tx, c->d_gtptr.as<int64_t>(),
-                                       c->d_ents3.as<Entry3>()));
+        FFTT_HIP(c, launch_group_order(s, c->d_tptr.as<int64_t>(), c->d_ents.as<Entry>(),
+                                       bmask.as<uint8_t>(), n_act, (int)n_tx,
+                                       c->d_gtptr.as<int64_t>(), c->d_ents3.as<Entry3>()));
         // the host offsets must outlive the asynchronous copy
         FFTT_HIP(c, hipStreamSynchronize(s));
         c->jt_grouped = true;
@@ -341,7 +354,7 @@ fftt_status build_lists(fftt_ctx* c) {
         FFTT_HIP(c, c->d_ents3.alloc((size_t)(nnz + kEntryPad) * sizeof(Entry3)));
         FFTT_HIP(c, hipMemsetAsync(c->d_ents3.as<Entry3>() + nnz, 0, kEntryPad * sizeof(Entry3),
                                    s));
-        FFTT_HIP(c, launch_pack_jt_entries(s, c->d_ents.as<Entry>(), nnz,
+        FFTT_HIP(c, launch_pack_jt_entries(s, c->d_ents.as<Entry>(), bmask.as<uint8_t>(), nnz,
                                            c->d_ents3.as<Entry3>()));
     }
     c->lists_rcut = r_cut;
@@ -392,7 +405,9 @@ int op_table(const fftt_ctx* c, fftt_precision prec) {
 // staging is off, nothing fits, or a kernel pair spans two blocks (the
 // per-wavefront kernels run then).
 int staged_q(fftt_ctx* c, fftt_precision prec) {
-    if (!c->staged || prec == FFTT_FP64) return 0;
+    // the staged kernels read the entry copies, whose transducer fields hold
+    // indices below kCopyMaxTx
+    if (!c->staged || prec == FFTT_FP64 || c->n_tx >= kCopyMaxTx) return 0;
     const int fmt = op_table(c, prec);
     int q = 16;
     while (q < c->n_tx) q *= 2;

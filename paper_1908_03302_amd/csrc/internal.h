@@ -229,10 +229,24 @@ constexpr int kGroupMaxTx = 1024;
 hipError_t launch_pack_txc32(hipStream_t s, const TxConst* txc, int64_t n, TxConst32* out);
 // The staged J reads only sr and R0hi of an entry: out [n][2] words, the
 // same order as ents.
-hipError_t launch_pack_j_entries(hipStream_t s, const Entry* ents, int64_t n, uint32_t* out);
+hipError_t launch_pack_j_entries(hipStream_t s, const Entry* ents, const uint8_t* bmask,
+                                 int64_t n, uint32_t* out);
 hipError_t launch_group_order(hipStream_t s, const int64_t* tptr, const Entry* ents,
-                              int64_t n_act, int n_tx, const int64_t* gtptr, Entry3* gents);
-hipError_t launch_pack_jt_entries(hipStream_t s, const Entry* ents, int64_t n, Entry3* out);
+                              const uint8_t* bmask, int64_t n_act, int n_tx,
+                              const int64_t* gtptr, Entry3* gents);
+hipError_t launch_pack_jt_entries(hipStream_t s, const Entry* ents, const uint8_t* bmask,
+                                  int64_t n, Entry3* out);
+// In both copies the source | receiver word is s | r << 14 | bands << 28
+// (transducers below kCopyMaxTx); bands: bit b set when band b's kernel can
+// be nonzero somewhere in the tile (launch_band_masks).
+constexpr int kCopyMaxTx = 1 << 14;
+// Per entry, the bands whose truncation radius exceeds the culling lower
+// bound of the detour over the tile (r_cut[b] = R_max[b] + slack): bit b of
+// bmask[e]; the other bands' kernel is zero over the whole tile.
+hipError_t launch_band_masks(hipStream_t s, const int32_t* tiles, int64_t n_act,
+                             const TxConst* txc, int64_t n_tx, const double* L,
+                             const GridGeom& g, const double* r_cut, int nb,
+                             const int64_t* tptr, const Entry* ents, uint8_t* bmask);
 // J per-pair sum: S slices per 64-pair group (reduce_slices), FP64 scratch
 // red [nb][S][Mk], then the rows of every caller pair of a group.
 int reduce_slices(int64_t Mk, int n_cu);

@@ -1159,6 +1159,7 @@ struct StepEntries {
     int s[U];
     int r[U];
     float R0[U];
+    int m[U];   // the staged copies: bands whose kernel can be nonzero (else all)
 };
 
 // Transducer indices are returned relative to the staged block's first one.
@@ -1178,12 +1179,14 @@ __device__ __forceinline__ StepEntries<U> load_entries(const Entry* __restrict__
         E.s[u] = (int)(v[u].y & 0xffffu) - base;
         E.r[u] = (int)(v[u].y >> 16) - base;
         E.R0[u] = __uint_as_float(v[u].z);
+        E.m[u] = 0xf;
     }
     return E;
 }
 
 // The staged J's entries: (sr, R0hi) word pairs, eight bytes each (the pair
-// index is not needed there); StepEntries.p is left unset.
+// index is not needed there); StepEntries.p is left unset.  The copies' sr
+// word is s | r << 14 | bands << 28.
 template <int U>
 __device__ __forceinline__ StepEntries<U> load_entries(const uint32_t* __restrict__ ents8,
                                                        int64_t e, int base) {
@@ -1195,9 +1198,10 @@ __device__ __forceinline__ StepEntries<U> load_entries(const uint32_t* __restric
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         E.p[u] = 0;
-        E.s[u] = (int)(v[u].x & 0xffffu) - base;
-        E.r[u] = (int)(v[u].x >> 16) - base;
+        E.s[u] = (int)(v[u].x & 0x3fffu) - base;
+        E.r[u] = (int)((v[u].x >> 14) & 0x3fffu) - base;
         E.R0[u] = __uint_as_float(v[u].y);
+        E.m[u] = (int)(v[u].x >> 28);
     }
     return E;
 }
@@ -1215,9 +1219,10 @@ __device__ __forceinline__ StepEntries<U> load_entries(const Entry3* __restrict_
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         E.p[u] = (int)v[3 * u];
-        E.s[u] = (int)(v[3 * u + 1] & 0xffffu) - base;
-        E.r[u] = (int)(v[3 * u + 1] >> 16) - base;
+        E.s[u] = (int)(v[3 * u + 1] & 0x3fffu) - base;
+        E.r[u] = (int)((v[3 * u + 1] >> 14) & 0x3fffu) - base;
         E.R0[u] = __uint_as_float(v[3 * u + 2]);
+        E.m[u] = (int)(v[3 * u + 1] >> 28);
     }
     return E;
 }
@@ -1238,10 +1243,10 @@ __device__ __forceinline__ int source_at(const Entry* __restrict__ ents, int64_t
     return (int)(ents[e].sr & 0xffffu);
 }
 __device__ __forceinline__ int source_at(const uint32_t* __restrict__ ents8, int64_t e) {
-    return (int)(ents8[2 * e] & 0xffffu);
+    return (int)(ents8[2 * e] & 0x3fffu);
 }
 __device__ __forceinline__ int source_at(const Entry3* __restrict__ ents3, int64_t e) {
-    return (int)(ents3[e].sr & 0xffffu);
+    return (int)(ents3[e].sr & 0x3fffu);
 }
 template <class EntT>
 __device__ __forceinline__ int64_t first_source_at_least(const EntT* __restrict__ ents,
@@ -1464,8 +1469,17 @@ __device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, c
 #pragma unroll
         for (int u = 0; u < U; ++u)   // R / dR_0 = (delta_s + delta_r) / dR_0 + R0 / dR_0
             x0[u] = fmaf(E.R0[u], A.inv_dr[0], sd[u] + rd[u]);
+        // bands whose kernel is zero for every entry of the step are skipped
+        int bands = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) bands |= E.m[u];
+        if constexpr (NB > 1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) hw[u] = 0.0f;
+        }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
+            if (NB > 1 && !((bands >> b) & 1)) continue;
             float xb[U], h[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) xb[u] = b == 0 ? x0[u] : x0[u] * A.xr[b];
@@ -1474,7 +1488,7 @@ __device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, c
             for (int u = 0; u < U; ++u) {
                 if constexpr (MODE == 1) h[u] = fabsf(h[u]);
                 if constexpr (MODE == 2) h[u] *= h[u];
-                hw[u] = b == 0 ? h[u] * W.w[u][0] : fmaf(h[u], W.w[u][b], hw[u]);
+                hw[u] = NB == 1 ? h[u] * W.w[u][0] : fmaf(h[u], W.w[u][b], hw[u]);
             }
         }
 #pragma unroll
@@ -1552,15 +1566,22 @@ __device__ __forceinline__ void j32s_body(const ApplyArgs& A, const TabT* st, co
             x0[u] = fmaf(E.R0[u], A.inv_dr[0], sd[u] + rd[u]);
             t[u] = sg[u] * rg[u];
         }
+        // bands whose kernel is zero for every entry of the step: zero sums
+        int bands = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) bands |= E.m[u];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            float xb[U], v[U];
+            float sum = 0.0f;
+            if (NB == 1 || ((bands >> b) & 1)) {
+                float xb[U], v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) xb[u] = b == 0 ? x0[u] : x0[u] * A.xr[b];
-            lookup_n<U>(band_tab(st, b, A.ntab), xb, nm1, v);
+                for (int u = 0; u < U; ++u) xb[u] = b == 0 ? x0[u] : x0[u] * A.xr[b];
+                lookup_n<U>(band_tab(st, b, A.ntab), xb, nm1, v);
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] *= t[u];
-            const float sum = multi_sum<U>(v, lane);
+                for (int u = 0; u < U; ++u) v[u] *= t[u];
+                sum = multi_sum<U>(v, lane);
+            }
             if constexpr (U == 8) {
                 if ((lane & 7) == 0) part[b * A.nnz + e + sum8_value_of_lane(lane)] = sum;
             } else {
@@ -1808,6 +1829,11 @@ hipError_t launch_group_fill(hipStream_t s, const int64_t* tptr, const Entry* en
 // and the rest's are interleaved evenly (Bresenham) when the step map fits
 // in LDS, else the grouped steps come first.
 
+// Source | receiver word of the staged copies (transducers below kCopyMaxTx).
+__device__ __forceinline__ uint32_t copy_sr(uint32_t s, uint32_t r, uint32_t bands) {
+    return s | (r << 14) | (bands << 28);
+}
+
 constexpr int kGroupThreads = 256;
 constexpr int kGroupMaxSteps = 4096;
 
@@ -1817,8 +1843,9 @@ __device__ __forceinline__ int group_source(const int* deg, uint32_t sr) {
 }
 
 __global__ __launch_bounds__(kGroupThreads) void k_group_order(
-    const int64_t* __restrict__ tptr, const Entry* __restrict__ ents, int n_tx,
-    const int64_t* __restrict__ gtptr, Entry3* __restrict__ gents) {
+    const int64_t* __restrict__ tptr, const Entry* __restrict__ ents,
+    const uint8_t* __restrict__ bmask, int n_tx, const int64_t* __restrict__ gtptr,
+    Entry3* __restrict__ gents) {
     __shared__ int deg[kGroupMaxTx], cnt[kGroupMaxTx], gcnt[kGroupMaxTx];
     __shared__ int gstart[kGroupMaxTx], rstart[kGroupMaxTx], run[kGroupMaxTx];
     __shared__ int smap[kGroupMaxSteps];
@@ -1908,13 +1935,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_order(
             const int s = (int)(E.sr & 0xffffu), r = (int)(E.sr >> 16);
             Entry3 O;
             O.p = E.p;
-            O.sr = (uint32_t)q | ((uint32_t)(q == s ? r : s) << 16);
+            O.sr = copy_sr((uint32_t)q, (uint32_t)(q == s ? r : s), bmask[t0 + e]);
             O.R0hi = E.R0hi;
             gents[o0 + pos] = O;
         }
         __syncthreads();
     }
-    // padding: zero kernel value (the detour is far beyond any table), pair 0
+    // padding: zero kernel value (the detour is far beyond any table, no band
+    // flagged), pair 0, transducer 0 at both ends
     const int X = n - P;
     if (tid < nout - n) {
         Entry3 O;
@@ -1948,44 +1976,96 @@ hipError_t launch_pack_txc32(hipStream_t s, const TxConst* txc, int64_t n, TxCon
     return hipGetLastError();
 }
 
-__global__ void k_pack_j_entries(const Entry* __restrict__ in, int64_t n,
-                                 uint2* __restrict__ out) {
+__global__ void k_pack_j_entries(const Entry* __restrict__ in, const uint8_t* __restrict__ bm,
+                                 int64_t n, uint2* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = make_uint2(in[i].sr, __float_as_uint(in[i].R0hi));
+    if (i < n)
+        out[i] = make_uint2(copy_sr(in[i].sr & 0xffffu, in[i].sr >> 16, bm[i]),
+                            __float_as_uint(in[i].R0hi));
 }
 
-hipError_t launch_pack_j_entries(hipStream_t s, const Entry* ents, int64_t n, uint32_t* out) {
+hipError_t launch_pack_j_entries(hipStream_t s, const Entry* ents, const uint8_t* bmask,
+                                 int64_t n, uint32_t* out) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack_j_entries, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ents,
-                       n, reinterpret_cast<uint2*>(out));
+                       bmask, n, reinterpret_cast<uint2*>(out));
     return hipGetLastError();
 }
 
-__global__ void k_pack_jt_entries(const Entry* __restrict__ in, int64_t n,
-                                  Entry3* __restrict__ out) {
+// One workgroup per tile: the culling bound of each entry (as in k_cull)
+// against every band's cut radius.
+struct BandCuts {
+    double r[kMaxBands];
+};
+
+__global__ __launch_bounds__(256) void k_band_masks(const TxConst* __restrict__ txc,
+                                                    int64_t n_tx, const double* __restrict__ L,
+                                                    double hwx, double hwy, double hwz,
+                                                    BandCuts cut, int nb,
+                                                    const int64_t* __restrict__ tptr,
+                                                    const Entry* __restrict__ ents,
+                                                    uint8_t* __restrict__ bmask) {
+    const int64_t a = blockIdx.x;
+    const TxConst* row = txc + a * n_tx;
+    for (int64_t e = tptr[a] + threadIdx.x; e < tptr[a + 1]; e += blockDim.x) {
+        const Entry E = ents[e];
+        const TxConst A = row[E.sr & 0xffffu], B = row[E.sr >> 16];
+        const double R0 = (double)A.D0f + (double)B.D0f - L[E.p];
+        const double ia = 0.5 / (double)A.D0f, ib = 0.5 / (double)B.D0f;
+        const double gx = A.d2x * ia + B.d2x * ib;
+        const double gy = A.d2y * ia + B.d2y * ib;
+        const double gz = A.d2z * ia + B.d2z * ib;
+        const double lb = R0 - (fabs(gx) * hwx + fabs(gy) * hwy + fabs(gz) * hwz);
+        uint32_t m = 0;
+        for (int b = 0; b < nb; ++b) m |= (lb < cut.r[b] ? 1u : 0u) << b;
+        bmask[e] = (uint8_t)m;
+    }
+}
+
+hipError_t launch_band_masks(hipStream_t s, const int32_t* tiles, int64_t n_act,
+                             const TxConst* txc, int64_t n_tx, const double* L,
+                             const GridGeom& g, const double* r_cut, int nb,
+                             const int64_t* tptr, const Entry* ents, uint8_t* bmask) {
+    (void)tiles;
+    if (n_act == 0) return hipSuccess;
+    if (nb < 1 || nb > kMaxBands) return hipErrorInvalidValue;
+    BandCuts cut{};
+    for (int b = 0; b < nb; ++b) cut.r[b] = r_cut[b];
+    const double hwx = 0.5 * (kTile - 1) * g.spacing[0];
+    const double hwy = 0.5 * (kTile - 1) * g.spacing[1];
+    const double hwz = 0.5 * (kTile - 1) * g.spacing[2];
+    hipLaunchKernelGGL(k_band_masks, dim3((unsigned)n_act), dim3(256), 0, s, txc, n_tx, L, hwx,
+                       hwy, hwz, cut, nb, tptr, ents, bmask);
+    return hipGetLastError();
+}
+
+__global__ void k_pack_jt_entries(const Entry* __restrict__ in, const uint8_t* __restrict__ bm,
+                                  int64_t n, Entry3* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         Entry3 o;
         o.p = in[i].p;
-        o.sr = in[i].sr;
+        o.sr = copy_sr(in[i].sr & 0xffffu, in[i].sr >> 16, bm[i]);
         o.R0hi = in[i].R0hi;
         out[i] = o;
     }
 }
 
-hipError_t launch_pack_jt_entries(hipStream_t s, const Entry* ents, int64_t n, Entry3* out) {
+hipError_t launch_pack_jt_entries(hipStream_t s, const Entry* ents, const uint8_t* bmask,
+                                  int64_t n, Entry3* out) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack_jt_entries, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       ents, n, out);
+                       ents, bmask, n, out);
     return hipGetLastError();
 }
 
 hipError_t launch_group_order(hipStream_t s, const int64_t* tptr, const Entry* ents,
-                              int64_t n_act, int n_tx, const int64_t* gtptr, Entry3* gents) {
+                              const uint8_t* bmask, int64_t n_act, int n_tx,
+                              const int64_t* gtptr, Entry3* gents) {
     if (n_act == 0) return hipSuccess;
     if (n_tx > kGroupMaxTx) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_group_order, dim3((unsigned)n_act), dim3(kGroupThreads), 0, s, tptr,
-                       ents, n_tx, gtptr, gents);
+                       ents, bmask, n_tx, gtptr, gents);
     return hipGetLastError();
 }
 
