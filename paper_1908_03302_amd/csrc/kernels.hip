@@ -1227,6 +1227,10 @@ __device__ __forceinline__ StepEntries<U> load_entries(const Entry3* __restrict_
     return E;
 }
 
+// A float in the global address space (for pointers rebuilt from integers,
+// which would otherwise be generic and take flat instructions).
+typedef __attribute__((address_space(1))) float GlobalF;
+
 __device__ __forceinline__ int64_t uniform64(int64_t x) {
     const uint64_t u = (uint64_t)x;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
@@ -1294,26 +1298,25 @@ __device__ __forceinline__ void for_each_block(const ApplyArgs& A, const EntT* e
     }
 }
 
-// Source terms of a step: the scaled detour part and 1/R_xs times a per-lane
-// factor (J: the model value of the voxel, J^T: 1).  The last source read is
-// cached (prev, cd, cg); a step whose entries share one source needs one LDS
-// read at most (none when it is the cached one), any other step reads every
-// entry's source.  J^T takes a step of eight as two halves of four that are
-// handled so, and walks source-grouped lists on which almost every half
-// shares its source.  (J, whose source factor carries the model value, keeps
-// whole steps: the larger code was slower there.)  The arithmetic of the
-// step is instantiated per case so that shared values are used in place (no
-// register copies); an empty asm statement, distinct per case, ends each
-// case so that the compiler does not merge their arithmetic into one block
-// (which brings the copies back: up to 14 v_mov per step).
-template <int U, bool SCALE, class F>
+// Source terms of a J^T step: the scaled detour part and 1/R_xs.  The last
+// source read is cached (prev, cd, cg); a step whose entries share one source
+// needs one LDS read at most (none when it is the cached one), any other step
+// reads every entry's source.  A step of eight is taken as two halves of four
+// that are handled so: J^T walks source-grouped lists on which almost every
+// half shares its source.  The arithmetic of the step is instantiated per
+// case so that shared values are used in place (no register copies); an
+// empty asm statement, distinct per case, ends each case so that the
+// compiler does not merge their arithmetic into one block (which brings the
+// copies back: up to 14 v_mov per step).  body also receives, as a
+// compile-time constant, which entries share one source: bit 0 the first
+// half of the step, bit 1 the second half, bit 2 all of it.
+template <int U, class F>
 __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const float2* sx, int lane,
-                                             int& prev, float& cd, float& cg, float factor,
-                                             F&& body) {
+                                             int& prev, float& cd, float& cg, F&& body) {
     auto fetch = [&](int q, float& d, float& g) {
         const float2 v = sx[q * 64 + lane];
         d = v.x;
-        g = SCALE ? v.y * factor : v.y;
+        g = v.y;
     };
     auto refresh = [&](int q) {
         if (q != prev) {
@@ -1321,7 +1324,7 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
             prev = q;
         }
     };
-    if constexpr (U == 8 && !SCALE) {
+    if constexpr (U == 8) {
         bool lo = true, hi = true;
 #pragma unroll
         for (int u = 1; u < 4; ++u) lo = lo && (E.s[u] == E.s[0]);
@@ -1336,7 +1339,7 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
                     d[u] = cd;
                     g[u] = cg;
                 }
-                body(d, g);
+                body(d, g, std::integral_constant<int, 7>{});
                 asm volatile("; source case 1");
             } else {
                 float hd, hg;
@@ -1348,7 +1351,7 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
                     d[u + 4] = hd;
                     g[u + 4] = hg;
                 }
-                body(d, g);
+                body(d, g, std::integral_constant<int, 3>{});
                 asm volatile("; source case 2");
                 prev = E.s[4];
                 cd = hd;
@@ -1362,7 +1365,7 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
                 g[u] = cg;
                 fetch(E.s[u + 4], d[u + 4], g[u + 4]);
             }
-            body(d, g);
+            body(d, g, std::integral_constant<int, 1>{});
             asm volatile("; source case 3");
             prev = E.s[7];
             cd = d[7];
@@ -1376,12 +1379,12 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
                 d[u] = cd;
                 g[u] = cg;
             }
-            body(d, g);
+            body(d, g, std::integral_constant<int, 2>{});
             asm volatile("; source case 4");
         } else {
 #pragma unroll
             for (int u = 0; u < 8; ++u) fetch(E.s[u], d[u], g[u]);
-            body(d, g);
+            body(d, g, std::integral_constant<int, 0>{});
             asm volatile("; source case 5");
             prev = E.s[7];
             cd = d[7];
@@ -1400,12 +1403,12 @@ __device__ __forceinline__ void with_sources(const StepEntries<U>& E, const floa
             d[u] = cd;
             g[u] = cg;
         }
-        body(d, g);
+        body(d, g, std::integral_constant<int, 7>{});
         asm volatile("; source case 6");
     } else {
 #pragma unroll
         for (int u = 0; u < U; ++u) fetch(E.s[u], d[u], g[u]);
-        body(d, g);
+        body(d, g, std::integral_constant<int, 0>{});
         asm volatile("; source case 7");
         prev = E.s[U - 1];
         cd = d[U - 1];
@@ -1463,8 +1466,9 @@ __device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, c
         rd[u] = v.x;
         rg[u] = v.y;
     }
-    with_sources<U, false>(E, sx, lane, prev, cd, cg, 1.0f,
-                           [&](const float (&sd)[U], const float (&sg)[U]) {
+    with_sources<U>(E, sx, lane, prev, cd, cg,
+                    [&](const float (&sd)[U], const float (&sg)[U], auto share) {
+        constexpr int SH = decltype(share)::value;
         float x0[U], hw[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)   // R / dR_0 = (delta_s + delta_r) / dR_0 + R0 / dR_0
@@ -1491,10 +1495,28 @@ __device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, c
                 hw[u] = NB == 1 ? h[u] * W.w[u][0] : fmaf(h[u], W.w[u][b], hw[u]);
             }
         }
+        // sum_u hw_u / (R_xs R_xr): entries that share a source add
+        // sum_u hw_u / R_xr first and take 1/R_xs once
+        auto shared = [&](int u0, int u1) {
+            float t = hw[u0] * rg[u0];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const float g = sg[u] * rg[u];
-            acc = fmaf(hw[u], MODE == 2 ? g * g : g, acc);
+            for (int u = u0 + 1; u < u1; ++u) t = fmaf(hw[u], rg[u], t);
+            acc = fmaf(t, sg[u0], acc);
+        };
+        auto each = [&](int u0, int u1) {
+#pragma unroll
+            for (int u = u0; u < u1; ++u) {
+                const float g = sg[u] * rg[u];
+                acc = fmaf(hw[u], MODE == 2 ? g * g : g, acc);
+            }
+        };
+        if constexpr (MODE == 2) {
+            each(0, U);
+        } else if constexpr ((SH & 4) != 0) {
+            shared(0, U);
+        } else {
+            if constexpr ((SH & 1) != 0) shared(0, U / 2); else each(0, U / 2);
+            if constexpr ((SH & 2) != 0) shared(U / 2, U); else each(U / 2, U);
         }
     });
 }
@@ -1518,7 +1540,8 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_jt32s(ApplyArgs A) {
         float cd = 0.f, cg = 0.f;
         int prev = -1;
         int64_t e = e0;
-        for (; e + U <= e1; e += U) {
+        // a 32-bit step count keeps the loop test on the scalar unit
+        for (int n = (int)((e1 - e0) / U); n > 0; --n, e += U) {
             const StepEntries<U> E = load_entries<U>(el, e, q0);
             jt32s_body<NB, TabT, U, MODE>(A, st, sx, E, load_weights<NB, U>(A, w, E), nm1, lane,
                                           prev, cd, cg, acc);
@@ -1545,11 +1568,47 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_jt32s(ApplyArgs A) {
     if (inside) static_cast<float*>(A.out)[vidx] = act ? t : 0.f;
 }
 
+// Source terms of a J step: the scaled detour part and dc_j / R_xs.  J walks
+// the lists in pair order, in which a tile's entries of one source form runs
+// (about 13 entries on average for a 128-element ring): a step inside one run
+// reads its source once, any other step reads every entry's source.  Nothing
+// is kept from one step to the next (a cached source costs register copies
+// at every step; so did instantiating the arithmetic for each split point of
+// a step over two runs, which was slower overall).
+template <int U, class F>
+__device__ __forceinline__ void with_sources_j(const StepEntries<U>& E, const float2* sx,
+                                               int lane, float factor, F&& body) {
+    auto fetch = [&](int q, float& d, float& g) {
+        const float2 v = sx[q * 64 + lane];
+        d = v.x;
+        g = v.y * factor;
+    };
+    float d[U], g[U];
+    bool same = true;
+#pragma unroll
+    for (int u = 1; u < U; ++u) same = same && (E.s[u] == E.s[0]);
+    if (same) {
+        float a, ga;
+        fetch(E.s[0], a, ga);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            d[u] = a;
+            g[u] = ga;
+        }
+        body(d, g);
+        asm volatile("; J sources: one run");
+        return;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) fetch(E.s[u], d[u], g[u]);
+    body(d, g);
+    asm volatile("; J sources: per entry");
+}
+
 template <int NB, class TabT, int U>
 __device__ __forceinline__ void j32s_body(const ApplyArgs& A, const TabT* st, const float2* sx,
                                           const StepEntries<U>& E, float* __restrict__ part,
-                                          float xv, float nm1, int lane, int64_t e, int& prev,
-                                          float& cd, float& cg) {
+                                          float xv, float nm1, int lane, int64_t e) {
     float rd[U], rg[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1557,9 +1616,8 @@ __device__ __forceinline__ void j32s_body(const ApplyArgs& A, const TabT* st, co
         rd[u] = v.x;
         rg[u] = v.y;
     }
-    // source factor cached as dc_j / R_xs
-    with_sources<U, true>(E, sx, lane, prev, cd, cg, xv,
-                          [&](const float (&sd)[U], const float (&sg)[U]) {
+    // source factor dc_j / R_xs
+    with_sources_j<U>(E, sx, lane, xv, [&](const float (&sd)[U], const float (&sg)[U]) {
         float x0[U], t[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1582,10 +1640,15 @@ __device__ __forceinline__ void j32s_body(const ApplyArgs& A, const TabT* st, co
                 for (int u = 0; u < U; ++u) v[u] *= t[u];
                 sum = multi_sum<U>(v, lane);
             }
+            // uniform base, per-lane 32-bit offset (scalar-base stores; the
+            // base is passed through readfirstlane so that it is not folded
+            // into a per-lane pointer advanced by a vector add each step)
+            GlobalF* pe = reinterpret_cast<GlobalF*>(
+                uniform64(reinterpret_cast<int64_t>(part + (b * A.nnz + e))));
             if constexpr (U == 8) {
-                if ((lane & 7) == 0) part[b * A.nnz + e + sum8_value_of_lane(lane)] = sum;
+                if ((lane & 7) == 0) pe[sum8_value_of_lane(lane)] = sum;
             } else {
-                if (lane < U) part[b * A.nnz + e + lane] = sum;
+                if (lane < U) pe[lane] = sum;
             }
         }
     });
@@ -1608,15 +1671,14 @@ __global__ __launch_bounds__(1024, NB == 1 ? 8 : 4) void k_j32s(ApplyArgs A) {
     }
     const float nm1 = (float)(A.ntab - 1);
     for_each_block<U>(A, A.ents8, A.tptr, a, sx, lane, [&](int q0, int64_t e0, int64_t e1) {
-        float cd = 0.f, cg = 0.f;
-        int prev = -1;
         int64_t e = e0;
-        for (; e + U <= e1; e += U)
+        // a 32-bit step count keeps the loop test on the scalar unit
+        for (int n = (int)((e1 - e0) / U); n > 0; --n, e += U)
             j32s_body<NB, TabT, U>(A, st, sx, load_entries<U>(A.ents8, e, q0), part, xv, nm1,
-                                   lane, e, prev, cd, cg);
+                                   lane, e);
         for (; e < e1; ++e)
             j32s_body<NB, TabT, 1>(A, st, sx, load_entries<1>(A.ents8, e, q0), part, xv, nm1,
-                                   lane, e, prev, cd, cg);
+                                   lane, e);
     });
 }
 
