@@ -1466,6 +1466,13 @@ __device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, c
         rd[u] = v.x;
         rg[u] = v.y;
     }
+    // one band: the pair weight goes into the receiver factor as soon as it
+    // arrives (fewer live registers over the lookups than h w formed after)
+    constexpr bool WR = NB == 1 && MODE != 2;
+    if constexpr (WR) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) rg[u] *= W.w[u][0];
+    }
     with_sources<U>(E, sx, lane, prev, cd, cg,
                     [&](const float (&sd)[U], const float (&sg)[U], auto share) {
         constexpr int SH = decltype(share)::value;
@@ -1492,11 +1499,12 @@ __device__ __forceinline__ void jt32s_body(const ApplyArgs& A, const TabT* st, c
             for (int u = 0; u < U; ++u) {
                 if constexpr (MODE == 1) h[u] = fabsf(h[u]);
                 if constexpr (MODE == 2) h[u] *= h[u];
-                hw[u] = NB == 1 ? h[u] * W.w[u][0] : fmaf(h[u], W.w[u][b], hw[u]);
+                hw[u] = WR ? h[u] : (NB == 1 ? h[u] * W.w[u][0] : fmaf(h[u], W.w[u][b], hw[u]));
             }
         }
-        // sum_u hw_u / (R_xs R_xr): entries that share a source add
-        // sum_u hw_u / R_xr first and take 1/R_xs once
+        // sum_u hw_u / (R_xs R_xr) (one band: w_u already in the 1/R_xr
+        // factor): entries that share a source add sum_u hw_u / R_xr first
+        // and take 1/R_xs once
         auto shared = [&](int u0, int u1) {
             float t = hw[u0] * rg[u0];
 #pragma unroll
@@ -1741,10 +1749,6 @@ static hipError_t launch_staged_nb(hipStream_t s, int tabfmt, bool transpose, co
 }
 
 hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const ApplyArgs& a) {
-    // one-band J^T keeps the select on the same zero-topped node table
-    // (identical values): without it its eight-entry kernel exceeds the 64
-    // registers of two workgroups per CU
-    if (transpose && a.nb == 1 && tabfmt == STAB_NODE32Z) tabfmt = STAB_NODE32;
     switch (a.nb) {
         case 1: return launch_staged_nb<1>(s, tabfmt, transpose, a);
         case 2: return launch_staged_nb<2>(s, tabfmt, transpose, a);
@@ -1758,7 +1762,9 @@ hipError_t launch_apply_staged(hipStream_t s, int tabfmt, bool transpose, const 
 // (four entries per step) with per-pair weights from k_coverage_weights.
 template <int NB, int MODE>
 static hipError_t launch_coverage_nb(hipStream_t s, int tabfmt, const ApplyArgs& a) {
-    if (tabfmt == STAB_NODE32Z) tabfmt = STAB_NODE32;   // as J^T
+    // no zero-topped instantiation here: the select of the plain node
+    // format gives the same values on that table
+    if (tabfmt == STAB_NODE32Z) tabfmt = STAB_NODE32;
     switch (tabfmt) {
         case STAB_NODE32:
             return launch_staged(k_jt32s<NB, float, 4, MODE>, s, a, (size_t)NB * a.ntab * 4);
