@@ -639,9 +639,10 @@ def tv_leg(fftt, torch, iters=10, n_fd=8):
     the FP64 operator plus 5 ns noise, then the TV-regularised misfit of
     eq. leastSquare_misfit1 minimised by L-BFGS (strong Wolfe) through the
     autograd wrapper (backward = the J^T kernel), in FP32 and in FP64.
-    Reported: wall time, objective evaluations, objective decrease, and the
+    Reported: wall time, objective evaluations, objective decrease, the
     gradient against central differences along seeded directions on the
-    central 32x32x16 block."""
+    central 32x32x16 block, and (FP32) the objective and gradient against
+    the FP64 ones at the same point."""
     import numpy as np
     from paper_1908_03302_amd import inputs as I
     from paper_1908_03302_amd.autograd import invert_tv, misfit_tv
@@ -663,15 +664,29 @@ def tv_leg(fftt, torch, iters=10, n_fd=8):
         invert_tv(ctx, d, sig, alpha, beta, dims, sp, iters=2, prec=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, hist = invert_tv(ctx, d, sig, alpha, beta, dims, sp, iters=iters, prec=prec)
+        # the evaluation budget does not bind: both precisions take all
+        # `iters` iterations, however many trial points their line searches use
+        x, hist = invert_tv(ctx, d, sig, alpha, beta, dims, sp, iters=iters, prec=prec,
+                            max_eval=4 * iters)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         res[name] = {"s": wall, "evaluations": len(hist), "objective_first": hist[0],
                      "objective_last": hist[-1], "decrease": hist[-1] / hist[0]}
         # gradient check at the L-BFGS end point
         xg = x.clone().requires_grad_(True)
-        misfit_tv(ctx, xg, d, sig, alpha, beta, dims, sp, prec).backward()
+        fx = misfit_tv(ctx, xg, d, sig, alpha, beta, dims, sp, prec)
+        fx.backward()
         g = xg.grad.detach()
+        if prec != fftt.FP64:
+            # the same objective and gradient in FP64 at the same point: the
+            # FP32 path's own error (the FP32 central differences below are
+            # limited by the rounding of the FP32 objective)
+            x64 = x.detach().double().requires_grad_(True)
+            f64 = misfit_tv(ctx, x64, d64, sig, alpha, beta, dims, sp, fftt.FP64)
+            f64.backward()
+            g64 = x64.grad.detach()
+            res[name]["objective_rel_vs_fp64"] = abs(float(fx) - float(f64)) / abs(float(f64))
+            res[name]["gradient_rel_vs_fp64"] = float((g.double() - g64).norm() / g64.norm())
         nx, ny, nz = dims
         sub = np.zeros((nz, ny, nx), dtype=bool)
         sub[nz // 2 - 8:nz // 2 + 8, ny // 2 - 16:ny // 2 + 16, nx // 2 - 16:nx // 2 + 16] = True
@@ -692,7 +707,11 @@ def tv_leg(fftt, torch, iters=10, n_fd=8):
         res[name]["fd_directions"] = n_fd
         res[name]["fd_eps"] = eps
         log("bench: four-band TV + L-BFGS %s: %.2f s, %d evaluations, objective %.4g -> %.4g, "
-            "FD gradient worst %.2e" % (name, wall, len(hist), hist[0], hist[-1], worst))
+            "FD gradient worst %.2e%s" % (name, wall, len(hist), hist[0], hist[-1], worst,
+                                          "" if prec == fftt.FP64 else
+                                          ", objective / gradient vs FP64 at the end point "
+                                          "%.2e / %.2e" % (res[name]["objective_rel_vs_fp64"],
+                                                           res[name]["gradient_rel_vs_fp64"])))
     del ctx
     torch.cuda.empty_cache()
     return res

@@ -53,17 +53,19 @@ def misfit_tv(op, x, d_obs, sigma, alpha_tv, beta, dims, spacing, prec=fftt.FP32
 
 
 def invert_tv(op, d_obs, sigma, alpha_tv, beta, dims, spacing, iters=20, prec=fftt.FP32,
-              x0=None, history_size=10):
-    """Minimise misfit_tv with L-BFGS (strong Wolfe line search); returns
-    (x, list of objective values per outer iteration)."""
+              x0=None, history_size=10, max_eval=None):
+    """Minimise misfit_tv with L-BFGS (strong Wolfe line search): at most
+    `iters` iterations and `max_eval` objective evaluations (default 1.25
+    iters, the optimizer's own); returns (x, list of objective values per
+    evaluation)."""
     dt = torch.float64 if prec == fftt.FP64 else torch.float32
     n = int(dims[0] * dims[1] * dims[2])
     x = (torch.zeros(n, dtype=dt, device=d_obs.device) if x0 is None
          else x0.detach().clone().to(dt))
     x.requires_grad_(True)
-    opt = torch.optim.LBFGS([x], lr=1.0, max_iter=iters, history_size=history_size,
-                            line_search_fn="strong_wolfe", tolerance_grad=0.0,
-                            tolerance_change=0.0)
+    opt = torch.optim.LBFGS([x], lr=1.0, max_iter=iters, max_eval=max_eval,
+                            history_size=history_size, line_search_fn="strong_wolfe",
+                            tolerance_grad=0.0, tolerance_change=0.0)
     hist = []
 
     def closure():
