@@ -339,7 +339,9 @@ fftt_status fftt_psf(fftt_ctx *ctx, fftt_precision prec, const int64_t *voxels,
  *     1 = a workgroup owns a tile and its wavefronts split the tile's pairs.
  *   FFTT_TUNE_STAGED: 1 (default) = FP32/BF16 operators first evaluate the
  *     transducer distances of a tile into LDS (Q * 512 bytes plus the
- *     tables, see FFTT_TUNE_STAGED_BLOCK), 0 = never.
+ *     tables, see FFTT_TUNE_STAGED_BLOCK), 0 = never.  The staged kernels
+ *     take fewer than 16384 transducers (their entry copies hold 14-bit
+ *     transducer indices); with more, the per-wavefront kernels run.
  *   FFTT_TUNE_UNROLL_JT_STAGED / FFTT_TUNE_UNROLL_J_STAGED: unroll of those:
  *     1, 2, 4 or 8.
  *   FFTT_TUNE_STAGED_TABLE: table layout of the staged FP32 kernels:
