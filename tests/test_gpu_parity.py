@@ -305,6 +305,34 @@ def test_ring2d_sampled_rows_and_columns(ring2d):
     assert mbj < ELEM["BF16"] and mbt < ELEM["BF16"]
 
 
+def test_ring2d_fp64_sampled_rows_and_columns(ring2d):
+    """Full-size 128-element ring, FP64 path: sampled rows of J dc and
+    sampled columns of J^T dT against the oracle with the same linear table
+    (1e-11 norm-wise, 1e-10 of the largest element), and against quadrature
+    within the table's own interpolation error (the FP32 bar)."""
+    w, o, ctx = ring2d
+    f = _fftt()
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    rng = np.random.default_rng(19)
+    rows = np.sort(rng.choice(w.m, 16, replace=False))
+    x = w.model
+    y = host(ctx.apply_J(dev(x, f.FP64), prec=f.FP64))
+    y_tab, y_q = ot.rows(rows, x), o.rows(rows, x)
+    act = np.flatnonzero(w.mask)
+    cols = np.sort(rng.choice(act, 512, replace=False))
+    yt = I.random_vector(w.m, 20) * 1e-7
+    xg = host(ctx.apply_JT(dev(yt, f.FP64), prec=f.FP64))
+    x_tab, x_q = ot.cols(cols, yt), o.cols(cols, yt)
+    ej, et = rel(y[rows], y_tab), rel(xg[cols], x_tab)
+    mj, mt = emax(y[rows], y_tab), emax(xg[cols], x_tab)
+    qj, qt = rel(y[rows], y_q), rel(xg[cols], x_q)
+    say("ring2d FP64 sampled rows %.2e (max-elem %.2e) cols %.2e (max-elem %.2e) vs table; "
+        "%.2e / %.2e vs quadrature" % (ej, mj, et, mt, qj, qt))
+    assert ej < 1e-11 and et < 1e-11
+    assert mj < 1e-10 and mt < 1e-10
+    assert qj < 1e-5 and qt < 1e-5
+
+
 def test_ring2d_adjoint_fp32(ring2d):
     w, o, ctx = ring2d
     f = _fftt()
