@@ -377,6 +377,13 @@ def test_multiband_full_size_sampled_rows_and_columns():
     assert ej < 1e-5 and et < 1e-5
     assert ejq < ejtab + 1e-5 and etq < ettab + 1e-5
     assert mj < ELEM["FP32"] and mt < ELEM["FP32"]
+    # the FP64 path (per-wavefront kernels, four bands in one launch) against
+    # the same table oracle
+    y64 = host(ctx.apply_J(dev(x, f.FP64), prec=f.FP64)).reshape(4, w.m)
+    x64 = host(ctx.apply_JT(dev(dT, f.FP64), prec=f.FP64))
+    e64j, e64t = rel(y64[:, rows], yt_), rel(x64[cols], xt)
+    say("multiband FP64 vs table: rows %.2e cols %.2e" % (e64j, e64t))
+    assert e64j < 1e-11 and e64t < 1e-11
 
 
 # ------------------------------------------------------------ launch shapes
