@@ -454,6 +454,14 @@ def test_slices3d_sampled_rows_and_columns(slices3d):
             % (ej, mj, et, mt))
         assert ej < bar and et < bar
         assert mj < ebar and mt < ebar
+    # FP64 path (per-wavefront kernels over all 4096 transducers) against the
+    # oracle with the same linear table
+    ot = oracle.Oracle.from_workload(w, table_mode=True)
+    y64 = host(ctx.apply_J(dev(w.model, f.FP64), prec=f.FP64))
+    x64 = host(ctx.apply_JT(dev(yt, f.FP64), prec=f.FP64))
+    e64j, e64t = rel(y64[rows], ot.rows(rows, w.model)), rel(x64[cols], ot.cols(cols, yt))
+    say("slices3d FP64 vs table: rows %.2e cols %.2e" % (e64j, e64t))
+    assert e64j < 1e-11 and e64t < 1e-11
 
 
 # ------------------------------------------------------------ autotuner
