@@ -193,8 +193,8 @@ def main():
                     help="1: per-tile LDS-staged kernels (default), 0: per-wavefront kernels")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the operators are not sharded); "
-              "use --gpus 1", file=sys.stderr)
+        print("bench.py: the operators run on one GPU only (they are not sharded across "
+              "GPUs); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
